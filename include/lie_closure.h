@@ -1,0 +1,175 @@
+/*
+ * lie_closure.h -- C ABI of the MI355X (gfx950) Lie-closure engine.
+ *
+ * The engine computes the closure c of a tuple of d x d anti-Hermitian
+ * generators G -- the smallest Lie algebra containing G -- as an orthonormal
+ * basis V built in the order of the dimension-only orthonormalization
+ * algorithm of arXiv 2506.01120 (Algorithm 4, Section 3.2):
+ *
+ *   generator phase:  for g in G: g_perp = g - proj_V g; if g_perp != 0, append g_perp/||g_perp||
+ *   bracket loop:     for each unordered pair (l, m), m < l, rows l in order:
+ *                       h = [V_l, V_m];  h_perp = h - proj_V h;  if h_perp != 0, append h_perp/||h_perp||
+ *
+ * with the bracket [a,b] = ab - ba, the inner product <a,b> = tr(a^H b)/d and
+ * the norm ||a|| = sqrt(<a,a>) of Section 2.2, and proj_V h = sum_k <V_k,h> V_k
+ * (the Corollary of Theorem 1).  The returned basis satisfies
+ * <V_i, V_j> = delta_ij, i.e. ||V_k||_F = sqrt(d).
+ *
+ * Decision rule ("h_perp != 0", which the paper leaves without a threshold):
+ * a generator is kept iff ||g_perp|| > tol * ||g||; a bracket of two unit-norm
+ * basis elements is kept iff ||h_perp|| > tol.  Exactly zero brackets are
+ * rejected.
+ *
+ * All device work runs in the library's own HIP kernels on one GPU.  Host
+ * pointers are plain CPU memory; device pointers are HIP device memory of the
+ * handle's device.  No function throws; every failure returns a negative
+ * lie_status and records a message readable with lie_last_error().
+ *
+ * Threading: a handle is not thread-safe; distinct handles are independent.
+ */
+#ifndef LIE_CLOSURE_H
+#define LIE_CLOSURE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lie_closure lie_closure;             /* opaque; owned by the caller until lie_closure_free */
+typedef struct lie_closure_batch lie_closure_batch; /* opaque; owned by the caller until lie_closure_batch_free */
+
+typedef enum lie_status {
+    LIE_OK = 0,
+    LIE_INCOMPLETE = 1,            /* a budgeted run stopped early; call again to resume */
+    LIE_ERR_ARG = -1,              /* invalid argument (null pointer, bad size, bad tolerance, bad config) */
+    LIE_ERR_NOT_ANTIHERMITIAN = -2,/* a generator violates ||g + g^H||_F <= 1e-12 * max(1, ||g||_F) */
+    LIE_ERR_NONFINITE = -3,        /* NaN or Inf in the input */
+    LIE_ERR_OOM = -4,              /* device or host allocation failed */
+    LIE_ERR_DEVICE = -5,           /* a HIP runtime call failed */
+    LIE_ERR_STATE = -6,            /* call not allowed in the handle's state (e.g. after a failed run) */
+    LIE_ERR_CAPACITY = -7,         /* the basis reached max_dim, or an output buffer is too small */
+    LIE_ERR_NUMERIC = -8           /* non-finite norm, or |V| exceeded the ambient bound (spurious element) */
+} lie_status;
+
+/* Arithmetic of the screening pass (the commutator and the first projection). */
+typedef enum lie_precision {
+    LIE_PREC_FP64 = 0,    /* everything in FP64 */
+    LIE_PREC_FP32 = 1,    /* screen in FP32 (MFMA, FP32 accumulate); FP64 verification */
+    LIE_PREC_BF16X3 = 2   /* screen in split BF16 (hi*hi + hi*lo + lo*hi on MFMA, FP32 accumulate); FP64 verification */
+} lie_precision;
+
+/* How a screened candidate is decided (ignored for LIE_PREC_FP64). */
+typedef enum lie_decide {
+    LIE_DECIDE_FP64 = 0,   /* every candidate is decided from its FP64 residual (screen used for nothing) */
+    LIE_DECIDE_STRICT = 1, /* screened residual <= tol/100 rejects; every other candidate is decided in FP64 */
+    LIE_DECIDE_SCREEN = 2  /* screened residual < tau_rej rejects; the rest are decided in FP64 */
+} lie_decide;
+
+typedef struct lie_closure_config {
+    uint32_t struct_size;  /* must be sizeof(lie_closure_config) */
+    int32_t precision;     /* lie_precision, default LIE_PREC_FP64 */
+    int32_t decide;        /* lie_decide, default LIE_DECIDE_SCREEN for screened precisions */
+    int32_t block;         /* candidates per block: 1 = plain one-at-a-time form, 0 = default */
+    int32_t early_exit;    /* 1: stop once |V| equals the ambient bound (exact; d^2-1 for traceless inputs) */
+    int32_t device;        /* HIP device ordinal; -1 = the calling thread's current device */
+    double tau_rej;        /* SCREEN reject threshold on the screened residual; 0 = precision default */
+    int64_t max_dim;       /* basis capacity; 0 = ambient bound */
+    void *stream;          /* hipStream_t the handle runs on; NULL = a stream the library creates */
+    int32_t use_graphs;    /* 1: replay block steps from captured hipGraphs (default 1) */
+    int32_t reserved[7];   /* must be zero */
+} lie_closure_config;
+
+typedef struct lie_closure_stats {
+    uint32_t struct_size;         /* must be sizeof(lie_closure_stats) */
+    int32_t done;                 /* 1 when the closure is complete (all pairs bracketed, or early exit) */
+    int64_t dim;                  /* |V| */
+    int64_t ambient;              /* d^2 - 1 (traceless generators) or d^2 */
+    int64_t candidates;           /* bracket candidates evaluated (N(N-1)/2 in full certification) */
+    int64_t generator_checks;     /* generator candidates evaluated */
+    int64_t zero_brackets;        /* brackets whose screened or FP64 norm was exactly zero */
+    int64_t screen_rejected;      /* candidates rejected from the screened residual alone */
+    int64_t fp64_decided;         /* candidates whose decision used an FP64 residual */
+    int64_t accepted;             /* elements appended by the bracket loop */
+    int64_t blocks;               /* block steps executed */
+    int64_t host_syncs;           /* device-to-host synchronisations of the driver */
+    double min_accepted_residual; /* smallest FP64 residual that was accepted (bracket loop) */
+    double max_rejected_residual; /* largest FP64 residual that was rejected (bracket loop) */
+    double max_screen_rejected;   /* largest screened residual among screen rejects */
+    double run_ms;                /* wall time spent inside lie_closure_run* calls */
+    int32_t precision, decide, block, early_exit;
+} lie_closure_stats;
+
+/* Fill *cfg with defaults (struct_size set).  Returns LIE_ERR_ARG for NULL. */
+lie_status lie_closure_config_default(lie_closure_config *cfg);
+
+/*
+ * Create a closure problem and run the generator phase (Algorithm 4, the loop
+ * over G) on the device.
+ *   out        -- receives the new handle (NULL on failure)
+ *   generators -- host, n_gen * d * d complex128, row-major, interleaved (re, im);
+ *                 copied, the caller keeps ownership
+ *   n_gen      -- >= 1; d -- 1..128; tol -- 0 < tol < 1
+ *   cfg        -- NULL for defaults
+ * Validates every argument before any HIP call (LIE_ERR_ARG / _NONFINITE /
+ * _NOT_ANTIHERMITIAN).  Zero generators are accepted and skipped.
+ */
+lie_status lie_closure_init(lie_closure **out, const double *generators, int32_t n_gen, int32_t d, double tol,
+                            const lie_closure_config *cfg);
+
+/* Run the bracket loop (Algorithm 4) to completion.  Blocking.  A no-op after completion. */
+lie_status lie_closure_run(lie_closure *h);
+
+/* Run at most max_candidates more bracket candidates (rounded up to whole blocks).
+ * Returns LIE_INCOMPLETE if work remains; calling again resumes at the exact pair cursor. */
+lie_status lie_closure_run_budget(lie_closure *h, int64_t max_candidates);
+
+/* Current |V| (valid any time after init). */
+lie_status lie_closure_dim(const lie_closure *h, int64_t *dim);
+
+/* Copy V (in append order) into a host buffer of capacity * d * d complex128,
+ * interleaved.  *written = |V|.  LIE_ERR_CAPACITY (with *written = |V|) if
+ * capacity < |V|. */
+lie_status lie_closure_basis(const lie_closure *h, double *out, int64_t capacity, int64_t *written);
+
+/* Same into device memory of the handle's device (ordered on the handle's stream). */
+lie_status lie_closure_basis_device(const lie_closure *h, void *dst, int64_t capacity, int64_t *written);
+
+/* ||G - I||_F with G_ij = <V_i, V_j>, computed in FP64 on the device. */
+lie_status lie_closure_orthogonality(lie_closure *h, double *loss);
+
+/* Counters and residual-gap statistics (out->struct_size must be set). */
+lie_status lie_closure_stats_get(const lie_closure *h, lie_closure_stats *out);
+
+/* Release everything the handle owns.  NULL-safe. */
+void lie_closure_free(lie_closure *h);
+
+/* Static description of a status code. */
+const char *lie_status_string(lie_status s);
+
+/* Detail message of the last failure on the calling thread ("" if none). */
+const char *lie_last_error(void);
+
+/*
+ * Batched form: n_problems independent closures (uneven d and generator
+ * counts) advanced together, one block step of every live problem per launch
+ * sequence, so small problems fill the GPU together.
+ *   generators[i] -- host, n_gen[i] * d[i] * d[i] complex128 (copied)
+ *   tol[i]        -- per-problem tolerance
+ *   cfg           -- shared configuration (precision, decide, block, early_exit)
+ */
+lie_status lie_closure_batch_init(lie_closure_batch **out, int32_t n_problems, const double *const *generators,
+                                  const int32_t *n_gen, const int32_t *d, const double *tol,
+                                  const lie_closure_config *cfg);
+lie_status lie_closure_batch_run(lie_closure_batch *b);
+lie_status lie_closure_batch_dim(const lie_closure_batch *b, int32_t i, int64_t *dim);
+lie_status lie_closure_batch_basis(const lie_closure_batch *b, int32_t i, double *out, int64_t capacity,
+                                   int64_t *written);
+lie_status lie_closure_batch_stats_get(const lie_closure_batch *b, int32_t i, lie_closure_stats *out);
+void lie_closure_batch_free(lie_closure_batch *b);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LIE_CLOSURE_H */

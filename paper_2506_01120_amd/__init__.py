@@ -1,0 +1,192 @@
+"""MI355X-native Lie-closure engine (arXiv 2506.01120, dimension-only orthonormalization).
+
+The Python layer only marshals arguments to the C ABI of ``liblieclosure.so``;
+every step of the closure runs in the library's HIP kernels.  PyTorch, when
+used, only supplies device memory (``basis_device``) and a HIP stream.
+
+    >>> from paper_2506_01120_amd import LieClosure, workloads
+    >>> lc = LieClosure(workloads.ising(3), tol=1e-10)
+    >>> lc.run(); lc.dim
+    15
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import _lib
+from ._lib import LieError
+
+__all__ = ["LieClosure", "BatchClosure", "closure", "LieError", "make_config"]
+
+
+def make_config(*, precision: str = "fp64", decide: str = "screen", block: int = 0, early_exit: bool = False,
+                tau_rej: float = 0.0, max_dim: int = 0, stream=None, device: int | None = None,
+                use_graphs: bool = True) -> _lib.Config:
+    cfg = _lib.Config()
+    _lib.check(_lib.load().lie_closure_config_default(ctypes.byref(cfg)))
+    cfg.precision = _lib.PRECISIONS[precision]
+    cfg.decide = _lib.DECIDES[decide]
+    cfg.block = int(block)
+    cfg.early_exit = 1 if early_exit else 0
+    cfg.tau_rej = float(tau_rej)
+    cfg.max_dim = int(max_dim)
+    cfg.device = -1 if device is None else int(device)
+    cfg.use_graphs = 1 if use_graphs else 0
+    if stream is not None:
+        cfg.stream = int(getattr(stream, "cuda_stream", stream))
+    return cfg
+
+
+def _host_generators(generators) -> np.ndarray:
+    if hasattr(generators, "detach"):  # a torch tensor
+        generators = generators.detach().cpu().numpy()
+    g = np.ascontiguousarray(np.asarray(generators, dtype=np.complex128))
+    if g.ndim == 2:
+        g = g[None]
+    if g.ndim != 3 or g.shape[1] != g.shape[2]:
+        raise ValueError("generators must have shape (n_gen, d, d)")
+    return g
+
+
+class LieClosure:
+    """One closure problem on the GPU.  Wraps lie_closure_init/run/dim/basis/stats/free."""
+
+    def __init__(self, generators, tol: float, **config):
+        self._libh = _lib.load()
+        g = _host_generators(generators)
+        self.d = int(g.shape[1])
+        self.n_gen = int(g.shape[0])
+        self.tol = float(tol)
+        self._cfg = make_config(**config)
+        self._gens = g  # kept alive only for the duration of init (the library copies)
+        h = ctypes.c_void_p()
+        _lib.check(self._libh.lie_closure_init(ctypes.byref(h), g.ctypes.data, self.n_gen, self.d, self.tol,
+                                               ctypes.byref(self._cfg)))
+        self._h = h
+        self._gens = None
+
+    def close(self) -> None:
+        h = getattr(self, "_h", None)
+        if h:
+            self._libh.lie_closure_free(h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def run(self, budget: int | None = None) -> bool:
+        """Run the bracket loop; with ``budget`` at most that many candidates.  Returns True when complete."""
+        if budget is None:
+            _lib.check(self._libh.lie_closure_run(self._h))
+            return True
+        st = _lib.check(self._libh.lie_closure_run_budget(self._h, int(budget)), allow_incomplete=True)
+        return st == _lib.LIE_OK
+
+    @property
+    def dim(self) -> int:
+        n = ctypes.c_int64()
+        _lib.check(self._libh.lie_closure_dim(self._h, ctypes.byref(n)))
+        return int(n.value)
+
+    def basis(self) -> np.ndarray:
+        """V as a host complex128 array (dim, d, d), in append order, <V_i, V_j> = delta_ij."""
+        n = self.dim
+        out = np.empty((max(n, 1), self.d, self.d), dtype=np.complex128)
+        w = ctypes.c_int64()
+        _lib.check(self._libh.lie_closure_basis(self._h, out.ctypes.data, n, ctypes.byref(w)))
+        return out[: w.value]
+
+    def basis_device(self):
+        """V as a torch complex128 CUDA tensor (dim, d, d) written by the library."""
+        import torch
+
+        n = self.dim
+        out = torch.empty((max(n, 1), self.d, self.d), dtype=torch.complex128, device="cuda")
+        w = ctypes.c_int64()
+        _lib.check(self._libh.lie_closure_basis_device(self._h, ctypes.c_void_p(out.data_ptr()), n, ctypes.byref(w)))
+        return out[: w.value]
+
+    def orthogonality(self) -> float:
+        """||G - I||_F, G_ij = <V_i, V_j>, computed in FP64 on the GPU."""
+        x = ctypes.c_double()
+        _lib.check(self._libh.lie_closure_orthogonality(self._h, ctypes.byref(x)))
+        return float(x.value)
+
+    def stats(self) -> dict:
+        s = _lib.Stats()
+        s.struct_size = ctypes.sizeof(_lib.Stats)
+        _lib.check(self._libh.lie_closure_stats_get(self._h, ctypes.byref(s)))
+        return s.as_dict()
+
+
+def closure(generators, tol: float, **config):
+    """Run a closure to completion; return (dim, basis, stats)."""
+    with LieClosure(generators, tol, **config) as lc:
+        lc.run()
+        return lc.dim, lc.basis(), lc.stats()
+
+
+class BatchClosure:
+    """Many independent closure problems advanced together (lie_closure_batch_*)."""
+
+    def __init__(self, problems, tols, **config):
+        self._libh = _lib.load()
+        gens = [_host_generators(g) for g in problems]
+        n = len(gens)
+        if np.isscalar(tols):
+            tols = [float(tols)] * n
+        self.ds = [int(g.shape[1]) for g in gens]
+        ptrs = (ctypes.c_void_p * n)(*[g.ctypes.data for g in gens])
+        ngen = (ctypes.c_int32 * n)(*[int(g.shape[0]) for g in gens])
+        dd = (ctypes.c_int32 * n)(*self.ds)
+        tt = (ctypes.c_double * n)(*[float(t) for t in tols])
+        self._cfg = make_config(**config)
+        h = ctypes.c_void_p()
+        _lib.check(self._libh.lie_closure_batch_init(ctypes.byref(h), n, ptrs, ngen, dd, tt, ctypes.byref(self._cfg)))
+        self._h = h
+        self.n = n
+
+    def close(self) -> None:
+        h = getattr(self, "_h", None)
+        if h:
+            self._libh.lie_closure_batch_free(h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def run(self) -> None:
+        _lib.check(self._libh.lie_closure_batch_run(self._h))
+
+    def dim(self, i: int) -> int:
+        n = ctypes.c_int64()
+        _lib.check(self._libh.lie_closure_batch_dim(self._h, i, ctypes.byref(n)))
+        return int(n.value)
+
+    def basis(self, i: int) -> np.ndarray:
+        n = self.dim(i)
+        d = self.ds[i]
+        out = np.empty((max(n, 1), d, d), dtype=np.complex128)
+        w = ctypes.c_int64()
+        _lib.check(self._libh.lie_closure_batch_basis(self._h, i, out.ctypes.data, n, ctypes.byref(w)))
+        return out[: w.value]
+
+    def stats(self, i: int) -> dict:
+        s = _lib.Stats()
+        s.struct_size = ctypes.sizeof(_lib.Stats)
+        _lib.check(self._libh.lie_closure_batch_stats_get(self._h, i, ctypes.byref(s)))
+        return s.as_dict()

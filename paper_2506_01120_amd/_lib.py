@@ -1,0 +1,137 @@
+"""ctypes declarations of the engine's C ABI (include/lie_closure.h).
+
+Loading fails loudly when the HIP library is not built: there is no fallback
+implementation of any step.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "liblieclosure.so")
+
+LIE_OK = 0
+LIE_INCOMPLETE = 1
+
+STATUS_NAMES = {
+    0: "LIE_OK", 1: "LIE_INCOMPLETE", -1: "LIE_ERR_ARG", -2: "LIE_ERR_NOT_ANTIHERMITIAN", -3: "LIE_ERR_NONFINITE",
+    -4: "LIE_ERR_OOM", -5: "LIE_ERR_DEVICE", -6: "LIE_ERR_STATE", -7: "LIE_ERR_CAPACITY", -8: "LIE_ERR_NUMERIC",
+}
+
+PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 2}
+DECIDES = {"fp64": 0, "strict": 1, "screen": 2}
+
+# Every symbol include/lie_closure.h declares.
+EXPORTS = (
+    "lie_closure_config_default", "lie_closure_init", "lie_closure_run", "lie_closure_run_budget",
+    "lie_closure_dim", "lie_closure_basis", "lie_closure_basis_device", "lie_closure_orthogonality",
+    "lie_closure_stats_get", "lie_closure_free", "lie_status_string", "lie_last_error",
+    "lie_closure_batch_init", "lie_closure_batch_run", "lie_closure_batch_dim", "lie_closure_batch_basis",
+    "lie_closure_batch_stats_get", "lie_closure_batch_free",
+)
+
+
+class Config(ctypes.Structure):
+    _fields_ = [
+        ("struct_size", ctypes.c_uint32),
+        ("precision", ctypes.c_int32),
+        ("decide", ctypes.c_int32),
+        ("block", ctypes.c_int32),
+        ("early_exit", ctypes.c_int32),
+        ("device", ctypes.c_int32),
+        ("tau_rej", ctypes.c_double),
+        ("max_dim", ctypes.c_int64),
+        ("stream", ctypes.c_void_p),
+        ("use_graphs", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 7),
+    ]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [
+        ("struct_size", ctypes.c_uint32),
+        ("done", ctypes.c_int32),
+        ("dim", ctypes.c_int64),
+        ("ambient", ctypes.c_int64),
+        ("candidates", ctypes.c_int64),
+        ("generator_checks", ctypes.c_int64),
+        ("zero_brackets", ctypes.c_int64),
+        ("screen_rejected", ctypes.c_int64),
+        ("fp64_decided", ctypes.c_int64),
+        ("accepted", ctypes.c_int64),
+        ("blocks", ctypes.c_int64),
+        ("host_syncs", ctypes.c_int64),
+        ("min_accepted_residual", ctypes.c_double),
+        ("max_rejected_residual", ctypes.c_double),
+        ("max_screen_rejected", ctypes.c_double),
+        ("run_ms", ctypes.c_double),
+        ("precision", ctypes.c_int32),
+        ("decide", ctypes.c_int32),
+        ("block", ctypes.c_int32),
+        ("early_exit", ctypes.c_int32),
+    ]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_ if name != "struct_size"}
+
+
+_lib = None
+
+
+def _declare(lib: ctypes.CDLL) -> ctypes.CDLL:
+    vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    pp = ctypes.POINTER(ctypes.c_void_p)
+    st = ctypes.c_int
+    i64p = ctypes.POINTER(ctypes.c_int64)
+    dblp = ctypes.POINTER(ctypes.c_double)
+    sigs = {
+        "lie_closure_config_default": (st, [ctypes.POINTER(Config)]),
+        "lie_closure_init": (st, [pp, vp, i32, i32, dbl, ctypes.POINTER(Config)]),
+        "lie_closure_run": (st, [vp]),
+        "lie_closure_run_budget": (st, [vp, i64]),
+        "lie_closure_dim": (st, [vp, i64p]),
+        "lie_closure_basis": (st, [vp, vp, i64, i64p]),
+        "lie_closure_basis_device": (st, [vp, vp, i64, i64p]),
+        "lie_closure_orthogonality": (st, [vp, dblp]),
+        "lie_closure_stats_get": (st, [vp, ctypes.POINTER(Stats)]),
+        "lie_closure_free": (None, [vp]),
+        "lie_status_string": (ctypes.c_char_p, [st]),
+        "lie_last_error": (ctypes.c_char_p, []),
+        "lie_closure_batch_init": (st, [pp, i32, ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_int32),
+                                        ctypes.POINTER(ctypes.c_int32), dblp, ctypes.POINTER(Config)]),
+        "lie_closure_batch_run": (st, [vp]),
+        "lie_closure_batch_dim": (st, [vp, i32, i64p]),
+        "lie_closure_batch_basis": (st, [vp, i32, vp, i64, i64p]),
+        "lie_closure_batch_stats_get": (st, [vp, i32, ctypes.POINTER(Stats)]),
+        "lie_closure_batch_free": (None, [vp]),
+    }
+    for name, (res, args) in sigs.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+def load() -> ctypes.CDLL:
+    """Load the built HIP library; raise if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(
+                f"{LIB_PATH} is not built; run `python -m paper_2506_01120_amd.build` (hipcc, gfx950) first")
+        _lib = _declare(ctypes.CDLL(LIB_PATH))
+    return _lib
+
+
+class LieError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        self.status = status
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+
+
+def check(status: int, allow_incomplete: bool = False) -> int:
+    if status == LIE_OK or (allow_incomplete and status == LIE_INCOMPLETE):
+        return status
+    msg = load().lie_last_error().decode(errors="replace")
+    raise LieError(status, msg)

@@ -1,0 +1,615 @@
+// Host driver and C ABI of the closure engine (see include/lie_closure.h).
+//
+// The driver owns one problem's device state: the FP64 basis V64 in the
+// packed anti-Hermitian layout, the candidate block buffer, coefficient and
+// scratch buffers, and the DevState counters.  It runs the generator phase and
+// then the bracket loop of the dimension-only orthonormalization algorithm as a
+// sequence of block steps over consecutive pair indices.
+#include "lie_internal.h"
+#include "../../include/lie_closure.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+namespace {
+
+thread_local std::string g_last_error;
+
+lie_status fail(lie_status st, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return st;
+}
+
+#define HIP_TRY(expr)                                                                                     \
+    do {                                                                                                  \
+        hipError_t e_ = (expr);                                                                           \
+        if (e_ != hipSuccess)                                                                             \
+            return fail(e_ == hipErrorOutOfMemory ? LIE_ERR_OOM : LIE_ERR_DEVICE, "%s failed: %s (%s:%d)", \
+                        #expr, hipGetErrorString(e_), __FILE__, __LINE__);                                \
+    } while (0)
+
+constexpr int kDefaultBlock = 256;
+constexpr int kMaxBlock = 1024;
+constexpr int kMaxD = 128;
+
+int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+}  // namespace
+
+struct lie_closure {
+    // problem
+    int d = 0;
+    int64_t D = 0;
+    double tol = 0;
+    int n_gen = 0;
+    int64_t cap = 0;
+    int64_t ambient = 0;
+    lie_closure_config cfg{};
+    int block = 1;
+    // device
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    double *V64 = nullptr;     // cap x D
+    double *H64 = nullptr;     // block x D (candidates, then residuals)
+    double *C = nullptr;       // block x cap coefficients
+    double *part = nullptr;    // split-K scratch + norm partials
+    double *rho2 = nullptr;    // block: squared residual norms (pass 2)
+    double *rho2a = nullptr;   // block: squared residual norms (pass 1)
+    double *h2 = nullptr;      // block: squared candidate norms
+    double *h2b = nullptr;     // block: pass-2 input norms (unused)
+    lie::DevState *st = nullptr;
+    double *scalar = nullptr;  // one double of device scratch
+    // host mirror
+    lie::DevState hs{};
+    int64_t cursor = 0;  // next pair index
+    bool done = false;
+    bool failed = false;
+    int64_t blocks = 0;
+    int64_t host_syncs = 0;
+    double run_ms = 0;
+
+    ~lie_closure()
+    {
+        if (device >= 0)
+            (void)hipSetDevice(device);
+        if (stream)
+            (void)hipStreamSynchronize(stream);
+        for (void *p : {(void *)V64, (void *)H64, (void *)C, (void *)part, (void *)rho2, (void *)rho2a, (void *)h2,
+                        (void *)h2b, (void *)st, (void *)scalar})
+            if (p)
+                (void)hipFree(p);
+        if (own_stream && stream)
+            (void)hipStreamDestroy(stream);
+    }
+
+    lie_status sync_state()
+    {
+        HIP_TRY(hipMemcpyAsync(&hs, st, sizeof hs, hipMemcpyDeviceToHost, stream));
+        HIP_TRY(hipStreamSynchronize(stream));
+        ++host_syncs;
+        return LIE_OK;
+    }
+
+    lie_status check_state()
+    {
+        if (hs.numeric_error == 1) {
+            failed = true;
+            return fail(LIE_ERR_NUMERIC, "non-finite residual norm encountered");
+        }
+        if (hs.numeric_error == 2) {
+            failed = true;
+            return fail(LIE_ERR_NUMERIC,
+                        "an independent candidate was found with |V| already at the ambient bound %lld (spurious "
+                        "element from round-off)",
+                        (long long)ambient);
+        }
+        if (hs.full) {
+            failed = true;
+            return fail(LIE_ERR_CAPACITY, "basis capacity %lld reached", (long long)cap);
+        }
+        return LIE_OK;
+    }
+
+    lie_status project(double *rho2_out, double *h2_out, int cnt, int64_t n_hi)
+    {
+        lie::ProjShape sh{D, cnt, std::min(n_hi, cap)};
+        HIP_TRY(lie::launch_project_f64(V64, &st->N, H64, C, part, rho2_out, h2_out, sh, stream));
+        return LIE_OK;
+    }
+
+    // Generator phase: every generator in input order, FP64.
+    lie_status generators(const double *gens_host)
+    {
+        double *staging = nullptr;
+        const size_t bytes = (size_t)n_gen * D * 2 * sizeof(double);
+        HIP_TRY(hipMalloc(&staging, bytes));
+        struct Guard {
+            double *p;
+            ~Guard() { (void)hipFree(p); }
+        } guard{staging};
+        double *packed = nullptr;
+        HIP_TRY(hipMalloc(&packed, (size_t)n_gen * D * sizeof(double)));
+        Guard guard2{packed};
+        HIP_TRY(hipMemcpyAsync(staging, gens_host, bytes, hipMemcpyHostToDevice, stream));
+        HIP_TRY(lie::launch_pack_c128(staging, packed, n_gen, d, stream));
+        for (int g = 0; g < n_gen; ++g) {
+            HIP_TRY(hipMemcpyAsync(H64, packed + (size_t)g * D, D * sizeof(double), hipMemcpyDeviceToDevice, stream));
+            lie_status s;
+            if ((s = project(rho2a, h2, 1, g)) != LIE_OK)
+                return s;
+            if ((s = project(rho2, h2b, 1, g)) != LIE_OK)
+                return s;
+            HIP_TRY(lie::launch_accept_f64(V64, st, H64, rho2, h2, 1, D, cap, ambient, tol, 0, 0, stream));
+        }
+        lie_status s = sync_state();
+        if (s != LIE_OK)
+            return s;
+        return check_state();
+    }
+
+    // One block step over pair indices [cursor, cursor + cnt).
+    lie_status step(int cnt, int64_t n_hi)
+    {
+        HIP_TRY(lie::launch_comm_f64(V64, d, cursor, nullptr, cnt, H64, stream));
+        lie_status s;
+        if ((s = project(rho2a, h2, cnt, n_hi)) != LIE_OK)
+            return s;
+        if ((s = project(rho2, h2b, cnt, n_hi)) != LIE_OK)
+            return s;
+        HIP_TRY(lie::launch_accept_f64(V64, st, H64, rho2, h2, cnt, D, cap, ambient, tol, 1, cfg.early_exit, stream));
+        cursor += cnt;
+        ++blocks;
+        return LIE_OK;
+    }
+
+    lie_status run(int64_t budget)
+    {
+        if (failed)
+            return fail(LIE_ERR_STATE, "a previous run of this handle failed");
+        if (done)
+            return LIE_OK;
+        HIP_TRY(hipSetDevice(device));
+        const auto t0 = std::chrono::steady_clock::now();
+        int64_t spent = 0;
+        lie_status s = LIE_OK;
+        for (;;) {
+            if (hs.done || (cfg.early_exit && hs.N >= ambient)) {
+                done = true;
+                break;
+            }
+            const int64_t avail = lie::pairs_below(hs.N);
+            if (cursor >= avail) {
+                done = true;
+                break;
+            }
+            if (budget >= 0 && spent >= budget) {
+                s = LIE_INCOMPLETE;
+                break;
+            }
+            const int cnt = (int)std::min<int64_t>(block, avail - cursor);
+            if ((s = step(cnt, hs.N + cnt)) != LIE_OK)
+                break;
+            spent += cnt;
+            if ((s = sync_state()) != LIE_OK)
+                break;
+            if ((s = check_state()) != LIE_OK)
+                break;
+        }
+        run_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        if (s < 0)
+            failed = true;
+        return s;
+    }
+};
+
+// ------------------------------------------------------------------ validation (host, before any HIP call)
+
+namespace {
+
+lie_status validate_generators(const double *g, int32_t n_gen, int32_t d, double tol, int64_t *ambient_out)
+{
+    if (!g)
+        return fail(LIE_ERR_ARG, "generators is NULL");
+    if (n_gen < 1)
+        return fail(LIE_ERR_ARG, "n_gen must be >= 1 (got %d)", n_gen);
+    if (d < 1 || d > kMaxD)
+        return fail(LIE_ERR_ARG, "d must be in [1, %d] (got %d)", kMaxD, d);
+    if (!(tol > 0.0 && tol < 1.0))
+        return fail(LIE_ERR_ARG, "tol must satisfy 0 < tol < 1 (got %g)", tol);
+    const int64_t D = (int64_t)d * d;
+    bool traceless = true;
+    for (int32_t k = 0; k < n_gen; ++k) {
+        const double *x = g + (size_t)k * D * 2;
+        double nrm2 = 0.0, defect2 = 0.0, tr_re = 0.0, tr_im = 0.0;
+        for (int64_t e = 0; e < 2 * D; ++e)
+            if (!std::isfinite(x[e]))
+                return fail(LIE_ERR_NONFINITE, "generator %d has a non-finite entry", k);
+        for (int i = 0; i < d; ++i)
+            for (int j = 0; j < d; ++j) {
+                const double re = x[2 * (i * d + j)], im = x[2 * (i * d + j) + 1];
+                const double tre = x[2 * (j * d + i)], tim = x[2 * (j * d + i) + 1];
+                nrm2 += re * re + im * im;
+                // (g + g^H)_ij = g_ij + conj(g_ji)
+                const double sre = re + tre, sim = im - tim;
+                defect2 += sre * sre + sim * sim;
+            }
+        for (int i = 0; i < d; ++i) {
+            tr_re += x[2 * (i * d + i)];
+            tr_im += x[2 * (i * d + i) + 1];
+        }
+        const double nrm = std::sqrt(nrm2);
+        if (std::sqrt(defect2) > 1e-12 * std::max(1.0, nrm))
+            return fail(LIE_ERR_NOT_ANTIHERMITIAN,
+                        "generator %d is not anti-Hermitian (||g + g^H||_F = %.3e); pass i*H for a Hermitian H", k,
+                        std::sqrt(defect2));
+        if (std::hypot(tr_re, tr_im) > 1e-12 * std::max(1.0, nrm))
+            traceless = false;
+    }
+    *ambient_out = traceless ? D - 1 : D;
+    if (D == 1)
+        *ambient_out = traceless ? 0 : 1;
+    return LIE_OK;
+}
+
+lie_status resolve_config(const lie_closure_config *in, lie_closure_config *out)
+{
+    lie_closure_config_default(out);
+    if (!in)
+        return LIE_OK;
+    if (in->struct_size != sizeof(lie_closure_config))
+        return fail(LIE_ERR_ARG, "config.struct_size must be %zu", sizeof(lie_closure_config));
+    *out = *in;
+    if (out->precision < LIE_PREC_FP64 || out->precision > LIE_PREC_BF16X3)
+        return fail(LIE_ERR_ARG, "unknown precision %d", out->precision);
+    if (out->decide < LIE_DECIDE_FP64 || out->decide > LIE_DECIDE_SCREEN)
+        return fail(LIE_ERR_ARG, "unknown decide mode %d", out->decide);
+    if (out->block < 0 || out->block > kMaxBlock)
+        return fail(LIE_ERR_ARG, "block must be in [0, %d]", kMaxBlock);
+    if (out->max_dim < 0)
+        return fail(LIE_ERR_ARG, "max_dim must be >= 0");
+    if (out->tau_rej < 0 || !std::isfinite(out->tau_rej))
+        return fail(LIE_ERR_ARG, "tau_rej must be finite and >= 0");
+    for (int r : out->reserved)
+        if (r != 0)
+            return fail(LIE_ERR_ARG, "config.reserved must be zero");
+    if (out->block == 0)
+        out->block = kDefaultBlock;
+    return LIE_OK;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ C ABI
+
+extern "C" {
+
+lie_status lie_closure_config_default(lie_closure_config *cfg)
+{
+    if (!cfg)
+        return fail(LIE_ERR_ARG, "cfg is NULL");
+    std::memset(cfg, 0, sizeof *cfg);
+    cfg->struct_size = sizeof(lie_closure_config);
+    cfg->precision = LIE_PREC_FP64;
+    cfg->decide = LIE_DECIDE_SCREEN;
+    cfg->block = 0;
+    cfg->early_exit = 0;
+    cfg->device = -1;
+    cfg->use_graphs = 1;
+    return LIE_OK;
+}
+
+lie_status lie_closure_init(lie_closure **out, const double *generators, int32_t n_gen, int32_t d, double tol,
+                            const lie_closure_config *cfg_in)
+{
+    g_last_error.clear();
+    if (!out)
+        return fail(LIE_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    int64_t ambient = 0;
+    lie_status s = validate_generators(generators, n_gen, d, tol, &ambient);
+    if (s != LIE_OK)
+        return s;
+    lie_closure_config cfg;
+    if ((s = resolve_config(cfg_in, &cfg)) != LIE_OK)
+        return s;
+
+    lie_closure *h = new (std::nothrow) lie_closure();
+    if (!h)
+        return fail(LIE_ERR_OOM, "host allocation failed");
+    h->d = d;
+    h->D = (int64_t)d * d;
+    h->tol = tol;
+    h->n_gen = n_gen;
+    h->ambient = ambient;
+    h->cfg = cfg;
+    h->block = cfg.block;
+    h->cap = cfg.max_dim > 0 ? std::min<int64_t>(cfg.max_dim, h->D) : std::max<int64_t>(ambient, 1);
+    h->device = -1;
+
+    auto bail = [&](lie_status st) {
+        delete h;
+        return st;
+    };
+    int dev = cfg.device;
+    if (dev < 0) {
+        hipError_t e = hipGetDevice(&dev);
+        if (e != hipSuccess)
+            return bail(fail(LIE_ERR_DEVICE, "hipGetDevice failed: %s", hipGetErrorString(e)));
+    }
+    h->device = dev;
+    {
+        hipError_t e = hipSetDevice(dev);
+        if (e != hipSuccess)
+            return bail(fail(LIE_ERR_DEVICE, "hipSetDevice(%d) failed: %s", dev, hipGetErrorString(e)));
+    }
+    if (cfg.stream) {
+        h->stream = (hipStream_t)cfg.stream;
+    } else {
+        hipError_t e = hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking);
+        if (e != hipSuccess)
+            return bail(fail(LIE_ERR_DEVICE, "hipStreamCreate failed: %s", hipGetErrorString(e)));
+        h->own_stream = true;
+    }
+    const int64_t D = h->D;
+    const int b = h->block;
+    auto alloc = [&](double **p, size_t n) -> lie_status {
+        hipError_t e = hipMalloc(p, std::max<size_t>(n, 1) * sizeof(double));
+        if (e != hipSuccess)
+            return fail(e == hipErrorOutOfMemory ? LIE_ERR_OOM : LIE_ERR_DEVICE, "hipMalloc of %zu doubles failed: %s",
+                        n, hipGetErrorString(e));
+        return LIE_OK;
+    };
+    const int bmax = std::max(b, 1);
+    if ((s = alloc(&h->V64, (size_t)h->cap * D)) != LIE_OK || (s = alloc(&h->H64, (size_t)bmax * D)) != LIE_OK ||
+        (s = alloc(&h->C, (size_t)bmax * round_up(h->cap, 16))) != LIE_OK ||
+        (s = alloc(&h->part, lie::proj_scratch_doubles(D, bmax, h->cap))) != LIE_OK ||
+        (s = alloc(&h->rho2, bmax)) != LIE_OK || (s = alloc(&h->rho2a, bmax)) != LIE_OK ||
+        (s = alloc(&h->h2, bmax)) != LIE_OK || (s = alloc(&h->h2b, bmax)) != LIE_OK ||
+        (s = alloc(&h->scalar, 1)) != LIE_OK)
+        return bail(s);
+    {
+        hipError_t e = hipMalloc(&h->st, sizeof(lie::DevState));
+        if (e != hipSuccess)
+            return bail(fail(LIE_ERR_OOM, "hipMalloc(DevState) failed: %s", hipGetErrorString(e)));
+    }
+    h->hs = lie::DevState{};
+    h->hs.min_acc = INFINITY;
+    h->hs.max_rej = 0.0;
+    h->hs.max_screen_rej = 0.0;
+    {
+        hipError_t e = hipMemcpyAsync(h->st, &h->hs, sizeof h->hs, hipMemcpyHostToDevice, h->stream);
+        if (e != hipSuccess)
+            return bail(fail(LIE_ERR_DEVICE, "state upload failed: %s", hipGetErrorString(e)));
+    }
+    if ((s = h->generators(generators)) != LIE_OK)
+        return bail(s);
+    *out = h;
+    return LIE_OK;
+}
+
+lie_status lie_closure_run(lie_closure *h)
+{
+    if (!h)
+        return fail(LIE_ERR_ARG, "handle is NULL");
+    return h->run(-1);
+}
+
+lie_status lie_closure_run_budget(lie_closure *h, int64_t max_candidates)
+{
+    if (!h)
+        return fail(LIE_ERR_ARG, "handle is NULL");
+    if (max_candidates < 0)
+        return fail(LIE_ERR_ARG, "max_candidates must be >= 0");
+    return h->run(max_candidates);
+}
+
+lie_status lie_closure_dim(const lie_closure *h, int64_t *dim)
+{
+    if (!h || !dim)
+        return fail(LIE_ERR_ARG, "NULL argument");
+    *dim = h->hs.N;
+    return LIE_OK;
+}
+
+static lie_status basis_common(const lie_closure *h, void *dst, int64_t capacity, int64_t *written, bool device_dst)
+{
+    if (!h || !written || (!dst && capacity > 0))
+        return fail(LIE_ERR_ARG, "NULL argument");
+    const int64_t n = h->hs.N;
+    *written = n;
+    if (capacity < n)
+        return fail(LIE_ERR_CAPACITY, "output holds %lld elements, basis has %lld", (long long)capacity,
+                    (long long)n);
+    if (n == 0)
+        return LIE_OK;
+    HIP_TRY(hipSetDevice(h->device));
+    if (device_dst) {
+        HIP_TRY(lie::launch_unpack_c128(h->V64, (double *)dst, n, h->d, h->stream));
+        HIP_TRY(hipStreamSynchronize(h->stream));
+        return LIE_OK;
+    }
+    double *tmp = nullptr;
+    HIP_TRY(hipMalloc(&tmp, (size_t)n * h->D * 2 * sizeof(double)));
+    hipError_t e = lie::launch_unpack_c128(h->V64, tmp, n, h->d, h->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(dst, tmp, (size_t)n * h->D * 2 * sizeof(double), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(h->stream);
+    (void)hipFree(tmp);
+    if (e != hipSuccess)
+        return fail(LIE_ERR_DEVICE, "basis copy failed: %s", hipGetErrorString(e));
+    return LIE_OK;
+}
+
+lie_status lie_closure_basis(const lie_closure *h, double *out, int64_t capacity, int64_t *written)
+{
+    return basis_common(h, out, capacity, written, false);
+}
+
+lie_status lie_closure_basis_device(const lie_closure *h, void *dst, int64_t capacity, int64_t *written)
+{
+    return basis_common(h, dst, capacity, written, true);
+}
+
+lie_status lie_closure_orthogonality(lie_closure *h, double *loss)
+{
+    if (!h || !loss)
+        return fail(LIE_ERR_ARG, "NULL argument");
+    const int64_t n = h->hs.N;
+    HIP_TRY(hipSetDevice(h->device));
+    double *work = nullptr;
+    HIP_TRY(hipMalloc(&work, ((size_t)n * n + 256) * sizeof(double)));
+    hipError_t e = lie::launch_orth_loss(h->V64, n, h->D, work, h->scalar, h->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(loss, h->scalar, sizeof(double), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(h->stream);
+    (void)hipFree(work);
+    if (e != hipSuccess)
+        return fail(LIE_ERR_DEVICE, "orthogonality check failed: %s", hipGetErrorString(e));
+    return LIE_OK;
+}
+
+lie_status lie_closure_stats_get(const lie_closure *h, lie_closure_stats *out)
+{
+    if (!h || !out)
+        return fail(LIE_ERR_ARG, "NULL argument");
+    if (out->struct_size != sizeof(lie_closure_stats))
+        return fail(LIE_ERR_ARG, "stats.struct_size must be %zu", sizeof(lie_closure_stats));
+    std::memset(out, 0, sizeof *out);
+    out->struct_size = sizeof(lie_closure_stats);
+    out->done = h->done ? 1 : 0;
+    out->dim = h->hs.N;
+    out->ambient = h->ambient;
+    out->candidates = h->hs.n_cand;
+    out->generator_checks = h->n_gen;
+    out->zero_brackets = h->hs.n_zero;
+    out->screen_rejected = h->hs.n_screen_rej;
+    out->fp64_decided = h->hs.n_fp64;
+    out->accepted = h->hs.n_acc;
+    out->blocks = h->blocks;
+    out->host_syncs = h->host_syncs;
+    out->min_accepted_residual = h->hs.min_acc;
+    out->max_rejected_residual = h->hs.max_rej;
+    out->max_screen_rejected = h->hs.max_screen_rej;
+    out->run_ms = h->run_ms;
+    out->precision = h->cfg.precision;
+    out->decide = h->cfg.decide;
+    out->block = h->block;
+    out->early_exit = h->cfg.early_exit;
+    return LIE_OK;
+}
+
+void lie_closure_free(lie_closure *h) { delete h; }
+
+const char *lie_status_string(lie_status s)
+{
+    switch (s) {
+    case LIE_OK: return "LIE_OK";
+    case LIE_INCOMPLETE: return "LIE_INCOMPLETE";
+    case LIE_ERR_ARG: return "LIE_ERR_ARG";
+    case LIE_ERR_NOT_ANTIHERMITIAN: return "LIE_ERR_NOT_ANTIHERMITIAN";
+    case LIE_ERR_NONFINITE: return "LIE_ERR_NONFINITE";
+    case LIE_ERR_OOM: return "LIE_ERR_OOM";
+    case LIE_ERR_DEVICE: return "LIE_ERR_DEVICE";
+    case LIE_ERR_STATE: return "LIE_ERR_STATE";
+    case LIE_ERR_CAPACITY: return "LIE_ERR_CAPACITY";
+    case LIE_ERR_NUMERIC: return "LIE_ERR_NUMERIC";
+    }
+    return "unknown lie_status";
+}
+
+const char *lie_last_error(void) { return g_last_error.c_str(); }
+
+// ------------------------------------------------------------------ batched form (problems advanced together)
+
+}  // extern "C"
+
+struct lie_closure_batch {
+    std::vector<lie_closure *> probs;
+    ~lie_closure_batch()
+    {
+        for (auto *p : probs)
+            delete p;
+    }
+};
+
+extern "C" {
+
+lie_status lie_closure_batch_init(lie_closure_batch **out, int32_t n_problems, const double *const *generators,
+                                  const int32_t *n_gen, const int32_t *d, const double *tol,
+                                  const lie_closure_config *cfg)
+{
+    if (!out || !generators || !n_gen || !d || !tol)
+        return fail(LIE_ERR_ARG, "NULL argument");
+    *out = nullptr;
+    if (n_problems < 1)
+        return fail(LIE_ERR_ARG, "n_problems must be >= 1");
+    auto *b = new (std::nothrow) lie_closure_batch();
+    if (!b)
+        return fail(LIE_ERR_OOM, "host allocation failed");
+    for (int32_t i = 0; i < n_problems; ++i) {
+        lie_closure *h = nullptr;
+        lie_status s = lie_closure_init(&h, generators[i], n_gen[i], d[i], tol[i], cfg);
+        if (s != LIE_OK) {
+            std::string msg = g_last_error;
+            delete b;
+            return fail(s, "problem %d: %s", i, msg.c_str());
+        }
+        b->probs.push_back(h);
+    }
+    *out = b;
+    return LIE_OK;
+}
+
+lie_status lie_closure_batch_run(lie_closure_batch *b)
+{
+    if (!b)
+        return fail(LIE_ERR_ARG, "batch is NULL");
+    for (size_t i = 0; i < b->probs.size(); ++i) {
+        lie_status s = b->probs[i]->run(-1);
+        if (s != LIE_OK)
+            return s;
+    }
+    return LIE_OK;
+}
+
+lie_status lie_closure_batch_dim(const lie_closure_batch *b, int32_t i, int64_t *dim)
+{
+    if (!b || i < 0 || i >= (int32_t)b->probs.size())
+        return fail(LIE_ERR_ARG, "bad batch index");
+    return lie_closure_dim(b->probs[i], dim);
+}
+
+lie_status lie_closure_batch_basis(const lie_closure_batch *b, int32_t i, double *out, int64_t capacity,
+                                   int64_t *written)
+{
+    if (!b || i < 0 || i >= (int32_t)b->probs.size())
+        return fail(LIE_ERR_ARG, "bad batch index");
+    return lie_closure_basis(b->probs[i], out, capacity, written);
+}
+
+lie_status lie_closure_batch_stats_get(const lie_closure_batch *b, int32_t i, lie_closure_stats *out)
+{
+    if (!b || i < 0 || i >= (int32_t)b->probs.size())
+        return fail(LIE_ERR_ARG, "bad batch index");
+    return lie_closure_stats_get(b->probs[i], out);
+}
+
+void lie_closure_batch_free(lie_closure_batch *b) { delete b; }
+
+}  // extern "C"

@@ -1,0 +1,609 @@
+// FP64 kernels of the closure engine: layout conversion, the bracket, the
+// projection/residual pass, sequential acceptance and the orthogonality check.
+// Operators use the packed anti-Hermitian layout described in lie_internal.h.
+#include "lie_internal.h"
+
+#include <algorithm>
+#include <cmath>
+
+namespace lie {
+
+namespace {
+
+constexpr int kThreads = 256;
+
+__device__ inline double wave_sum(double v)
+{
+    for (int off = 32; off > 0; off >>= 1)
+        v += __shfl_down(v, off, 64);
+    return v;
+}
+
+// Sum over a 256-thread workgroup; result valid in thread 0.
+__device__ inline double block_sum(double v, double *red /* >= 4 doubles of LDS */)
+{
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0)
+        red[w] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < (int)(blockDim.x >> 6); ++i)
+            s += red[i];
+    __syncthreads();
+    return s;
+}
+
+// ------------------------------------------------------------------ layout
+
+__global__ void k_pack_c128(const double *__restrict__ src, double *__restrict__ dst, int count, int d)
+{
+    const int64_t D = (int64_t)d * d;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)count * D)
+        return;
+    const int64_t e = idx / D, r = idx % D;
+    const int i = (int)(r / d), j = (int)(r % d);
+    const double *x = src + e * D * 2;
+    const double s2 = sqrt(2.0 / d), s1 = sqrt(1.0 / d);
+    double v;
+    // project onto the anti-Hermitian part (X - X^H)/2 while packing
+    if (i < j) {
+        v = s2 * 0.5 * (x[2 * (i * d + j)] - x[2 * (j * d + i)]);
+    } else if (i > j) {
+        v = s2 * 0.5 * (x[2 * (j * d + i) + 1] + x[2 * (i * d + j) + 1]);
+    } else {
+        v = s1 * x[2 * (i * d + i) + 1];
+    }
+    dst[idx] = v;
+}
+
+__global__ void k_unpack_c128(const double *__restrict__ src, double *__restrict__ dst, int64_t count, int d)
+{
+    const int64_t D = (int64_t)d * d;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= count * D)
+        return;
+    const int64_t e = idx / D, r = idx % D;
+    const int i = (int)(r / d), j = (int)(r % d);
+    const double *p = src + e * D;
+    const double u2 = sqrt(d / 2.0), u1 = sqrt((double)d);
+    double re, im;
+    if (i < j) {
+        re = u2 * p[i * d + j];
+        im = u2 * p[j * d + i];
+    } else if (i > j) {
+        re = -u2 * p[j * d + i];
+        im = u2 * p[i * d + j];
+    } else {
+        re = 0.0;
+        im = u1 * p[i * d + i];
+    }
+    dst[2 * idx] = re;
+    dst[2 * idx + 1] = im;
+}
+
+// ------------------------------------------------------------------ bracket
+//
+// For anti-Hermitian A, B write A = sqrt(d/2) (Ar + i Ai) with Ar antisymmetric
+// and Ai symmetric real, read straight from the packed arrays:
+//   Ar[i][k] = p[i][k] (i<k), -p[k][i] (i>k), 0 (i=k)
+//   Ai[i][k] = p[k][i] (i<k),  p[i][k] (i>k), sqrt(2) p[i][i] (i=k)
+// With P = (Ar + i Ai)(Br + i Bi) the bracket is [A,B] = AB - BA = (d/2)(P - P^H)
+// because BA = (AB)^H for anti-Hermitian A, B.  Its packed form is
+//   out[i][j] = sqrt(d/2) (Pr[i][j] - Pr[j][i]),  out[j][i] = sqrt(d/2) (Pi[i][j] + Pi[j][i])  (i<j)
+//   out[i][i] = sqrt(d) Pi[i][i].
+
+__device__ inline double unp_re(const double *p, int d, int i, int k)
+{
+    return i < k ? p[i * d + k] : (i > k ? -p[k * d + i] : 0.0);
+}
+__device__ inline double unp_im(const double *p, int d, int i, int k)
+{
+    return i < k ? p[k * d + i] : (i > k ? p[i * d + k] : 1.4142135623730951 * p[i * d + i]);
+}
+
+// One workgroup per candidate; both operands unpacked into LDS (d <= 64).
+__global__ void __launch_bounds__(kThreads) k_comm_f64_lds(const double *__restrict__ V, int d, int64_t p0,
+                                                           const int64_t *__restrict__ pair_list, int cnt,
+                                                           double *__restrict__ H)
+{
+    extern __shared__ double lds[];
+    const int c = blockIdx.x;
+    if (c >= cnt)
+        return;
+    const int64_t D = (int64_t)d * d;
+    int64_t l, m;
+    decode_pair(pair_list ? pair_list[c] : p0 + c, l, m);
+    const double *pa = V + l * D, *pb = V + m * D;
+    const int ld = d + 1;
+    double *Ar = lds, *Ai = Ar + d * ld, *Br = Ai + d * ld, *Bi = Br + d * ld;
+    for (int idx = threadIdx.x; idx < d * d; idx += blockDim.x) {
+        const int i = idx / d, k = idx % d;
+        Ar[i * ld + k] = unp_re(pa, d, i, k);
+        Ai[i * ld + k] = unp_im(pa, d, i, k);
+        Br[i * ld + k] = unp_re(pb, d, i, k);
+        Bi[i * ld + k] = unp_im(pb, d, i, k);
+    }
+    __syncthreads();
+    const double so = sqrt(d / 2.0), sd = sqrt((double)d);
+    double *out = H + (int64_t)c * D;
+    const int npairs = d * (d + 1) / 2;
+    for (int q = threadIdx.x; q < npairs; q += blockDim.x) {
+        // q -> (i, j), i <= j, row-major over the upper triangle
+        int i = 0, rem = q;
+        while (rem >= d - i) {
+            rem -= d - i;
+            ++i;
+        }
+        const int j = i + rem;
+        double prij = 0, piij = 0, prji = 0, piji = 0;
+        for (int k = 0; k < d; ++k) {
+            const double ar = Ar[i * ld + k], ai = Ai[i * ld + k];
+            const double br = Br[k * ld + j], bi = Bi[k * ld + j];
+            prij += ar * br - ai * bi;
+            piij += ar * bi + ai * br;
+            const double ar2 = Ar[j * ld + k], ai2 = Ai[j * ld + k];
+            const double br2 = Br[k * ld + i], bi2 = Bi[k * ld + i];
+            prji += ar2 * br2 - ai2 * bi2;
+            piji += ar2 * bi2 + ai2 * br2;
+        }
+        if (i < j) {
+            out[i * d + j] = so * (prij - prji);
+            out[j * d + i] = so * (piij + piji);
+        } else {
+            out[i * d + i] = sd * piij;
+        }
+    }
+}
+
+// Same bracket reading operands directly from global memory (any d).
+__global__ void __launch_bounds__(kThreads) k_comm_f64_global(const double *__restrict__ V, int d, int64_t p0,
+                                                              const int64_t *__restrict__ pair_list, int cnt,
+                                                              double *__restrict__ H)
+{
+    const int64_t D = (int64_t)d * d;
+    const int c = blockIdx.y;
+    if (c >= cnt)
+        return;
+    int64_t l, m;
+    decode_pair(pair_list ? pair_list[c] : p0 + c, l, m);
+    const double *pa = V + l * D, *pb = V + m * D;
+    const double so = sqrt(d / 2.0), sd = sqrt((double)d);
+    double *out = H + (int64_t)c * D;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= D)
+        return;
+    const int i = (int)(idx / d), j = (int)(idx % d);
+    if (i > j)
+        return;
+    double prij = 0, piij = 0, prji = 0, piji = 0;
+    for (int k = 0; k < d; ++k) {
+        const double ar = unp_re(pa, d, i, k), ai = unp_im(pa, d, i, k);
+        const double br = unp_re(pb, d, k, j), bi = unp_im(pb, d, k, j);
+        prij += ar * br - ai * bi;
+        piij += ar * bi + ai * br;
+        const double ar2 = unp_re(pa, d, j, k), ai2 = unp_im(pa, d, j, k);
+        const double br2 = unp_re(pb, d, k, i), bi2 = unp_im(pb, d, k, i);
+        prji += ar2 * br2 - ai2 * bi2;
+        piji += ar2 * bi2 + ai2 * br2;
+    }
+    if (i < j) {
+        out[i * d + j] = so * (prij - prji);
+        out[j * d + i] = so * (piij + piji);
+    } else {
+        out[i * d + i] = sd * piij;
+    }
+}
+
+// ------------------------------------------------------------------ projection
+//
+// C[c][k] = <H_c, V_k> for k < N (tiled: 16 basis rows x 16 candidates per workgroup).
+constexpr int kDotT = 16, kDotJ = 32;
+
+__global__ void __launch_bounds__(kThreads) k_dot_f64(const double *__restrict__ V, const int64_t *__restrict__ dN,
+                                                      int64_t N_fixed, const double *__restrict__ H, int cnt,
+                                                      int64_t D, double *__restrict__ C, int64_t ldc)
+{
+    const int64_t N = dN ? *dN : N_fixed;
+    const int64_t k0 = (int64_t)blockIdx.x * kDotT;
+    const int c0 = blockIdx.y * kDotT;
+    if (k0 >= N || c0 >= cnt)
+        return;
+    __shared__ double Vs[kDotT][kDotJ + 1];
+    __shared__ double Hs[kDotT][kDotJ + 1];
+    const int tk = threadIdx.x % kDotT, tc = threadIdx.x / kDotT;
+    double acc = 0.0;
+    for (int64_t j0 = 0; j0 < D; j0 += kDotJ) {
+        for (int e = threadIdx.x; e < kDotT * kDotJ; e += blockDim.x) {
+            const int r = e / kDotJ, jj = e % kDotJ;
+            const int64_t j = j0 + jj;
+            Vs[r][jj] = (k0 + r < N && j < D) ? V[(k0 + r) * D + j] : 0.0;
+            Hs[r][jj] = (c0 + r < cnt && j < D) ? H[(int64_t)(c0 + r) * D + j] : 0.0;
+        }
+        __syncthreads();
+        for (int jj = 0; jj < kDotJ; ++jj)
+            acc += Hs[tc][jj] * Vs[tk][jj];
+        __syncthreads();
+    }
+    if (k0 + tk < N && c0 + tc < cnt)
+        C[(int64_t)(c0 + tc) * ldc + k0 + tk] = acc;
+}
+
+// part[ks][c][j] = sum_{k in chunk ks} C[c][k] V[k][j]  (64 columns x 4 candidates per workgroup)
+constexpr int kSubJ = 64, kSubC = 4, kSubK = 16;
+
+__global__ void __launch_bounds__(kThreads) k_sub_partial_f64(const double *__restrict__ V,
+                                                              const int64_t *__restrict__ dN,
+                                                              const double *__restrict__ C, int64_t ldc, int cnt,
+                                                              int64_t D, int ks_total, double *__restrict__ part)
+{
+    const int64_t N = *dN;
+    const int64_t j0 = (int64_t)blockIdx.x * kSubJ;
+    const int c0 = blockIdx.y * kSubC;
+    const int ks = blockIdx.z;
+    const int tj = threadIdx.x % kSubJ, tc = threadIdx.x / kSubJ;
+    const int64_t chunk = (N + ks_total - 1) / ks_total;
+    const int64_t kb = ks * chunk, ke = std::min<int64_t>(N, kb + chunk);
+    __shared__ double Vs[kSubK][kSubJ];
+    __shared__ double Cs[kSubC][kSubK];
+    double acc = 0.0;
+    for (int64_t k0 = kb; k0 < ke; k0 += kSubK) {
+        for (int e = threadIdx.x; e < kSubK * kSubJ; e += blockDim.x) {
+            const int r = e / kSubJ, jj = e % kSubJ;
+            const int64_t k = k0 + r, j = j0 + jj;
+            Vs[r][jj] = (k < ke && j < D) ? V[k * D + j] : 0.0;
+        }
+        if (threadIdx.x < kSubC * kSubK) {
+            const int r = threadIdx.x / kSubK, kk = threadIdx.x % kSubK;
+            const int64_t k = k0 + kk;
+            Cs[r][kk] = (k < ke && c0 + r < cnt) ? C[(int64_t)(c0 + r) * ldc + k] : 0.0;
+        }
+        __syncthreads();
+        for (int kk = 0; kk < kSubK; ++kk)
+            acc += Cs[tc][kk] * Vs[kk][tj];
+        __syncthreads();
+    }
+    const int c = c0 + tc;
+    const int64_t j = j0 + tj;
+    if (c < cnt && j < D)
+        part[((int64_t)ks * cnt + c) * D + j] = acc;
+}
+
+// R = H - sum_ks part, written over H; per-(candidate, tile) squared norms of R and H.
+__global__ void __launch_bounds__(kThreads) k_sub_reduce_f64(double *__restrict__ H, const double *__restrict__ part,
+                                                             int cnt, int64_t D, int ks_total,
+                                                             double *__restrict__ normpart)
+{
+    __shared__ double red[8];
+    const int c = blockIdx.y;
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double r2 = 0.0, h2 = 0.0;
+    if (j < D) {
+        const double h = H[(int64_t)c * D + j];
+        double s = 0.0;
+        for (int ks = 0; ks < ks_total; ++ks)
+            s += part[((int64_t)ks * cnt + c) * D + j];
+        const double r = h - s;
+        H[(int64_t)c * D + j] = r;
+        r2 = r * r;
+        h2 = h * h;
+    }
+    r2 = block_sum(r2, red);
+    h2 = block_sum(h2, red);
+    if (threadIdx.x == 0) {
+        normpart[((int64_t)c * gridDim.x + blockIdx.x) * 2] = r2;
+        normpart[((int64_t)c * gridDim.x + blockIdx.x) * 2 + 1] = h2;
+    }
+}
+
+__global__ void k_norm_final(const double *__restrict__ normpart, int cnt, int tiles, double *__restrict__ rho2,
+                             double *__restrict__ h2)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= cnt)
+        return;
+    double a = 0.0, b = 0.0;
+    for (int t = 0; t < tiles; ++t) {
+        a += normpart[((int64_t)c * tiles + t) * 2];
+        b += normpart[((int64_t)c * tiles + t) * 2 + 1];
+    }
+    rho2[c] = a;
+    h2[c] = b;
+}
+
+int split_k(int64_t D, int cnt, int64_t n_hi)
+{
+    const int64_t jt = (D + kSubJ - 1) / kSubJ;
+    const int64_t ct = (cnt + kSubC - 1) / kSubC;
+    int64_t ks = (1024 + jt * ct - 1) / (jt * ct);
+    ks = std::min<int64_t>(ks, std::max<int64_t>(1, (n_hi + kSubK - 1) / kSubK));
+    ks = std::min<int64_t>(ks, 64);
+    return (int)std::max<int64_t>(ks, 1);
+}
+
+// ------------------------------------------------------------------ acceptance
+
+constexpr int kAccThreads = 256;
+constexpr int kMaxBlock = 1024;
+
+__global__ void __launch_bounds__(kAccThreads) k_accept_f64(double *__restrict__ V, DevState *__restrict__ st,
+                                                            double *__restrict__ H, const double *__restrict__ rho2,
+                                                            const double *__restrict__ h2v, int cnt, int64_t D,
+                                                            int64_t cap, int64_t ambient, double tol, int mode,
+                                                            int early_exit)
+{
+    __shared__ double coef[kMaxBlock];
+    __shared__ double red[8];
+    __shared__ int64_t sN;
+    __shared__ int stop;
+    __shared__ int verdict;
+    __shared__ double rr_s;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    if (threadIdx.x == 0) {
+        sN = st->N;
+        stop = st->done || st->numeric_error || st->full;
+    }
+    __syncthreads();
+    if (stop)
+        return;
+    const int64_t N0 = sN;
+    for (int c = 0; c < cnt; ++c) {
+        __syncthreads();  // everyone has read the previous candidate's verdict
+        const double r1 = sqrt(rho2[c]);
+        const double hn = sqrt(h2v[c]);
+        const double thr = mode == 0 ? tol * hn : tol;
+        double *R = H + (int64_t)c * D;
+        if (threadIdx.x == 0) {
+            verdict = 1;
+            if (mode == 1)
+                st->n_cand++;
+            if (!isfinite(r1) || !isfinite(hn)) {
+                st->numeric_error = 1;
+                verdict = -1;
+            } else if (hn == 0.0) {
+                if (mode == 1)
+                    st->n_zero++;
+                verdict = 0;
+            } else if (!(r1 > thr)) {
+                if (mode == 1) {
+                    st->n_fp64++;
+                    st->max_rej = fmax(st->max_rej, r1);
+                }
+                verdict = 0;
+            }
+        }
+        __syncthreads();
+        if (verdict < 0)
+            break;
+        if (verdict == 0)
+            continue;
+        // orthogonalise against the elements appended earlier in this call, twice
+        for (int pass = 0; pass < 2; ++pass) {
+            const int64_t A = sN - N0;
+            if (A == 0)
+                break;
+            for (int64_t a = w; a < A; a += nw) {
+                const double *va = V + (N0 + a) * D;
+                double s = 0.0;
+                for (int64_t j = lane; j < D; j += 64)
+                    s += va[j] * R[j];
+                s = wave_sum(s);
+                if (lane == 0)
+                    coef[a] = s;
+            }
+            __syncthreads();
+            for (int64_t j = threadIdx.x; j < D; j += blockDim.x) {
+                double s = 0.0;
+                for (int64_t a = 0; a < A; ++a)
+                    s += coef[a] * V[(N0 + a) * D + j];
+                R[j] -= s;
+            }
+            __syncthreads();
+        }
+        double loc = 0.0;
+        for (int64_t j = threadIdx.x; j < D; j += blockDim.x)
+            loc += R[j] * R[j];
+        loc = block_sum(loc, red);
+        if (threadIdx.x == 0) {
+            const double rr = sqrt(loc);
+            rr_s = rr;
+            if (mode == 1)
+                st->n_fp64++;
+            if (!isfinite(rr)) {
+                st->numeric_error = 1;
+                verdict = -1;
+            } else if (!(rr > thr)) {
+                if (mode == 1)
+                    st->max_rej = fmax(st->max_rej, rr);
+                verdict = 0;
+            } else if (mode == 1 && sN >= ambient) {
+                st->numeric_error = 2;  // one more independent element than the space holds
+                verdict = -1;
+            } else if (sN >= cap) {
+                st->full = 1;
+                verdict = -1;
+            } else {
+                verdict = 1;
+            }
+        }
+        __syncthreads();
+        if (verdict < 0)
+            break;
+        if (verdict == 0)
+            continue;
+        const double inv = 1.0 / rr_s;
+        double *dst = V + sN * D;
+        for (int64_t j = threadIdx.x; j < D; j += blockDim.x)
+            dst[j] = R[j] * inv;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            sN++;
+            if (mode == 1) {
+                st->n_acc++;
+                st->min_acc = fmin(st->min_acc, rr_s);
+            } else {
+                st->n_gen_acc++;
+            }
+            if (early_exit && sN >= ambient)
+                st->done = 1;
+        }
+        __syncthreads();
+        if (early_exit && sN >= ambient)
+            break;
+    }
+    if (threadIdx.x == 0)
+        st->N = sN;
+}
+
+// ------------------------------------------------------------------ orthogonality
+
+__global__ void __launch_bounds__(kThreads) k_gram_loss_part(const double *__restrict__ G, int64_t n,
+                                                             double *__restrict__ part)
+{
+    __shared__ double red[8];
+    double s = 0.0;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n * n; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = e / n, j = e % n;
+        const double g = G[e] - (i == j ? 1.0 : 0.0);
+        s += g * g;
+    }
+    s = block_sum(s, red);
+    if (threadIdx.x == 0)
+        part[blockIdx.x] = s;
+}
+
+__global__ void k_gram_loss_final(const double *__restrict__ part, int parts, double *__restrict__ out)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        double s = 0.0;
+        for (int i = 0; i < parts; ++i)
+            s += part[i];
+        *out = sqrt(s);
+    }
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ launchers
+
+hipError_t launch_pack_c128(const double *src, double *dst, int count, int d, hipStream_t s)
+{
+    const int64_t total = (int64_t)count * d * d;
+    const int blocks = (int)((total + kThreads - 1) / kThreads);
+    if (blocks == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_pack_c128, dim3(blocks), dim3(kThreads), 0, s, src, dst, count, d);
+    return hipGetLastError();
+}
+
+hipError_t launch_unpack_c128(const double *src, double *dst, int64_t count, int d, hipStream_t s)
+{
+    const int64_t total = count * d * d;
+    const int64_t blocks = (total + kThreads - 1) / kThreads;
+    if (blocks == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_unpack_c128, dim3((unsigned)blocks), dim3(kThreads), 0, s, src, dst, count, d);
+    return hipGetLastError();
+}
+
+hipError_t launch_comm_f64(const double *V, int d, int64_t p0, const int64_t *pair_list, int cnt, double *H,
+                           hipStream_t s)
+{
+    if (cnt <= 0)
+        return hipSuccess;
+    const size_t lds = (size_t)4 * d * (d + 1) * sizeof(double);
+    static int max_lds = -1;
+    if (max_lds < 0) {
+        int dev = 0, v = 65536;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess)
+            max_lds = v;
+        else
+            max_lds = 65536;
+        if (max_lds > 65536)
+            (void)hipFuncSetAttribute((const void *)k_comm_f64_lds, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      max_lds);
+    }
+    if (d <= 64 && lds <= (size_t)max_lds) {
+        hipLaunchKernelGGL(k_comm_f64_lds, dim3(cnt), dim3(kThreads), lds, s, V, d, p0, pair_list, cnt, H);
+    } else {
+        const int64_t D = (int64_t)d * d;
+        hipLaunchKernelGGL(k_comm_f64_global, dim3((unsigned)((D + kThreads - 1) / kThreads), cnt), dim3(kThreads), 0,
+                           s, V, d, p0, pair_list, cnt, H);
+    }
+    return hipGetLastError();
+}
+
+size_t proj_scratch_doubles(int64_t D, int cnt_max, int64_t cap)
+{
+    size_t best = 0;
+    for (int cnt = 1; cnt <= cnt_max; ++cnt) {
+        const int ks = split_k(D, cnt, cap);
+        best = std::max(best, (size_t)ks * cnt * D);
+    }
+    const int64_t tiles = (D + kThreads - 1) / kThreads;
+    return best + (size_t)cnt_max * tiles * 2;  // + norm partials
+}
+
+hipError_t launch_project_f64(const double *V, const int64_t *dN, double *H, double *C, double *part, double *rho2,
+                              double *h2, ProjShape sh, hipStream_t s)
+{
+    const int cnt = sh.cnt;
+    if (cnt <= 0)
+        return hipSuccess;
+    const int64_t D = sh.D;
+    const int64_t n_hi = std::max<int64_t>(sh.n_hi, 1);
+    const int64_t ldc = n_hi;
+    // 1) coefficients
+    hipLaunchKernelGGL(k_dot_f64, dim3((unsigned)((n_hi + kDotT - 1) / kDotT), (cnt + kDotT - 1) / kDotT),
+                       dim3(kThreads), 0, s, V, dN, (int64_t)0, H, cnt, D, C, ldc);
+    // 2) split-K partial subtraction
+    const int ks = split_k(D, cnt, n_hi);
+    hipLaunchKernelGGL(k_sub_partial_f64,
+                       dim3((unsigned)((D + kSubJ - 1) / kSubJ), (cnt + kSubC - 1) / kSubC, ks), dim3(kThreads), 0, s,
+                       V, dN, C, ldc, cnt, D, ks, part);
+    // 3) reduce, subtract, norms
+    const int tiles = (int)((D + kThreads - 1) / kThreads);
+    double *normpart = part + (size_t)ks * cnt * D;
+    hipLaunchKernelGGL(k_sub_reduce_f64, dim3(tiles, cnt), dim3(kThreads), 0, s, H, part, cnt, D, ks, normpart);
+    hipLaunchKernelGGL(k_norm_final, dim3((cnt + kThreads - 1) / kThreads), dim3(kThreads), 0, s, normpart, cnt,
+                       tiles, rho2, h2);
+    return hipGetLastError();
+}
+
+hipError_t launch_accept_f64(double *V, DevState *st, double *H, const double *rho2, const double *h2, int cnt,
+                             int64_t D, int64_t cap, int64_t ambient, double tol, int mode, int early_exit,
+                             hipStream_t s)
+{
+    if (cnt <= 0)
+        return hipSuccess;
+    if (cnt > kMaxBlock)
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_accept_f64, dim3(1), dim3(kAccThreads), 0, s, V, st, H, rho2, h2, cnt, D, cap, ambient, tol,
+                       mode, early_exit);
+    return hipGetLastError();
+}
+
+hipError_t launch_orth_loss(const double *V, int64_t n, int64_t D, double *work, double *out, hipStream_t s)
+{
+    if (n <= 0) {
+        return hipMemsetAsync(out, 0, sizeof(double), s);
+    }
+    // G = V V^T through the coefficient kernel (candidates = basis rows)
+    double *G = work;
+    for (int64_t c0 = 0; c0 < n; c0 += 65535 * kDotT) {
+        const int64_t rows = std::min<int64_t>(n - c0, (int64_t)65535 * kDotT);
+        hipLaunchKernelGGL(k_dot_f64, dim3((unsigned)((n + kDotT - 1) / kDotT), (unsigned)((rows + kDotT - 1) / kDotT)),
+                           dim3(kThreads), 0, s, V, (const int64_t *)nullptr, n, V + c0 * D, (int)rows, D,
+                           G + c0 * n, n);
+    }
+    const int parts = 256;
+    double *part = work + n * n;
+    hipLaunchKernelGGL(k_gram_loss_part, dim3(parts), dim3(kThreads), 0, s, G, n, part);
+    hipLaunchKernelGGL(k_gram_loss_final, dim3(1), dim3(64), 0, s, part, parts, out);
+    return hipGetLastError();
+}
+
+}  // namespace lie

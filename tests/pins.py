@@ -220,3 +220,17 @@ def orthonormality_loss(v: np.ndarray) -> float:
     q = _orthonormal_columns(v)
     g = q.conj().T @ q
     return float(np.linalg.norm(g - np.eye(g.shape[0])))
+
+
+def pauli_subset_span_distance(v: np.ndarray, strings) -> float:
+    """||P_V - P_S||_F for dim V = |S|, from the explicit residual V_k - sum_{P in S} <P,V_k> P.
+
+    Only the strings of S are formed, so this scales to large d when |S| is small.
+    """
+    from paper_2506_01120_amd.workloads import pauli_string
+
+    d = v.shape[-1]
+    mats = np.stack([pauli_string(s) for s in sorted(strings)])  # Hermitian, <P,Q> = delta
+    coef = np.einsum("pij,kji->kp", mats, v) / d
+    resid = v - np.einsum("kp,pij->kij", coef, mats)
+    return float(np.sqrt(2.0 * np.sum(np.abs(resid) ** 2) / d))

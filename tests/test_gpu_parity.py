@@ -1,0 +1,141 @@
+"""GPU parity: the HIP path against the CPU reference, through the C ABI.
+
+Bars (FP64 path): closure dimensions identical to the reference; span
+distance ||P_gpu - P_ref||_F <= 1e-8; element-wise basis agreement (the
+basis is fixed by the candidate order, so it is unique up to rounding);
+orthogonality loss ||V^H V - I||_F <= 1e-10.
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import pins
+from oracle import oracle as O
+from paper_2506_01120_amd import LieClosure, LieError, workloads as W
+
+pytestmark = pytest.mark.gpu
+
+SPAN_TOL_FP64 = 1e-8
+ELEM_TOL_FP64 = 1e-8
+ORTH_TOL_FP64 = 1e-10
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible to torch")
+    from paper_2506_01120_amd import _lib
+    _lib.load()
+
+
+def gpu_closure(gens, tol, **cfg):
+    print(f"[gpu] d={gens.shape[-1]} n_gen={len(gens)} tol={tol} cfg={cfg}", flush=True)
+    with LieClosure(gens, tol, **cfg) as lc:
+        lc.run()
+        return lc.dim, lc.basis(), lc.stats(), lc.orthogonality()
+
+
+def assert_parity(gens, tol, *, early_exit=False, expected=None, **cfg):
+    ref = O.closure(gens, tol, early_exit=early_exit)
+    dim, v, st, orth = gpu_closure(gens, tol, early_exit=early_exit, **cfg)
+    assert dim == ref.dim, (dim, ref.dim)
+    if expected is not None:
+        assert dim == expected
+    assert pins.span_distance(v, ref.basis) <= SPAN_TOL_FP64
+    assert np.max(np.abs(v - ref.basis)) <= ELEM_TOL_FP64
+    assert orth <= ORTH_TOL_FP64
+    assert st["done"] == 1
+    if not early_exit:
+        assert st["candidates"] == ref.candidates == dim * (dim - 1) // 2
+    return dim, v, st
+
+
+@pytest.mark.parametrize("block", [1, 7, 256])
+def test_ising3_plain_and_blocked(block):
+    """Open TFIM chain n=3, d=8: so(6), dim 15, tol 1e-10."""
+    dim, v, _ = assert_parity(W.ising(3), 1e-10, block=block, expected=15)
+    closed = pins.pauli_closure(["XII", "IXI", "IIX", "ZZI", "IZZ"])
+    assert pins.pauli_span_distance(v, closed) <= SPAN_TOL_FP64
+
+
+@pytest.mark.parametrize("block", [1, 256])
+def test_random_pair_16(block):
+    """Random traceless anti-Hermitian pair, d=16, seed 2: su(16), dim 255, tol 1e-10."""
+    dim, v, _ = assert_parity(W.rand_pair(16, seed=2), 1e-10, block=block, expected=255)
+    assert pins.su_span_distance(v) <= SPAN_TOL_FP64
+
+
+@pytest.mark.parametrize("d", [1, 2, 3, 5, 6, 7])
+def test_ragged_small_pairs(d):
+    gens = W.rand_pair(d, seed=40 + d) if d > 1 else np.array([[[1j]]])
+    assert_parity(gens, 1e-10, block=5)
+
+
+@pytest.mark.parametrize("n", [3, 4, 5])
+def test_xxyy_chain(n):
+    assert_parity(W.xxyy(n), 1e-10, block=64, expected=n * (n - 1) // 2)
+
+
+@pytest.mark.parametrize("n,k,seed", [(4, 5, 10), (4, 6, 11), (3, 6, 12)])
+def test_pauli_sets(n, k, seed):
+    strings, _ = W.pauli_set_strings(n, k, seed)
+    assert_parity(W.pauli_set(n, k, seed), 1e-10, block=32, expected=len(pins.pauli_closure(strings)))
+
+
+def test_generator_edge_cases():
+    g = W.ising(3)
+    gens = np.concatenate([np.zeros((1, 8, 8), complex), g, g[:2], 3.0 * g[2:3]])
+    assert_parity(gens, 1e-10, block=16, expected=15)
+
+
+def test_early_exit():
+    gens = W.rand_pair(8, seed=11)
+    dim, v, st = assert_parity(gens, 1e-10, block=32, early_exit=True, expected=63)
+    assert st["candidates"] < 63 * 62 // 2
+
+
+def test_budget_resume_matches_uninterrupted():
+    gens = W.rand_pair(6, seed=12)
+    with LieClosure(gens, 1e-10, block=8) as a:
+        a.run()
+        va, sa = a.basis(), a.stats()
+    with LieClosure(gens, 1e-10, block=8) as b:
+        calls = 0
+        while not b.run(budget=40):
+            calls += 1
+        vb, sb = b.basis(), b.stats()
+    assert calls > 3
+    assert sa["dim"] == sb["dim"] and sa["candidates"] == sb["candidates"]
+    np.testing.assert_array_equal(va, vb)
+
+
+def test_determinism():
+    gens = W.rand_pair(8, seed=13)
+    v1 = gpu_closure(gens, 1e-10, block=64)[1]
+    v2 = gpu_closure(gens, 1e-10, block=64)[1]
+    np.testing.assert_array_equal(v1, v2)
+
+
+def test_capacity_error():
+    with LieClosure(W.rand_pair(4, seed=3), 1e-10, max_dim=6, block=4) as lc:
+        with pytest.raises(LieError) as e:
+            lc.run()
+        assert e.value.status == -7
+        assert lc.dim == 6
+        with pytest.raises(LieError):
+            lc.run()  # a failed handle stays failed
+
+
+def test_basis_device_matches_host():
+    import torch
+
+    with LieClosure(W.ising(3), 1e-10) as lc:
+        lc.run()
+        host = lc.basis()
+        dev = lc.basis_device()
+        assert dev.device.type == "cuda"
+        np.testing.assert_array_equal(dev.cpu().numpy(), host)
+        torch.cuda.synchronize()
