@@ -1,0 +1,182 @@
+#!/usr/bin/env python3
+"""Benchmark: bracket + independence checks per second and time-to-closure on one MI355X.
+
+One step = one complete closure (the whole bracket loop, full certification
+unless --early-exit) of the workload's generators; the generator phase of each
+step's handle runs before the timed region, so the inputs (and the first basis
+elements) are resident in HBM when timing starts.
+
+Default workload: two random traceless anti-Hermitian 16 x 16 matrices
+(seed 2, Frobenius-normalised), tol 1e-10, FP64 decisions -- closure su(16),
+dim 255, 32,385 brackets per step.
+
+Prints ONE JSON line.  `roofline` describes the dominant kernel, timed live
+with HIP events on the library's stream during the timed steps; `cpu_baseline`
+times the CPU reference on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "bracket+independence checks/sec and time-to-closure; mixed/batched vs FP64 plain, 1 GPU"
+
+# MI355X published peaks
+PEAK = {"hbm_GBps": 8000.0, "fp64_TF": 78.6, "fp32_TF": 157.3, "bf16_TF": 2500.0}
+
+
+def workload(name: str):
+    from paper_2506_01120_amd import workloads as W
+
+    if name == "su16":
+        return W.rand_pair(16, seed=2), 1e-10, "random traceless anti-Hermitian pair d=16 seed 2 -> su(16)"
+    if name == "ising3":
+        return W.ising(3), 1e-10, "open transverse-field Ising chain n=3 d=8 -> so(6)"
+    if name == "su32":
+        return W.rand_pair(32, seed=3), 1e-8, "random traceless anti-Hermitian pair d=32 seed 3 -> su(32)"
+    if name == "su64":
+        return W.rand_pair(64, seed=5), 1e-8, "random traceless anti-Hermitian pair d=64 seed 5 -> su(64)"
+    raise SystemExit(f"unknown workload {name}")
+
+
+def run_steps(gens, tol, cfg, steps):
+    import torch
+
+    from paper_2506_01120_amd import LieClosure
+
+    handles = [LieClosure(gens, tol, **cfg) for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for h in handles:
+        h.run()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    stats = [h.stats() for h in handles]
+    dims = [h.dim for h in handles]
+    for h in handles:
+        h.close()
+    return t1 - t0, stats, dims
+
+
+def roofline(stats, precision: str):
+    """Dominant kernel class over the timed steps: algorithmic work / summed HIP-event time."""
+    names = list(stats[0]["kernel_ms"].keys())
+    ms = {k: sum(s["kernel_ms"][k] for s in stats) for k in names}
+    fl = {k: sum(s["kernel_flops"][k] for s in stats) for k in names}
+    by = {k: sum(s["kernel_bytes"][k] for s in stats) for k in names}
+    n = {k: sum(s["kernel_launches"][k] for s in stats) for k in names}
+    dom = max(names, key=lambda k: ms[k])
+    t = ms[dom] / 1e3
+    peak_tf = PEAK["fp64_TF"] if precision == "fp64" else PEAK["fp32_TF"] if precision == "fp32" else PEAK["bf16_TF"]
+    intensity = fl[dom] / by[dom] if by[dom] else float("inf")
+    ridge = peak_tf * 1e12 / (PEAK["hbm_GBps"] * 1e9)
+    if fl[dom] > 0 and intensity >= ridge:
+        achieved, peak, unit, bound = fl[dom] / t / 1e12, peak_tf, "TFLOP/s", "mfma"
+    else:
+        achieved, peak, unit, bound = by[dom] / t / 1e9, PEAK["hbm_GBps"], "GB/s", "hbm"
+    breakdown = {k: {"ms": round(ms[k], 3), "launches": n[k], "avg_us": round(1e3 * ms[k] / n[k], 3) if n[k] else 0}
+                 for k in names if n[k]}
+    return {"kernel": dom, "bound": bound, "achieved": round(achieved, 4), "peak": peak, "unit": unit,
+            "frac": round(achieved / peak, 5), "traffic": None,
+            "algorithmic_flops_per_launch": fl[dom] / n[dom], "algorithmic_bytes_per_launch": by[dom] / n[dom],
+            "avg_launch_us": 1e6 * t / n[dom], "breakdown": breakdown}
+
+
+def cpu_baseline(gens, tol, early_exit: bool, target_s: float = 10.0):
+    """The CPU reference as it stands, single-threaded, on this host: whole closures until ~target_s."""
+    from oracle import oracle as ref
+
+    ref.load()
+    done, cands, t = 0, 0, 0.0
+    while t < target_s and done < 3:
+        o = ref.Oracle(gens, tol)
+        t0 = time.perf_counter()
+        o.run(early_exit=early_exit)
+        t += time.perf_counter() - t0
+        cands += o.result().candidates
+        done += 1
+    return {"value": cands / t, "unit": "checks/s", "cores": 1, "kind": "oracle",
+            "sample": f"{done} complete closure(s) of the same workload, {cands} bracket checks, {t:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="su16")
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16x3"])
+    ap.add_argument("--decide", default="screen", choices=["fp64", "strict", "screen"])
+    ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--early-exit", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true", help="skip the one-candidate-at-a-time FP64 comparison run")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only: this build has no multi-GPU path (asked for --gpus {args.gpus}).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    gens, tol, desc = workload(args.workload)
+    cfg = dict(precision=args.precision, decide=args.decide, block=args.block, early_exit=args.early_exit)
+
+    print(f"[bench] warmup {args.warmup} x {args.workload} {cfg}", file=sys.stderr, flush=True)
+    if args.warmup:
+        run_steps(gens, tol, cfg, args.warmup)
+    print(f"[bench] timed {args.steps} steps", file=sys.stderr, flush=True)
+    elapsed, stats, dims = run_steps(gens, tol, dict(cfg, profile=True), args.steps)
+    checks = sum(s["candidates"] for s in stats)
+    value = checks / elapsed
+    ms_per_step = 1e3 * elapsed / args.steps
+    roof = roofline(stats, args.precision)
+
+    plain = None
+    if not args.no_plain:
+        print("[bench] plain one-at-a-time FP64 comparison step", file=sys.stderr, flush=True)
+        pt, pstats, _ = run_steps(gens, tol, dict(cfg, precision="fp64", block=1), 1)
+        plain = {"checks_per_s": pstats[0]["candidates"] / pt, "ms_per_step": 1e3 * pt}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        print("[bench] CPU reference baseline", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(gens, tol, args.early_exit)
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "checks/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else ("f32+f64" if args.precision == "fp32" else "bf16x3+f64"),
+        "data": "synthetic (seeded generators)",
+        "config": {"workload": desc, "d": int(gens.shape[-1]), "n_gen": int(gens.shape[0]), "tol": tol,
+                   "dim": dims[0], "checks_per_step": checks // args.steps, "precision": args.precision,
+                   "decide": args.decide if args.precision != "fp64" else "fp64",
+                   "block": stats[0]["block"], "early_exit": bool(args.early_exit), "parallelism": "single GPU"},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "plain_fp64": plain,
+        "speedup_vs_plain_fp64": round(value / plain["checks_per_s"], 2) if plain else None,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -77,8 +77,21 @@ typedef struct lie_closure_config {
     int64_t max_dim;       /* basis capacity; 0 = ambient bound */
     void *stream;          /* hipStream_t the handle runs on; NULL = a stream the library creates */
     int32_t use_graphs;    /* 1: replay block steps from captured hipGraphs (default 1) */
-    int32_t reserved[7];   /* must be zero */
+    int32_t profile;       /* 1: time every kernel launch with HIP events on the handle's stream */
+    int32_t reserved[6];   /* must be zero */
 } lie_closure_config;
+
+/* Kernel classes reported by the per-kernel counters of lie_closure_stats. */
+typedef enum lie_kernel_id {
+    LIE_K_COMM = 0,      /* screening (or FP64) bracket of a candidate block */
+    LIE_K_DOT = 1,       /* screening (or FP64) coefficients C = H V^T */
+    LIE_K_SUB = 2,       /* screening (or FP64) subtraction R = H - C V (+ norm partials) */
+    LIE_K_REDUCE = 3,    /* split-K reduction, residual norms, classification */
+    LIE_K_ACCEPT = 4,    /* sequential in-block acceptance and append (FP64) */
+    LIE_K_VERIFY = 5,    /* FP64 recomputation of screen survivors (bracket + CGS2 passes) */
+    LIE_K_OTHER = 6,     /* everything else (packing, shadow copies, bookkeeping) */
+    LIE_K_COUNT = 8
+} lie_kernel_id;
 
 typedef struct lie_closure_stats {
     uint32_t struct_size;         /* must be sizeof(lie_closure_stats) */
@@ -98,6 +111,14 @@ typedef struct lie_closure_stats {
     double max_screen_rejected;   /* largest screened residual among screen rejects */
     double run_ms;                /* wall time spent inside lie_closure_run* calls */
     int32_t precision, decide, block, early_exit;
+    /* Per kernel class (lie_kernel_id), accumulated over the run: launches, and
+     * the algorithmic floating-point operations and bytes those launches must
+     * perform (formulas in the engine source).  kernel_ms is the summed
+     * HIP-event duration and is filled only when config.profile = 1. */
+    int64_t kernel_launches[LIE_K_COUNT];
+    double kernel_ms[LIE_K_COUNT];
+    double kernel_flops[LIE_K_COUNT];
+    double kernel_bytes[LIE_K_COUNT];
 } lie_closure_stats;
 
 /* Fill *cfg with defaults (struct_size set).  Returns LIE_ERR_ARG for NULL. */

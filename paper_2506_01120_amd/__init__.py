@@ -23,7 +23,7 @@ __all__ = ["LieClosure", "BatchClosure", "closure", "LieError", "make_config"]
 
 def make_config(*, precision: str = "fp64", decide: str = "screen", block: int = 0, early_exit: bool = False,
                 tau_rej: float = 0.0, max_dim: int = 0, stream=None, device: int | None = None,
-                use_graphs: bool = True) -> _lib.Config:
+                use_graphs: bool = True, profile: bool = False) -> _lib.Config:
     cfg = _lib.Config()
     _lib.check(_lib.load().lie_closure_config_default(ctypes.byref(cfg)))
     cfg.precision = _lib.PRECISIONS[precision]
@@ -34,6 +34,7 @@ def make_config(*, precision: str = "fp64", decide: str = "screen", block: int =
     cfg.max_dim = int(max_dim)
     cfg.device = -1 if device is None else int(device)
     cfg.use_graphs = 1 if use_graphs else 0
+    cfg.profile = 1 if profile else 0
     if stream is not None:
         cfg.stream = int(getattr(stream, "cuda_stream", stream))
     return cfg

@@ -20,6 +20,8 @@ STATUS_NAMES = {
 }
 
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 2}
+K_COUNT = 8
+KERNEL_NAMES = ("comm", "dot", "sub", "reduce", "accept", "verify", "other")
 DECIDES = {"fp64": 0, "strict": 1, "screen": 2}
 
 # Every symbol include/lie_closure.h declares.
@@ -44,7 +46,8 @@ class Config(ctypes.Structure):
         ("max_dim", ctypes.c_int64),
         ("stream", ctypes.c_void_p),
         ("use_graphs", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 7),
+        ("profile", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 6),
     ]
 
 
@@ -70,10 +73,22 @@ class Stats(ctypes.Structure):
         ("decide", ctypes.c_int32),
         ("block", ctypes.c_int32),
         ("early_exit", ctypes.c_int32),
+        ("kernel_launches", ctypes.c_int64 * K_COUNT),
+        ("kernel_ms", ctypes.c_double * K_COUNT),
+        ("kernel_flops", ctypes.c_double * K_COUNT),
+        ("kernel_bytes", ctypes.c_double * K_COUNT),
     ]
 
     def as_dict(self) -> dict:
-        return {name: getattr(self, name) for name, _ in self._fields_ if name != "struct_size"}
+        out = {}
+        for name, _ in self._fields_:
+            if name == "struct_size":
+                continue
+            v = getattr(self, name)
+            if name.startswith("kernel_"):
+                v = {KERNEL_NAMES[i]: v[i] for i in range(len(KERNEL_NAMES))}
+            out[name] = v
+        return out
 
 
 _lib = None

@@ -47,6 +47,81 @@ constexpr int kMaxD = 128;
 
 int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
+// Per-kernel-class launch counters, algorithmic work, and (optionally) HIP-event
+// durations.  Events bracket single kernel launches on the handle's stream and
+// are harvested at the driver's synchronisation points.
+struct KernelTimer {
+    bool on = false;
+    struct Pending {
+        int k;
+        hipEvent_t a, b;
+    };
+    std::vector<Pending> pending;
+    std::vector<hipEvent_t> pool;
+    int64_t n[LIE_K_COUNT] = {};
+    double ms[LIE_K_COUNT] = {};
+    double flops[LIE_K_COUNT] = {};
+    double bytes[LIE_K_COUNT] = {};
+    hipEvent_t cur_a = nullptr;
+
+    hipEvent_t get()
+    {
+        if (!pool.empty()) {
+            hipEvent_t e = pool.back();
+            pool.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess)
+            return nullptr;
+        return e;
+    }
+    void begin(hipStream_t s)
+    {
+        cur_a = nullptr;
+        if (!on)
+            return;
+        cur_a = get();
+        if (cur_a)
+            (void)hipEventRecord(cur_a, s);
+    }
+    void end(int k, hipStream_t s, double f, double b)
+    {
+        n[k]++;
+        flops[k] += f;
+        bytes[k] += b;
+        if (!on || !cur_a)
+            return;
+        hipEvent_t e = get();
+        if (!e)
+            return;
+        (void)hipEventRecord(e, s);
+        pending.push_back({k, cur_a, e});
+        cur_a = nullptr;
+    }
+    // Call only after the stream has been synchronised.
+    void harvest()
+    {
+        for (auto &p : pending) {
+            float t = 0.f;
+            if (hipEventElapsedTime(&t, p.a, p.b) == hipSuccess)
+                ms[p.k] += t;
+            pool.push_back(p.a);
+            pool.push_back(p.b);
+        }
+        pending.clear();
+    }
+    ~KernelTimer()
+    {
+        for (auto &p : pending) {
+            pool.push_back(p.a);
+            pool.push_back(p.b);
+        }
+        for (hipEvent_t e : pool)
+            (void)hipEventDestroy(e);
+    }
+};
+
 }  // namespace
 
 struct lie_closure {
@@ -81,6 +156,7 @@ struct lie_closure {
     int64_t blocks = 0;
     int64_t host_syncs = 0;
     double run_ms = 0;
+    KernelTimer timer;
 
     ~lie_closure()
     {
@@ -101,6 +177,7 @@ struct lie_closure {
         HIP_TRY(hipMemcpyAsync(&hs, st, sizeof hs, hipMemcpyDeviceToHost, stream));
         HIP_TRY(hipStreamSynchronize(stream));
         ++host_syncs;
+        timer.harvest();
         return LIE_OK;
     }
 
@@ -124,10 +201,25 @@ struct lie_closure {
         return LIE_OK;
     }
 
-    lie_status project(double *rho2_out, double *h2_out, int cnt, int64_t n_hi)
+    // One FP64 projection pass over H64[0..cnt) against the current basis
+    // (n_now = |V| as known to the host, an upper bound is enough for the grid).
+    // Algorithmic work per candidate: 2*N*D flops for the coefficients and
+    // 2*N*D for the subtraction; bytes: the basis streamed once per kernel,
+    // candidates read once and the residual written once.
+    lie_status project(double *rho2_out, double *h2_out, int cnt, int64_t n_now, int kid_dot, int kid_sub)
     {
-        lie::ProjShape sh{D, cnt, std::min(n_hi, cap)};
-        HIP_TRY(lie::launch_project_f64(V64, &st->N, H64, C, part, rho2_out, h2_out, sh, stream));
+        lie::ProjShape sh{D, cnt, std::min(std::max<int64_t>(n_now, 1), cap)};
+        const double N = (double)n_now, Dd = (double)D, c = cnt, w = sizeof(double);
+        timer.begin(stream);
+        HIP_TRY(lie::launch_dot_f64(V64, &st->N, H64, C, sh, stream));
+        timer.end(kid_dot, stream, 2.0 * N * Dd * c, (N * Dd + c * Dd + c * N) * w);
+        timer.begin(stream);
+        HIP_TRY(lie::launch_sub_f64(V64, &st->N, C, part, sh, stream));
+        timer.end(kid_sub, stream, 2.0 * N * Dd * c, (N * Dd + c * N + c * Dd) * w);
+        const int ks = lie::project_split_k(D, cnt, sh.n_hi);
+        timer.begin(stream);
+        HIP_TRY(lie::launch_reduce_f64(H64, part, rho2_out, h2_out, sh, stream));
+        timer.end(LIE_K_REDUCE, stream, 3.0 * c * Dd, (ks + 2.0) * c * Dd * w);
         return LIE_OK;
     }
 
@@ -149,11 +241,13 @@ struct lie_closure {
         for (int g = 0; g < n_gen; ++g) {
             HIP_TRY(hipMemcpyAsync(H64, packed + (size_t)g * D, D * sizeof(double), hipMemcpyDeviceToDevice, stream));
             lie_status s;
-            if ((s = project(rho2a, h2, 1, g)) != LIE_OK)
+            if ((s = project(rho2a, h2, 1, g, LIE_K_OTHER, LIE_K_OTHER)) != LIE_OK)
                 return s;
-            if ((s = project(rho2, h2b, 1, g)) != LIE_OK)
+            if ((s = project(rho2, h2b, 1, g, LIE_K_OTHER, LIE_K_OTHER)) != LIE_OK)
                 return s;
+            timer.begin(stream);
             HIP_TRY(lie::launch_accept_f64(V64, st, H64, rho2, h2, 1, D, cap, ambient, tol, 0, 0, stream));
+            timer.end(LIE_K_OTHER, stream, 0, 0);
         }
         lie_status s = sync_state();
         if (s != LIE_OK)
@@ -162,15 +256,22 @@ struct lie_closure {
     }
 
     // One block step over pair indices [cursor, cursor + cnt).
-    lie_status step(int cnt, int64_t n_hi)
+    // Bracket work per candidate: one complex d x d product (8 d^3 flops), since
+    // [a,b] = ab - (ab)^H for anti-Hermitian a, b; bytes: two operands read, one result written.
+    lie_status step(int cnt, int64_t n_now)
     {
+        const double c = cnt, Dd = (double)D, dd = d;
+        timer.begin(stream);
         HIP_TRY(lie::launch_comm_f64(V64, d, cursor, nullptr, cnt, H64, stream));
+        timer.end(LIE_K_COMM, stream, 8.0 * dd * dd * dd * c, 3.0 * c * Dd * sizeof(double));
         lie_status s;
-        if ((s = project(rho2a, h2, cnt, n_hi)) != LIE_OK)
+        if ((s = project(rho2a, h2, cnt, n_now, LIE_K_DOT, LIE_K_SUB)) != LIE_OK)
             return s;
-        if ((s = project(rho2, h2b, cnt, n_hi)) != LIE_OK)
+        if ((s = project(rho2, h2b, cnt, n_now, LIE_K_VERIFY, LIE_K_VERIFY)) != LIE_OK)
             return s;
+        timer.begin(stream);
         HIP_TRY(lie::launch_accept_f64(V64, st, H64, rho2, h2, cnt, D, cap, ambient, tol, 1, cfg.early_exit, stream));
+        timer.end(LIE_K_ACCEPT, stream, 0, 0);
         cursor += cnt;
         ++blocks;
         return LIE_OK;
@@ -201,7 +302,7 @@ struct lie_closure {
                 break;
             }
             const int cnt = (int)std::min<int64_t>(block, avail - cursor);
-            if ((s = step(cnt, hs.N + cnt)) != LIE_OK)
+            if ((s = step(cnt, hs.N)) != LIE_OK)
                 break;
             spent += cnt;
             if ((s = sync_state()) != LIE_OK)
@@ -337,6 +438,7 @@ lie_status lie_closure_init(lie_closure **out, const double *generators, int32_t
     h->ambient = ambient;
     h->cfg = cfg;
     h->block = cfg.block;
+    h->timer.on = cfg.profile != 0;
     h->cap = cfg.max_dim > 0 ? std::min<int64_t>(cfg.max_dim, h->D) : std::max<int64_t>(ambient, 1);
     h->device = -1;
 
@@ -511,6 +613,12 @@ lie_status lie_closure_stats_get(const lie_closure *h, lie_closure_stats *out)
     out->decide = h->cfg.decide;
     out->block = h->block;
     out->early_exit = h->cfg.early_exit;
+    for (int k = 0; k < LIE_K_COUNT; ++k) {
+        out->kernel_launches[k] = h->timer.n[k];
+        out->kernel_ms[k] = h->timer.ms[k];
+        out->kernel_flops[k] = h->timer.flops[k];
+        out->kernel_bytes[k] = h->timer.bytes[k];
+    }
     return LIE_OK;
 }
 

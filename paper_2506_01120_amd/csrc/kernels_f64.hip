@@ -547,27 +547,43 @@ size_t proj_scratch_doubles(int64_t D, int cnt_max, int64_t cap)
     return best + (size_t)cnt_max * tiles * 2;  // + norm partials
 }
 
-hipError_t launch_project_f64(const double *V, const int64_t *dN, double *H, double *C, double *part, double *rho2,
-                              double *h2, ProjShape sh, hipStream_t s)
+int project_split_k(int64_t D, int cnt, int64_t n_hi) { return split_k(D, cnt, std::max<int64_t>(n_hi, 1)); }
+
+hipError_t launch_dot_f64(const double *V, const int64_t *dN, const double *H, double *C, ProjShape sh, hipStream_t s)
 {
     const int cnt = sh.cnt;
     if (cnt <= 0)
         return hipSuccess;
-    const int64_t D = sh.D;
     const int64_t n_hi = std::max<int64_t>(sh.n_hi, 1);
-    const int64_t ldc = n_hi;
-    // 1) coefficients
     hipLaunchKernelGGL(k_dot_f64, dim3((unsigned)((n_hi + kDotT - 1) / kDotT), (cnt + kDotT - 1) / kDotT),
-                       dim3(kThreads), 0, s, V, dN, (int64_t)0, H, cnt, D, C, ldc);
-    // 2) split-K partial subtraction
-    const int ks = split_k(D, cnt, n_hi);
+                       dim3(kThreads), 0, s, V, dN, (int64_t)0, H, cnt, sh.D, C, n_hi);
+    return hipGetLastError();
+}
+
+hipError_t launch_sub_f64(const double *V, const int64_t *dN, const double *C, double *part, ProjShape sh,
+                          hipStream_t s)
+{
+    const int cnt = sh.cnt;
+    if (cnt <= 0)
+        return hipSuccess;
+    const int64_t n_hi = std::max<int64_t>(sh.n_hi, 1);
+    const int ks = split_k(sh.D, cnt, n_hi);
     hipLaunchKernelGGL(k_sub_partial_f64,
-                       dim3((unsigned)((D + kSubJ - 1) / kSubJ), (cnt + kSubC - 1) / kSubC, ks), dim3(kThreads), 0, s,
-                       V, dN, C, ldc, cnt, D, ks, part);
-    // 3) reduce, subtract, norms
-    const int tiles = (int)((D + kThreads - 1) / kThreads);
-    double *normpart = part + (size_t)ks * cnt * D;
-    hipLaunchKernelGGL(k_sub_reduce_f64, dim3(tiles, cnt), dim3(kThreads), 0, s, H, part, cnt, D, ks, normpart);
+                       dim3((unsigned)((sh.D + kSubJ - 1) / kSubJ), (cnt + kSubC - 1) / kSubC, ks), dim3(kThreads), 0,
+                       s, V, dN, C, n_hi, cnt, sh.D, ks, part);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_f64(double *H, double *part, double *rho2, double *h2, ProjShape sh, hipStream_t s)
+{
+    const int cnt = sh.cnt;
+    if (cnt <= 0)
+        return hipSuccess;
+    const int64_t n_hi = std::max<int64_t>(sh.n_hi, 1);
+    const int ks = split_k(sh.D, cnt, n_hi);
+    const int tiles = (int)((sh.D + kThreads - 1) / kThreads);
+    double *normpart = part + (size_t)ks * cnt * sh.D;
+    hipLaunchKernelGGL(k_sub_reduce_f64, dim3(tiles, cnt), dim3(kThreads), 0, s, H, part, cnt, sh.D, ks, normpart);
     hipLaunchKernelGGL(k_norm_final, dim3((cnt + kThreads - 1) / kThreads), dim3(kThreads), 0, s, normpart, cnt,
                        tiles, rho2, h2);
     return hipGetLastError();

@@ -77,8 +77,14 @@ struct ProjShape {
     int64_t n_hi;   // host upper bound of N (grid sizing)
 };
 size_t proj_scratch_doubles(int64_t D, int cnt_max, int64_t cap);
-hipError_t launch_project_f64(const double *V, const int64_t *dN, double *H, double *C, double *part,
-                              double *rho2, double *h2, ProjShape sh, hipStream_t s);
+int project_split_k(int64_t D, int cnt, int64_t n_hi);
+// C[c][k] = <H_c, V_k>, ldc = n_hi
+hipError_t launch_dot_f64(const double *V, const int64_t *dN, const double *H, double *C, ProjShape sh, hipStream_t s);
+// split-K partial products of C V into `part`
+hipError_t launch_sub_f64(const double *V, const int64_t *dN, const double *C, double *part, ProjShape sh,
+                          hipStream_t s);
+// R = H - sum(part) over H, and the squared norms of R and H
+hipError_t launch_reduce_f64(double *H, double *part, double *rho2, double *h2, ProjShape sh, hipStream_t s);
 
 // Sequential acceptance of a block (one workgroup): candidate c in order, FP64.
 // mode 0: generator (accept iff ||R|| > tol*||H||); mode 1: bracket (||R|| > tol).
