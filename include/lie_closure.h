@@ -109,6 +109,9 @@ typedef struct lie_closure_stats {
     double min_accepted_residual; /* smallest FP64 residual that was accepted (bracket loop) */
     double max_rejected_residual; /* largest FP64 residual that was rejected (bracket loop) */
     double max_screen_rejected;   /* largest screened residual among screen rejects */
+    double screen_max_dependent;  /* largest first-pass residual of a survivor whose FP64 residual against the
+                                     same basis snapshot is <= tol (the audit of the screen) */
+    double screen_min_independent;/* smallest first-pass residual of a survivor whose FP64 snapshot residual is > tol */
     double run_ms;                /* wall time spent inside lie_closure_run* calls */
     int32_t precision, decide, block, early_exit;
     /* Per kernel class (lie_kernel_id), accumulated over the run: launches, and

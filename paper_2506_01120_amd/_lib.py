@@ -68,6 +68,8 @@ class Stats(ctypes.Structure):
         ("min_accepted_residual", ctypes.c_double),
         ("max_rejected_residual", ctypes.c_double),
         ("max_screen_rejected", ctypes.c_double),
+        ("screen_max_dependent", ctypes.c_double),
+        ("screen_min_independent", ctypes.c_double),
         ("run_ms", ctypes.c_double),
         ("precision", ctypes.c_int32),
         ("decide", ctypes.c_int32),

@@ -15,6 +15,7 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <type_traits>
 #include <string>
 #include <vector>
 
@@ -42,6 +43,8 @@ lie_status fail(lie_status st, const char *fmt, ...)
     } while (0)
 
 constexpr int kDefaultBlock = 256;
+// Default SCREEN reject threshold on the FP32-screened residual (paper norm).
+constexpr double kDefaultTauFp32 = 1e-4;
 constexpr int kMaxBlock = 1024;
 constexpr int kMaxD = 128;
 
@@ -134,20 +137,32 @@ struct lie_closure {
     int64_t ambient = 0;
     lie_closure_config cfg{};
     int block = 1;
+    bool screened = false;   // FP32 screening pass in front of the FP64 decisions
+    int policy = lie::POL_ALL;
+    double policy_thr = 0.0;
     // device
-    int device = 0;
+    int device = -1;
     hipStream_t stream = nullptr;
     bool own_stream = false;
-    double *V64 = nullptr;     // cap x D
-    double *H64 = nullptr;     // block x D (candidates, then residuals)
-    double *C = nullptr;       // block x cap coefficients
-    double *part = nullptr;    // split-K scratch + norm partials
-    double *rho2 = nullptr;    // block: squared residual norms (pass 2)
-    double *rho2a = nullptr;   // block: squared residual norms (pass 1)
-    double *h2 = nullptr;      // block: squared candidate norms
-    double *h2b = nullptr;     // block: pass-2 input norms (unused)
+    double *V64 = nullptr;       // cap x D, FP64 basis
+    float *Vs = nullptr;         // cap x D, FP32 rounding of V64 (screened modes)
+    double *H64 = nullptr;       // block x D, FP64 candidates, then residuals
+    float *Hs = nullptr;         // block x D, FP32 screened candidates
+    double *C = nullptr;         // block x cap FP64 coefficients
+    float *Cs = nullptr;         // block x cap FP32 coefficients
+    double *part = nullptr;      // FP64 split-K scratch + norm partials
+    double *normpart_s = nullptr;// block x tiles, screened residual partial norms
+    double *cand_a2 = nullptr;   // block: squared residual of the first pass (screen or FP64)
+    double *cand_n2 = nullptr;   // block: squared candidate norm of the first pass
+    double *rho2 = nullptr;      // block: squared FP64 residuals of survivors
+    double *h2 = nullptr;        // block: squared FP64 candidate norms of survivors
+    double *h2b = nullptr;       // block: scratch norms
+    int *surv_rows = nullptr;    // block: survivor -> candidate
+    int64_t *surv_pairs = nullptr;  // block: survivor -> pair index
+    int *slot = nullptr;         // block: candidate -> survivor or -1
+    int *nsurv = nullptr;        // 1: survivor count
     lie::DevState *st = nullptr;
-    double *scalar = nullptr;  // one double of device scratch
+    double *scalar = nullptr;    // one double of device scratch
     // host mirror
     lie::DevState hs{};
     int64_t cursor = 0;  // next pair index
@@ -164,8 +179,10 @@ struct lie_closure {
             (void)hipSetDevice(device);
         if (stream)
             (void)hipStreamSynchronize(stream);
-        for (void *p : {(void *)V64, (void *)H64, (void *)C, (void *)part, (void *)rho2, (void *)rho2a, (void *)h2,
-                        (void *)h2b, (void *)st, (void *)scalar})
+        for (void *p : {(void *)V64, (void *)Vs, (void *)H64, (void *)Hs, (void *)C, (void *)Cs, (void *)part,
+                        (void *)normpart_s, (void *)cand_a2, (void *)cand_n2, (void *)rho2, (void *)h2, (void *)h2b,
+                        (void *)surv_rows, (void *)surv_pairs, (void *)slot, (void *)nsurv, (void *)st,
+                        (void *)scalar})
             if (p)
                 (void)hipFree(p);
         if (own_stream && stream)
@@ -201,29 +218,69 @@ struct lie_closure {
         return LIE_OK;
     }
 
-    // One FP64 projection pass over H64[0..cnt) against the current basis
-    // (n_now = |V| as known to the host, an upper bound is enough for the grid).
-    // Algorithmic work per candidate: 2*N*D flops for the coefficients and
-    // 2*N*D for the subtraction; bytes: the basis streamed once per kernel,
-    // candidates read once and the residual written once.
-    lie_status project(double *rho2_out, double *h2_out, int cnt, int64_t n_now, int kid_dot, int kid_sub)
+    // One FP64 projection pass R = H - V^T V H over rows of H64 (all `cnt`, or
+    // the survivor list when `rows`/`nrows` are given).  n_lo: known |V| (for the
+    // work accounting); n_hi: an upper bound (grid, leading dimension).
+    // Algorithmic work per row: 2*N*D flops for the coefficients and 2*N*D for
+    // the subtraction; bytes: the basis streamed once per kernel, the row read
+    // once and the residual written once.
+    lie_status project(const int *rows, const int *nrows, double *rho2_out, double *h2_out, int cnt, int64_t n_lo,
+                       int64_t n_hi, int kid_dot, int kid_sub, int kid_red)
     {
-        lie::ProjShape sh{D, cnt, std::min(std::max<int64_t>(n_now, 1), cap)};
-        const double N = (double)n_now, Dd = (double)D, c = cnt, w = sizeof(double);
+        lie::ProjShape sh{D, cnt, std::min(std::max<int64_t>(n_hi, 1), cap)};
+        const double N = (double)n_lo, Dd = (double)D, c = cnt, w = sizeof(double);
         timer.begin(stream);
-        HIP_TRY(lie::launch_dot_f64(V64, &st->N, H64, C, sh, stream));
+        HIP_TRY(lie::launch_dot_f64(V64, st, H64, rows, nrows, C, sh, stream));
         timer.end(kid_dot, stream, 2.0 * N * Dd * c, (N * Dd + c * Dd + c * N) * w);
         timer.begin(stream);
-        HIP_TRY(lie::launch_sub_f64(V64, &st->N, C, part, sh, stream));
+        HIP_TRY(lie::launch_sub_f64(V64, st, C, nrows, part, sh, stream));
         timer.end(kid_sub, stream, 2.0 * N * Dd * c, (N * Dd + c * N + c * Dd) * w);
         const int ks = lie::project_split_k(D, cnt, sh.n_hi);
         timer.begin(stream);
-        HIP_TRY(lie::launch_reduce_f64(H64, part, rho2_out, h2_out, sh, stream));
-        timer.end(LIE_K_REDUCE, stream, 3.0 * c * Dd, (ks + 2.0) * c * Dd * w);
+        HIP_TRY(lie::launch_reduce_f64(H64, rows, nrows, part, st, rho2_out, h2_out, sh, stream));
+        timer.end(kid_red, stream, 3.0 * c * Dd, (ks + 2.0) * c * Dd * w);
         return LIE_OK;
     }
 
-    // Generator phase: every generator in input order, FP64.
+    lie_status classify(int cnt, int64_t p0, int pol, double thr)
+    {
+        timer.begin(stream);
+        HIP_TRY(lie::launch_classify(cand_a2, cand_n2, cnt, p0, pol, thr, st, surv_rows, surv_pairs, slot, nsurv,
+                                     stream));
+        timer.end(LIE_K_REDUCE, stream, 0, 0);
+        return LIE_OK;
+    }
+
+    lie_status accept(int cnt, int mode, bool screen_first, const int *rrow, const double *h2_surv, int kid)
+    {
+        lie::AcceptArgs a{};
+        a.V = V64;
+        a.Vs = Vs;
+        a.st = st;
+        a.H = H64;
+        a.rrow = rrow;
+        a.cand_a2 = cand_a2;
+        a.cand_n2 = cand_n2;
+        a.slot = slot;
+        a.nsurv = nsurv;
+        a.surv_cand = surv_rows;
+        a.h2 = h2_surv;
+        a.rho2 = rho2;
+        a.cnt = cnt;
+        a.D = D;
+        a.cap = cap;
+        a.ambient = ambient;
+        a.tol = tol;
+        a.mode = mode;
+        a.screened = screen_first ? 1 : 0;
+        a.early_exit = mode == 1 ? cfg.early_exit : 0;
+        timer.begin(stream);
+        HIP_TRY(lie::launch_accept_f64(a, stream));
+        timer.end(kid, stream, 0, 0);
+        return LIE_OK;
+    }
+
+    // Generator phase: every generator in input order, FP64, relative threshold.
     lie_status generators(const double *gens_host)
     {
         double *staging = nullptr;
@@ -238,43 +295,72 @@ struct lie_closure {
         Guard guard2{packed};
         HIP_TRY(hipMemcpyAsync(staging, gens_host, bytes, hipMemcpyHostToDevice, stream));
         HIP_TRY(lie::launch_pack_c128(staging, packed, n_gen, d, stream));
+        lie_status s;
         for (int g = 0; g < n_gen; ++g) {
             HIP_TRY(hipMemcpyAsync(H64, packed + (size_t)g * D, D * sizeof(double), hipMemcpyDeviceToDevice, stream));
-            lie_status s;
-            if ((s = project(rho2a, h2, 1, g, LIE_K_OTHER, LIE_K_OTHER)) != LIE_OK)
+            if ((s = project(nullptr, nullptr, cand_a2, cand_n2, 1, g, g, LIE_K_OTHER, LIE_K_OTHER, LIE_K_OTHER)) !=
+                LIE_OK)
                 return s;
-            if ((s = project(rho2, h2b, 1, g, LIE_K_OTHER, LIE_K_OTHER)) != LIE_OK)
+            if ((s = classify(1, 0, lie::POL_REL, tol)) != LIE_OK)
                 return s;
-            timer.begin(stream);
-            HIP_TRY(lie::launch_accept_f64(V64, st, H64, rho2, h2, 1, D, cap, ambient, tol, 0, 0, stream));
-            timer.end(LIE_K_OTHER, stream, 0, 0);
+            if ((s = project(surv_rows, nsurv, rho2, h2b, 1, g, g, LIE_K_OTHER, LIE_K_OTHER, LIE_K_OTHER)) != LIE_OK)
+                return s;
+            if ((s = accept(1, 0, false, surv_rows, nullptr, LIE_K_OTHER)) != LIE_OK)
+                return s;
         }
-        lie_status s = sync_state();
-        if (s != LIE_OK)
+        if ((s = sync_state()) != LIE_OK)
             return s;
         return check_state();
     }
 
-    // One block step over pair indices [cursor, cursor + cnt).
+    // FP64 block step over pair indices [cursor, cursor + cnt).
     // Bracket work per candidate: one complex d x d product (8 d^3 flops), since
     // [a,b] = ab - (ab)^H for anti-Hermitian a, b; bytes: two operands read, one result written.
-    lie_status step(int cnt, int64_t n_now)
+    lie_status step_fp64(int cnt, int64_t n_lo, int64_t n_hi)
     {
         const double c = cnt, Dd = (double)D, dd = d;
         timer.begin(stream);
-        HIP_TRY(lie::launch_comm_f64(V64, d, cursor, nullptr, cnt, H64, stream));
+        HIP_TRY(lie::launch_comm_f64(V64, d, cursor, nullptr, nullptr, cnt, st, H64, stream));
         timer.end(LIE_K_COMM, stream, 8.0 * dd * dd * dd * c, 3.0 * c * Dd * sizeof(double));
         lie_status s;
-        if ((s = project(rho2a, h2, cnt, n_now, LIE_K_DOT, LIE_K_SUB)) != LIE_OK)
+        if ((s = project(nullptr, nullptr, cand_a2, cand_n2, cnt, n_lo, n_hi, LIE_K_DOT, LIE_K_SUB, LIE_K_REDUCE)) !=
+            LIE_OK)
             return s;
-        if ((s = project(rho2, h2b, cnt, n_now, LIE_K_VERIFY, LIE_K_VERIFY)) != LIE_OK)
+        if ((s = classify(cnt, cursor, lie::POL_ABS, tol)) != LIE_OK)
+            return s;
+        // re-orthogonalisation pass for the survivors only (twice is enough)
+        if ((s = project(surv_rows, nsurv, rho2, h2b, cnt, 0, n_hi, LIE_K_VERIFY, LIE_K_VERIFY, LIE_K_VERIFY)) !=
+            LIE_OK)
+            return s;
+        return accept(cnt, 1, false, surv_rows, nullptr, LIE_K_ACCEPT);
+    }
+
+    // Screened block step: FP32 bracket and projection on MFMA, classification,
+    // then FP64 recomputation (bracket + two projection passes) of the survivors.
+    lie_status step_screen(int cnt, int64_t n_lo, int64_t n_hi)
+    {
+        const double c = cnt, Dd = (double)D, dd = d, N = (double)n_lo, w = sizeof(float);
+        const int64_t nh = std::min(std::max<int64_t>(n_hi, 1), cap);
+        timer.begin(stream);
+        HIP_TRY(lie::launch_comm_f32(Vs, d, cursor, cnt, st, Hs, cand_n2, stream));
+        timer.end(LIE_K_COMM, stream, 8.0 * dd * dd * dd * c, 3.0 * c * Dd * w);
+        timer.begin(stream);
+        HIP_TRY(lie::launch_dot_f32(Vs, st, Hs, cnt, D, nh, Cs, stream));
+        timer.end(LIE_K_DOT, stream, 2.0 * N * Dd * c, (N * Dd + c * Dd + c * N) * w);
+        timer.begin(stream);
+        HIP_TRY(lie::launch_sub_f32(Vs, st, Hs, Cs, nh, cnt, D, normpart_s, cand_a2, stream));
+        timer.end(LIE_K_SUB, stream, 2.0 * N * Dd * c, (N * Dd + c * N + c * Dd) * w);
+        lie_status s;
+        if ((s = classify(cnt, cursor, policy, policy_thr)) != LIE_OK)
             return s;
         timer.begin(stream);
-        HIP_TRY(lie::launch_accept_f64(V64, st, H64, rho2, h2, cnt, D, cap, ambient, tol, 1, cfg.early_exit, stream));
-        timer.end(LIE_K_ACCEPT, stream, 0, 0);
-        cursor += cnt;
-        ++blocks;
-        return LIE_OK;
+        HIP_TRY(lie::launch_comm_f64(V64, d, 0, surv_pairs, nsurv, cnt, st, H64, stream));
+        timer.end(LIE_K_VERIFY, stream, 0, 0);
+        if ((s = project(nullptr, nsurv, rho2, h2, cnt, 0, n_hi, LIE_K_VERIFY, LIE_K_VERIFY, LIE_K_VERIFY)) != LIE_OK)
+            return s;
+        if ((s = project(nullptr, nsurv, rho2, h2b, cnt, 0, n_hi, LIE_K_VERIFY, LIE_K_VERIFY, LIE_K_VERIFY)) != LIE_OK)
+            return s;
+        return accept(cnt, 1, policy != lie::POL_ALL, nullptr, h2, LIE_K_ACCEPT);
     }
 
     lie_status run(int64_t budget)
@@ -285,30 +371,38 @@ struct lie_closure {
             return LIE_OK;
         HIP_TRY(hipSetDevice(device));
         const auto t0 = std::chrono::steady_clock::now();
+        constexpr int kMaxQueued = 64;
         int64_t spent = 0;
+        int queued = 0;
+        int64_t n_lo = hs.N;  // |V| at the last synchronisation (a lower bound of the device value)
         lie_status s = LIE_OK;
         for (;;) {
-            if (hs.done || (cfg.early_exit && hs.N >= ambient)) {
-                done = true;
-                break;
-            }
-            const int64_t avail = lie::pairs_below(hs.N);
-            if (cursor >= avail) {
-                done = true;
-                break;
-            }
-            if (budget >= 0 && spent >= budget) {
-                s = LIE_INCOMPLETE;
-                break;
+            int64_t avail = lie::pairs_below(n_lo);
+            const bool over_budget = budget >= 0 && spent >= budget;
+            if (cursor >= avail || queued >= kMaxQueued || over_budget) {
+                if ((s = sync_state()) != LIE_OK || (s = check_state()) != LIE_OK)
+                    break;
+                queued = 0;
+                n_lo = hs.N;
+                avail = lie::pairs_below(n_lo);
+                if (hs.done || (cfg.early_exit && n_lo >= ambient) || cursor >= avail) {
+                    done = true;
+                    break;
+                }
+                if (over_budget) {
+                    s = LIE_INCOMPLETE;
+                    break;
+                }
             }
             const int cnt = (int)std::min<int64_t>(block, avail - cursor);
-            if ((s = step(cnt, hs.N)) != LIE_OK)
+            const int64_t n_hi = std::min<int64_t>(cap, n_lo + (int64_t)queued * block);
+            s = screened ? step_screen(cnt, n_lo, n_hi) : step_fp64(cnt, n_lo, n_hi);
+            if (s != LIE_OK)
                 break;
+            cursor += cnt;
             spent += cnt;
-            if ((s = sync_state()) != LIE_OK)
-                break;
-            if ((s = check_state()) != LIE_OK)
-                break;
+            ++queued;
+            ++blocks;
         }
         run_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
         if (s < 0)
@@ -439,6 +533,26 @@ lie_status lie_closure_init(lie_closure **out, const double *generators, int32_t
     h->cfg = cfg;
     h->block = cfg.block;
     h->timer.on = cfg.profile != 0;
+    h->screened = cfg.precision != LIE_PREC_FP64;
+    if (cfg.precision == LIE_PREC_BF16X3) {
+        delete h;
+        return fail(LIE_ERR_ARG, "LIE_PREC_BF16X3 is not available in this build");
+    }
+    if (h->screened) {
+        switch (cfg.decide) {
+        case LIE_DECIDE_FP64:
+            h->policy = lie::POL_ALL;
+            break;
+        case LIE_DECIDE_STRICT:
+            h->policy = lie::POL_ABS;
+            h->policy_thr = tol / 100.0;
+            break;
+        default:
+            h->policy = lie::POL_GE;
+            h->policy_thr = cfg.tau_rej > 0 ? cfg.tau_rej : kDefaultTauFp32;
+            break;
+        }
+    }
     h->cap = cfg.max_dim > 0 ? std::min<int64_t>(cfg.max_dim, h->D) : std::max<int64_t>(ambient, 1);
     h->device = -1;
 
@@ -468,30 +582,35 @@ lie_status lie_closure_init(lie_closure **out, const double *generators, int32_t
     }
     const int64_t D = h->D;
     const int b = h->block;
-    auto alloc = [&](double **p, size_t n) -> lie_status {
-        hipError_t e = hipMalloc(p, std::max<size_t>(n, 1) * sizeof(double));
+    auto alloc = [&](auto **p, size_t n) -> lie_status {
+        using T = std::remove_pointer_t<std::remove_reference_t<decltype(*p)>>;
+        hipError_t e = hipMalloc((void **)p, std::max<size_t>(n, 1) * sizeof(T));
         if (e != hipSuccess)
-            return fail(e == hipErrorOutOfMemory ? LIE_ERR_OOM : LIE_ERR_DEVICE, "hipMalloc of %zu doubles failed: %s",
+            return fail(e == hipErrorOutOfMemory ? LIE_ERR_OOM : LIE_ERR_DEVICE, "hipMalloc of %zu elements failed: %s",
                         n, hipGetErrorString(e));
         return LIE_OK;
     };
     const int bmax = std::max(b, 1);
+    const size_t capr = (size_t)round_up(h->cap, 64);
     if ((s = alloc(&h->V64, (size_t)h->cap * D)) != LIE_OK || (s = alloc(&h->H64, (size_t)bmax * D)) != LIE_OK ||
-        (s = alloc(&h->C, (size_t)bmax * round_up(h->cap, 16))) != LIE_OK ||
+        (s = alloc(&h->C, (size_t)bmax * capr)) != LIE_OK ||
         (s = alloc(&h->part, lie::proj_scratch_doubles(D, bmax, h->cap))) != LIE_OK ||
-        (s = alloc(&h->rho2, bmax)) != LIE_OK || (s = alloc(&h->rho2a, bmax)) != LIE_OK ||
-        (s = alloc(&h->h2, bmax)) != LIE_OK || (s = alloc(&h->h2b, bmax)) != LIE_OK ||
-        (s = alloc(&h->scalar, 1)) != LIE_OK)
+        (s = alloc(&h->cand_a2, bmax)) != LIE_OK || (s = alloc(&h->cand_n2, bmax)) != LIE_OK ||
+        (s = alloc(&h->rho2, bmax)) != LIE_OK || (s = alloc(&h->h2, bmax)) != LIE_OK ||
+        (s = alloc(&h->h2b, bmax)) != LIE_OK || (s = alloc(&h->surv_rows, bmax)) != LIE_OK ||
+        (s = alloc(&h->surv_pairs, bmax)) != LIE_OK || (s = alloc(&h->slot, bmax)) != LIE_OK ||
+        (s = alloc(&h->nsurv, 1)) != LIE_OK || (s = alloc(&h->scalar, 1)) != LIE_OK ||
+        (s = alloc(&h->st, 1)) != LIE_OK)
         return bail(s);
-    {
-        hipError_t e = hipMalloc(&h->st, sizeof(lie::DevState));
-        if (e != hipSuccess)
-            return bail(fail(LIE_ERR_OOM, "hipMalloc(DevState) failed: %s", hipGetErrorString(e)));
+    if (h->screened) {
+        if ((s = alloc(&h->Vs, (size_t)h->cap * D)) != LIE_OK || (s = alloc(&h->Hs, (size_t)bmax * D)) != LIE_OK ||
+            (s = alloc(&h->Cs, (size_t)bmax * capr)) != LIE_OK ||
+            (s = alloc(&h->normpart_s, (size_t)bmax * lie::sub_f32_tiles(D))) != LIE_OK)
+            return bail(s);
     }
     h->hs = lie::DevState{};
     h->hs.min_acc = INFINITY;
-    h->hs.max_rej = 0.0;
-    h->hs.max_screen_rej = 0.0;
+    h->hs.scr_min_indep = INFINITY;
     {
         hipError_t e = hipMemcpyAsync(h->st, &h->hs, sizeof h->hs, hipMemcpyHostToDevice, h->stream);
         if (e != hipSuccess)
@@ -608,6 +727,8 @@ lie_status lie_closure_stats_get(const lie_closure *h, lie_closure_stats *out)
     out->min_accepted_residual = h->hs.min_acc;
     out->max_rejected_residual = h->hs.max_rej;
     out->max_screen_rejected = h->hs.max_screen_rej;
+    out->screen_max_dependent = h->hs.scr_max_dep;
+    out->screen_min_independent = h->hs.scr_min_indep;
     out->run_ms = h->run_ms;
     out->precision = h->cfg.precision;
     out->decide = h->cfg.decide;

@@ -106,12 +106,13 @@ __device__ inline double unp_im(const double *p, int d, int i, int k)
 
 // One workgroup per candidate; both operands unpacked into LDS (d <= 64).
 __global__ void __launch_bounds__(kThreads) k_comm_f64_lds(const double *__restrict__ V, int d, int64_t p0,
-                                                           const int64_t *__restrict__ pair_list, int cnt,
-                                                           double *__restrict__ H)
+                                                           const int64_t *__restrict__ pair_list,
+                                                           const int *__restrict__ ncnt, int cnt,
+                                                           const DevState *__restrict__ st, double *__restrict__ H)
 {
     extern __shared__ double lds[];
     const int c = blockIdx.x;
-    if (c >= cnt)
+    if (c >= (ncnt ? *ncnt : cnt) || (st && (st->done | st->numeric_error | st->full)))
         return;
     const int64_t D = (int64_t)d * d;
     int64_t l, m;
@@ -160,12 +161,14 @@ __global__ void __launch_bounds__(kThreads) k_comm_f64_lds(const double *__restr
 
 // Same bracket reading operands directly from global memory (any d).
 __global__ void __launch_bounds__(kThreads) k_comm_f64_global(const double *__restrict__ V, int d, int64_t p0,
-                                                              const int64_t *__restrict__ pair_list, int cnt,
+                                                              const int64_t *__restrict__ pair_list,
+                                                              const int *__restrict__ ncnt, int cnt,
+                                                              const DevState *__restrict__ st,
                                                               double *__restrict__ H)
 {
     const int64_t D = (int64_t)d * d;
     const int c = blockIdx.y;
-    if (c >= cnt)
+    if (c >= (ncnt ? *ncnt : cnt) || (st && (st->done | st->numeric_error | st->full)))
         return;
     int64_t l, m;
     decode_pair(pair_list ? pair_list[c] : p0 + c, l, m);
@@ -199,17 +202,27 @@ __global__ void __launch_bounds__(kThreads) k_comm_f64_global(const double *__re
 
 // ------------------------------------------------------------------ projection
 //
-// C[c][k] = <H_c, V_k> for k < N (tiled: 16 basis rows x 16 candidates per workgroup).
+// Rows of a pass are either H[0..cnt) or, with a row list, H[rows[r]] for
+// r < *nrows (survivors of an earlier pass).  Coefficients and partials are
+// indexed by the pass row r.
+
+__device__ inline bool aborted(const DevState *st) { return st->done | st->numeric_error | st->full; }
+
+// C[r][k] = <H_row(r), V_k> for k < N (tiled: 16 basis rows x 16 pass rows per workgroup).
 constexpr int kDotT = 16, kDotJ = 32;
 
-__global__ void __launch_bounds__(kThreads) k_dot_f64(const double *__restrict__ V, const int64_t *__restrict__ dN,
-                                                      int64_t N_fixed, const double *__restrict__ H, int cnt,
-                                                      int64_t D, double *__restrict__ C, int64_t ldc)
+__global__ void __launch_bounds__(kThreads) k_dot_f64(const double *__restrict__ V, const DevState *__restrict__ st,
+                                                      int64_t N_fixed, const double *__restrict__ H,
+                                                      const int *__restrict__ rows, const int *__restrict__ nrows,
+                                                      int cnt, int64_t D, double *__restrict__ C, int64_t ldc)
 {
-    const int64_t N = dN ? *dN : N_fixed;
+    if (st && aborted(st))
+        return;
+    const int64_t N = st ? st->N : N_fixed;
+    const int nr = nrows ? *nrows : cnt;
     const int64_t k0 = (int64_t)blockIdx.x * kDotT;
     const int c0 = blockIdx.y * kDotT;
-    if (k0 >= N || c0 >= cnt)
+    if (k0 >= N || c0 >= nr)
         return;
     __shared__ double Vs[kDotT][kDotJ + 1];
     __shared__ double Hs[kDotT][kDotJ + 1];
@@ -220,73 +233,90 @@ __global__ void __launch_bounds__(kThreads) k_dot_f64(const double *__restrict__
             const int r = e / kDotJ, jj = e % kDotJ;
             const int64_t j = j0 + jj;
             Vs[r][jj] = (k0 + r < N && j < D) ? V[(k0 + r) * D + j] : 0.0;
-            Hs[r][jj] = (c0 + r < cnt && j < D) ? H[(int64_t)(c0 + r) * D + j] : 0.0;
+            double hv = 0.0;
+            if (c0 + r < nr && j < D) {
+                const int hr = rows ? rows[c0 + r] : c0 + r;
+                hv = H[(int64_t)hr * D + j];
+            }
+            Hs[r][jj] = hv;
         }
         __syncthreads();
         for (int jj = 0; jj < kDotJ; ++jj)
             acc += Hs[tc][jj] * Vs[tk][jj];
         __syncthreads();
     }
-    if (k0 + tk < N && c0 + tc < cnt)
+    if (k0 + tk < N && c0 + tc < nr)
         C[(int64_t)(c0 + tc) * ldc + k0 + tk] = acc;
 }
 
-// part[ks][c][j] = sum_{k in chunk ks} C[c][k] V[k][j]  (64 columns x 4 candidates per workgroup)
+// part[ks][r][j] = sum_{k in chunk ks} C[r][k] V[k][j]  (64 columns x 4 pass rows per workgroup)
 constexpr int kSubJ = 64, kSubC = 4, kSubK = 16;
 
 __global__ void __launch_bounds__(kThreads) k_sub_partial_f64(const double *__restrict__ V,
-                                                              const int64_t *__restrict__ dN,
-                                                              const double *__restrict__ C, int64_t ldc, int cnt,
-                                                              int64_t D, int ks_total, double *__restrict__ part)
+                                                              const DevState *__restrict__ st,
+                                                              const double *__restrict__ C, int64_t ldc,
+                                                              const int *__restrict__ nrows, int cnt, int64_t D,
+                                                              int ks_total, double *__restrict__ part)
 {
-    const int64_t N = *dN;
+    if (aborted(st))
+        return;
+    const int64_t N = st->N;
+    const int nr = nrows ? *nrows : cnt;
     const int64_t j0 = (int64_t)blockIdx.x * kSubJ;
     const int c0 = blockIdx.y * kSubC;
+    if (c0 >= nr)
+        return;
     const int ks = blockIdx.z;
     const int tj = threadIdx.x % kSubJ, tc = threadIdx.x / kSubJ;
     const int64_t chunk = (N + ks_total - 1) / ks_total;
     const int64_t kb = ks * chunk, ke = std::min<int64_t>(N, kb + chunk);
-    __shared__ double Vs[kSubK][kSubJ];
-    __shared__ double Cs[kSubC][kSubK];
+    __shared__ double Vt[kSubK][kSubJ];
+    __shared__ double Ct[kSubC][kSubK];
     double acc = 0.0;
     for (int64_t k0 = kb; k0 < ke; k0 += kSubK) {
         for (int e = threadIdx.x; e < kSubK * kSubJ; e += blockDim.x) {
             const int r = e / kSubJ, jj = e % kSubJ;
             const int64_t k = k0 + r, j = j0 + jj;
-            Vs[r][jj] = (k < ke && j < D) ? V[k * D + j] : 0.0;
+            Vt[r][jj] = (k < ke && j < D) ? V[k * D + j] : 0.0;
         }
         if (threadIdx.x < kSubC * kSubK) {
             const int r = threadIdx.x / kSubK, kk = threadIdx.x % kSubK;
             const int64_t k = k0 + kk;
-            Cs[r][kk] = (k < ke && c0 + r < cnt) ? C[(int64_t)(c0 + r) * ldc + k] : 0.0;
+            Ct[r][kk] = (k < ke && c0 + r < nr) ? C[(int64_t)(c0 + r) * ldc + k] : 0.0;
         }
         __syncthreads();
         for (int kk = 0; kk < kSubK; ++kk)
-            acc += Cs[tc][kk] * Vs[kk][tj];
+            acc += Ct[tc][kk] * Vt[kk][tj];
         __syncthreads();
     }
     const int c = c0 + tc;
     const int64_t j = j0 + tj;
-    if (c < cnt && j < D)
+    if (c < nr && j < D)
         part[((int64_t)ks * cnt + c) * D + j] = acc;
 }
 
-// R = H - sum_ks part, written over H; per-(candidate, tile) squared norms of R and H.
+// R = H - sum_ks part, written over H_row(r); per-(row, tile) squared norms of R and H.
 __global__ void __launch_bounds__(kThreads) k_sub_reduce_f64(double *__restrict__ H, const double *__restrict__ part,
-                                                             int cnt, int64_t D, int ks_total,
+                                                             const int *__restrict__ rows,
+                                                             const int *__restrict__ nrows, int cnt, int64_t D,
+                                                             int ks_total, const DevState *__restrict__ st,
                                                              double *__restrict__ normpart)
 {
     __shared__ double red[8];
     const int c = blockIdx.y;
+    const int nr = nrows ? *nrows : cnt;
+    if (c >= nr || aborted(st))
+        return;
+    const int hr = rows ? rows[c] : c;
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     double r2 = 0.0, h2 = 0.0;
     if (j < D) {
-        const double h = H[(int64_t)c * D + j];
+        const double h = H[(int64_t)hr * D + j];
         double s = 0.0;
         for (int ks = 0; ks < ks_total; ++ks)
             s += part[((int64_t)ks * cnt + c) * D + j];
         const double r = h - s;
-        H[(int64_t)c * D + j] = r;
+        H[(int64_t)hr * D + j] = r;
         r2 = r * r;
         h2 = h * h;
     }
@@ -298,11 +328,12 @@ __global__ void __launch_bounds__(kThreads) k_sub_reduce_f64(double *__restrict_
     }
 }
 
-__global__ void k_norm_final(const double *__restrict__ normpart, int cnt, int tiles, double *__restrict__ rho2,
-                             double *__restrict__ h2)
+__global__ void k_norm_final(const double *__restrict__ normpart, const int *__restrict__ nrows, int cnt, int tiles,
+                             const DevState *__restrict__ st, double *__restrict__ rho2, double *__restrict__ h2)
 {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= cnt)
+    const int nr = nrows ? *nrows : cnt;
+    if (c >= nr || aborted(st))
         return;
     double a = 0.0, b = 0.0;
     for (int t = 0; t < tiles; ++t) {
@@ -324,108 +355,158 @@ int split_k(int64_t D, int cnt, int64_t n_hi)
 }
 
 // ------------------------------------------------------------------ acceptance
+//
+// One workgroup.  Phase A (parallel over the block's candidates): every
+// candidate that is not a survivor is rejected and counted -- exact zeros,
+// screen rejects (screened residual) or FP64 rejects (first-pass residual).
+// Phase B (sequential over survivors, in candidate order): the survivor's
+// FP64 residual R (after the re-orthogonalisation pass against the block's
+// basis snapshot) is orthogonalised twice against the elements appended
+// earlier in this block, its norm decides, and an accepted residual is
+// normalised and appended as V[N] (and its FP32 rounding as Vs[N]).
 
-constexpr int kAccThreads = 256;
+constexpr int kAccThreads = 1024;
 constexpr int kMaxBlock = 1024;
 
-__global__ void __launch_bounds__(kAccThreads) k_accept_f64(double *__restrict__ V, DevState *__restrict__ st,
-                                                            double *__restrict__ H, const double *__restrict__ rho2,
-                                                            const double *__restrict__ h2v, int cnt, int64_t D,
-                                                            int64_t cap, int64_t ambient, double tol, int mode,
-                                                            int early_exit)
+
+
+__device__ inline void atomic_max_pos(double *addr, double v)
+{
+    // values are non-negative, so the IEEE bit pattern orders like a signed integer
+    atomicMax(reinterpret_cast<unsigned long long *>(addr), (unsigned long long)__double_as_longlong(v));
+}
+__device__ inline void atomic_min_pos(double *addr, double v)
+{
+    atomicMin(reinterpret_cast<unsigned long long *>(addr), (unsigned long long)__double_as_longlong(v));
+}
+
+__global__ void __launch_bounds__(kAccThreads) k_accept_f64(AcceptArgs a)
 {
     __shared__ double coef[kMaxBlock];
-    __shared__ double red[8];
+    __shared__ double red[16];
     __shared__ int64_t sN;
-    __shared__ int stop;
-    __shared__ int verdict;
+    __shared__ int stop, verdict, ns;
     __shared__ double rr_s;
+    __shared__ unsigned long long s_cnt[4];  // zero, screen_rej, fp64_rej, nonfinite
+    __shared__ double s_max[2];              // max rejected FP64 residual, max screen-rejected residual
+    DevState *st = a.st;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
     if (threadIdx.x == 0) {
         sN = st->N;
-        stop = st->done || st->numeric_error || st->full;
+        stop = aborted(st);
+        ns = a.nsurv ? *a.nsurv : 0;
+        for (int i = 0; i < 4; ++i)
+            s_cnt[i] = 0;
+        s_max[0] = s_max[1] = 0.0;
     }
     __syncthreads();
     if (stop)
         return;
-    const int64_t N0 = sN;
-    for (int c = 0; c < cnt; ++c) {
-        __syncthreads();  // everyone has read the previous candidate's verdict
-        const double r1 = sqrt(rho2[c]);
-        const double hn = sqrt(h2v[c]);
-        const double thr = mode == 0 ? tol * hn : tol;
-        double *R = H + (int64_t)c * D;
-        if (threadIdx.x == 0) {
-            verdict = 1;
-            if (mode == 1)
-                st->n_cand++;
-            if (!isfinite(r1) || !isfinite(hn)) {
-                st->numeric_error = 1;
-                verdict = -1;
-            } else if (hn == 0.0) {
-                if (mode == 1)
-                    st->n_zero++;
-                verdict = 0;
-            } else if (!(r1 > thr)) {
-                if (mode == 1) {
-                    st->n_fp64++;
-                    st->max_rej = fmax(st->max_rej, r1);
-                }
-                verdict = 0;
-            }
-        }
-        __syncthreads();
-        if (verdict < 0)
-            break;
-        if (verdict == 0)
+    // ---- phase A
+    for (int c = threadIdx.x; c < a.cnt; c += blockDim.x) {
+        if (a.slot[c] >= 0)
             continue;
-        // orthogonalise against the elements appended earlier in this call, twice
+        const double r = sqrt(a.cand_a2[c]), h = sqrt(a.cand_n2[c]);
+        if (!isfinite(r) || !isfinite(h)) {
+            atomicAdd(&s_cnt[3], 1ull);
+        } else if (h == 0.0) {
+            atomicAdd(&s_cnt[0], 1ull);
+        } else if (a.screened) {
+            atomicAdd(&s_cnt[1], 1ull);
+            atomic_max_pos(&s_max[1], r);
+        } else {
+            atomicAdd(&s_cnt[2], 1ull);
+            atomic_max_pos(&s_max[0], r);
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        if (a.mode == 1) {
+            st->n_cand += a.cnt;
+            st->n_zero += s_cnt[0];
+            st->n_screen_rej += s_cnt[1];
+            st->n_fp64 += s_cnt[2];
+            st->max_rej = fmax(st->max_rej, s_max[0]);
+            st->max_screen_rej = fmax(st->max_screen_rej, s_max[1]);
+        }
+        if (s_cnt[3])
+            st->numeric_error = 1;
+        stop = s_cnt[3] != 0;
+    }
+    __syncthreads();
+    if (stop)
+        return;
+    // ---- phase B
+    const int64_t N0 = sN;
+    for (int r = 0; r < ns; ++r) {
+        __syncthreads();  // everyone has read the previous survivor's verdict
+        const int c = a.surv_cand[r];
+        double *R = a.H + (int64_t)(a.rrow ? a.rrow[r] : r) * a.D;
+        const double hn = sqrt(a.h2 ? a.h2[r] : a.cand_n2[c]);
+        const double thr = a.mode == 0 ? a.tol * hn : a.tol;
+        const double rs = sqrt(a.cand_a2[c]);  // screened (or first-pass) residual, for the audit
+        if (threadIdx.x == 0 && a.mode == 1 && a.rho2) {
+            // audit against the same basis snapshot the screen used
+            const double snap = sqrt(a.rho2[r]);
+            if (snap > thr)
+                st->scr_min_indep = fmin(st->scr_min_indep, rs);
+            else
+                st->scr_max_dep = fmax(st->scr_max_dep, rs);
+        }
         for (int pass = 0; pass < 2; ++pass) {
             const int64_t A = sN - N0;
             if (A == 0)
                 break;
-            for (int64_t a = w; a < A; a += nw) {
-                const double *va = V + (N0 + a) * D;
+            for (int64_t q = w; q < A; q += nw) {
+                const double *va = a.V + (N0 + q) * a.D;
                 double s = 0.0;
-                for (int64_t j = lane; j < D; j += 64)
+                for (int64_t j = lane; j < a.D; j += 64)
                     s += va[j] * R[j];
                 s = wave_sum(s);
                 if (lane == 0)
-                    coef[a] = s;
+                    coef[q] = s;
             }
             __syncthreads();
-            for (int64_t j = threadIdx.x; j < D; j += blockDim.x) {
+            for (int64_t j = threadIdx.x; j < a.D; j += blockDim.x) {
                 double s = 0.0;
-                for (int64_t a = 0; a < A; ++a)
-                    s += coef[a] * V[(N0 + a) * D + j];
+                for (int64_t q = 0; q < A; ++q)
+                    s += coef[q] * a.V[(N0 + q) * a.D + j];
                 R[j] -= s;
             }
             __syncthreads();
         }
         double loc = 0.0;
-        for (int64_t j = threadIdx.x; j < D; j += blockDim.x)
+        for (int64_t j = threadIdx.x; j < a.D; j += blockDim.x)
             loc += R[j] * R[j];
-        loc = block_sum(loc, red);
+        loc = wave_sum(loc);
+        if (lane == 0)
+            red[w] = loc;
+        __syncthreads();
         if (threadIdx.x == 0) {
-            const double rr = sqrt(loc);
+            double t = 0.0;
+            for (int i = 0; i < nw; ++i)
+                t += red[i];
+            const double rr = sqrt(t);
             rr_s = rr;
-            if (mode == 1)
+            verdict = 1;
+            if (a.mode == 1)
                 st->n_fp64++;
-            if (!isfinite(rr)) {
+            if (!isfinite(rr) || !isfinite(hn)) {
                 st->numeric_error = 1;
                 verdict = -1;
-            } else if (!(rr > thr)) {
-                if (mode == 1)
+            } else if (hn == 0.0 || !(rr > thr)) {
+                if (a.mode == 1) {
+                    if (hn == 0.0)
+                        st->n_zero++;
                     st->max_rej = fmax(st->max_rej, rr);
+                }
                 verdict = 0;
-            } else if (mode == 1 && sN >= ambient) {
+            } else if (a.mode == 1 && sN >= a.ambient) {
                 st->numeric_error = 2;  // one more independent element than the space holds
                 verdict = -1;
-            } else if (sN >= cap) {
+            } else if (sN >= a.cap) {
                 st->full = 1;
                 verdict = -1;
-            } else {
-                verdict = 1;
             }
         }
         __syncthreads();
@@ -434,23 +515,28 @@ __global__ void __launch_bounds__(kAccThreads) k_accept_f64(double *__restrict__
         if (verdict == 0)
             continue;
         const double inv = 1.0 / rr_s;
-        double *dst = V + sN * D;
-        for (int64_t j = threadIdx.x; j < D; j += blockDim.x)
-            dst[j] = R[j] * inv;
+        double *dst = a.V + sN * a.D;
+        float *dsts = a.Vs ? a.Vs + sN * a.D : nullptr;
+        for (int64_t j = threadIdx.x; j < a.D; j += blockDim.x) {
+            const double v = R[j] * inv;
+            dst[j] = v;
+            if (dsts)
+                dsts[j] = (float)v;
+        }
         __syncthreads();
         if (threadIdx.x == 0) {
             sN++;
-            if (mode == 1) {
+            if (a.mode == 1) {
                 st->n_acc++;
                 st->min_acc = fmin(st->min_acc, rr_s);
             } else {
                 st->n_gen_acc++;
             }
-            if (early_exit && sN >= ambient)
+            if (a.early_exit && sN >= a.ambient)
                 st->done = 1;
         }
         __syncthreads();
-        if (early_exit && sN >= ambient)
+        if (a.early_exit && sN >= a.ambient)
             break;
     }
     if (threadIdx.x == 0)
@@ -508,13 +594,14 @@ hipError_t launch_unpack_c128(const double *src, double *dst, int64_t count, int
     return hipGetLastError();
 }
 
-hipError_t launch_comm_f64(const double *V, int d, int64_t p0, const int64_t *pair_list, int cnt, double *H,
-                           hipStream_t s)
+hipError_t launch_comm_f64(const double *V, int d, int64_t p0, const int64_t *pair_list, const int *ncnt, int cnt,
+                           const DevState *st, double *H, hipStream_t s)
 {
     if (cnt <= 0)
         return hipSuccess;
     const size_t lds = (size_t)4 * d * (d + 1) * sizeof(double);
     static int max_lds = -1;
+    static size_t granted = 65536;
     if (max_lds < 0) {
         int dev = 0, v = 65536;
         if (hipGetDevice(&dev) == hipSuccess &&
@@ -522,16 +609,21 @@ hipError_t launch_comm_f64(const double *V, int d, int64_t p0, const int64_t *pa
             max_lds = v;
         else
             max_lds = 65536;
-        if (max_lds > 65536)
-            (void)hipFuncSetAttribute((const void *)k_comm_f64_lds, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                      max_lds);
     }
-    if (d <= 64 && lds <= (size_t)max_lds) {
-        hipLaunchKernelGGL(k_comm_f64_lds, dim3(cnt), dim3(kThreads), lds, s, V, d, p0, pair_list, cnt, H);
+    if (lds > granted && lds + 1024 <= (size_t)max_lds) {
+        // raise the dynamic LDS limit of this kernel to what this launch needs
+        if (hipFuncSetAttribute((const void *)k_comm_f64_lds, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) ==
+            hipSuccess)
+            granted = lds;
+        else
+            (void)hipGetLastError();  // clear the failed request; the fallback kernel is used
+    }
+    if (d <= 64 && lds <= granted) {
+        hipLaunchKernelGGL(k_comm_f64_lds, dim3(cnt), dim3(kThreads), lds, s, V, d, p0, pair_list, ncnt, cnt, st, H);
     } else {
         const int64_t D = (int64_t)d * d;
         hipLaunchKernelGGL(k_comm_f64_global, dim3((unsigned)((D + kThreads - 1) / kThreads), cnt), dim3(kThreads), 0,
-                           s, V, d, p0, pair_list, cnt, H);
+                           s, V, d, p0, pair_list, ncnt, cnt, st, H);
     }
     return hipGetLastError();
 }
@@ -549,19 +641,20 @@ size_t proj_scratch_doubles(int64_t D, int cnt_max, int64_t cap)
 
 int project_split_k(int64_t D, int cnt, int64_t n_hi) { return split_k(D, cnt, std::max<int64_t>(n_hi, 1)); }
 
-hipError_t launch_dot_f64(const double *V, const int64_t *dN, const double *H, double *C, ProjShape sh, hipStream_t s)
+hipError_t launch_dot_f64(const double *V, const DevState *st, const double *H, const int *rows, const int *nrows,
+                          double *C, ProjShape sh, hipStream_t s)
 {
     const int cnt = sh.cnt;
     if (cnt <= 0)
         return hipSuccess;
     const int64_t n_hi = std::max<int64_t>(sh.n_hi, 1);
     hipLaunchKernelGGL(k_dot_f64, dim3((unsigned)((n_hi + kDotT - 1) / kDotT), (cnt + kDotT - 1) / kDotT),
-                       dim3(kThreads), 0, s, V, dN, (int64_t)0, H, cnt, sh.D, C, n_hi);
+                       dim3(kThreads), 0, s, V, st, (int64_t)0, H, rows, nrows, cnt, sh.D, C, n_hi);
     return hipGetLastError();
 }
 
-hipError_t launch_sub_f64(const double *V, const int64_t *dN, const double *C, double *part, ProjShape sh,
-                          hipStream_t s)
+hipError_t launch_sub_f64(const double *V, const DevState *st, const double *C, const int *nrows, double *part,
+                          ProjShape sh, hipStream_t s)
 {
     const int cnt = sh.cnt;
     if (cnt <= 0)
@@ -570,11 +663,12 @@ hipError_t launch_sub_f64(const double *V, const int64_t *dN, const double *C, d
     const int ks = split_k(sh.D, cnt, n_hi);
     hipLaunchKernelGGL(k_sub_partial_f64,
                        dim3((unsigned)((sh.D + kSubJ - 1) / kSubJ), (cnt + kSubC - 1) / kSubC, ks), dim3(kThreads), 0,
-                       s, V, dN, C, n_hi, cnt, sh.D, ks, part);
+                       s, V, st, C, n_hi, nrows, cnt, sh.D, ks, part);
     return hipGetLastError();
 }
 
-hipError_t launch_reduce_f64(double *H, double *part, double *rho2, double *h2, ProjShape sh, hipStream_t s)
+hipError_t launch_reduce_f64(double *H, const int *rows, const int *nrows, double *part, const DevState *st,
+                             double *rho2, double *h2, ProjShape sh, hipStream_t s)
 {
     const int cnt = sh.cnt;
     if (cnt <= 0)
@@ -583,22 +677,20 @@ hipError_t launch_reduce_f64(double *H, double *part, double *rho2, double *h2, 
     const int ks = split_k(sh.D, cnt, n_hi);
     const int tiles = (int)((sh.D + kThreads - 1) / kThreads);
     double *normpart = part + (size_t)ks * cnt * sh.D;
-    hipLaunchKernelGGL(k_sub_reduce_f64, dim3(tiles, cnt), dim3(kThreads), 0, s, H, part, cnt, sh.D, ks, normpart);
-    hipLaunchKernelGGL(k_norm_final, dim3((cnt + kThreads - 1) / kThreads), dim3(kThreads), 0, s, normpart, cnt,
-                       tiles, rho2, h2);
+    hipLaunchKernelGGL(k_sub_reduce_f64, dim3(tiles, cnt), dim3(kThreads), 0, s, H, part, rows, nrows, cnt, sh.D, ks,
+                       st, normpart);
+    hipLaunchKernelGGL(k_norm_final, dim3((cnt + kThreads - 1) / kThreads), dim3(kThreads), 0, s, normpart, nrows, cnt,
+                       tiles, st, rho2, h2);
     return hipGetLastError();
 }
 
-hipError_t launch_accept_f64(double *V, DevState *st, double *H, const double *rho2, const double *h2, int cnt,
-                             int64_t D, int64_t cap, int64_t ambient, double tol, int mode, int early_exit,
-                             hipStream_t s)
+hipError_t launch_accept_f64(const AcceptArgs &args, hipStream_t s)
 {
-    if (cnt <= 0)
+    if (args.cnt <= 0)
         return hipSuccess;
-    if (cnt > kMaxBlock)
+    if (args.cnt > kMaxBlock)
         return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_accept_f64, dim3(1), dim3(kAccThreads), 0, s, V, st, H, rho2, h2, cnt, D, cap, ambient, tol,
-                       mode, early_exit);
+    hipLaunchKernelGGL(k_accept_f64, dim3(1), dim3(kAccThreads), 0, s, args);
     return hipGetLastError();
 }
 
@@ -612,8 +704,8 @@ hipError_t launch_orth_loss(const double *V, int64_t n, int64_t D, double *work,
     for (int64_t c0 = 0; c0 < n; c0 += 65535 * kDotT) {
         const int64_t rows = std::min<int64_t>(n - c0, (int64_t)65535 * kDotT);
         hipLaunchKernelGGL(k_dot_f64, dim3((unsigned)((n + kDotT - 1) / kDotT), (unsigned)((rows + kDotT - 1) / kDotT)),
-                           dim3(kThreads), 0, s, V, (const int64_t *)nullptr, n, V + c0 * D, (int)rows, D,
-                           G + c0 * n, n);
+                           dim3(kThreads), 0, s, V, (const DevState *)nullptr, n, V + c0 * D, (const int *)nullptr,
+                           (const int *)nullptr, (int)rows, D, G + c0 * n, n);
     }
     const int parts = 256;
     double *part = work + n * n;

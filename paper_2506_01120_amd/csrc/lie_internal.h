@@ -31,6 +31,8 @@ struct DevState {
     double min_acc;          // smallest accepted FP64 residual (bracket loop)
     double max_rej;          // largest rejected FP64 residual (bracket loop)
     double max_screen_rej;   // largest screened residual among screen rejects
+    double scr_max_dep;      // largest screened residual of a candidate found dependent in FP64
+    double scr_min_indep;    // smallest screened residual of a candidate found independent in FP64
     int32_t numeric_error;   // 1: non-finite residual; 2: |V| would pass the ambient bound
     int32_t full;            // 1: an append was refused because the capacity is reached
     int32_t done;            // 1: early-exit bound reached
@@ -52,11 +54,21 @@ __host__ __device__ inline void decode_pair(int64_t p, int64_t &l, int64_t &m)
 
 inline int64_t pairs_below(int64_t n) { return n * (n - 1) / 2; }
 
+// Candidate policies of the classification kernel (a2: squared residual, n2: squared norm).
+enum Policy {
+    POL_ALL = 0,  // every candidate survives
+    POL_ABS = 1,  // survive iff n2 > 0 and sqrt(a2) > thr
+    POL_REL = 2,  // survive iff n2 > 0 and sqrt(a2) > thr * sqrt(n2)
+    POL_GE = 3    // survive iff n2 > 0 and sqrt(a2) >= thr
+};
+
 // ------------------------------------------------------------- FP64 kernels
-// All pointers are device pointers.  `dN` points at DevState::N; kernels read
-// the current basis size from the device so that a host loop can enqueue
-// several block steps without a round trip.  Grids are sized on the host for
-// an upper bound `n_hi` of N; workgroups beyond N exit.
+// All pointers are device pointers.  Kernels of a block step read the current
+// basis size and the abort flags (done / numeric_error / full) from the
+// DevState, so a host loop can enqueue several block steps without a round
+// trip.  Grids are sized on the host for an upper bound `n_hi` of N;
+// workgroups beyond N exit.  Row lists (`rows`, `nrows`) restrict a pass to
+// the survivors of an earlier pass.
 
 // Pack complex128 operators (interleaved re,im; d x d row-major) into the packed layout.
 hipError_t launch_pack_c128(const double *src, double *dst, int count, int d, hipStream_t s);
@@ -64,37 +76,69 @@ hipError_t launch_pack_c128(const double *src, double *dst, int count, int d, hi
 hipError_t launch_unpack_c128(const double *src, double *dst, int64_t count, int d, hipStream_t s);
 
 // H[c] = pack([V_l, V_m]) for the pair of index p0 + c (pair_list == nullptr)
-// or pair_list[c], c < cnt.  FP64.
-hipError_t launch_comm_f64(const double *V, int d, int64_t p0, const int64_t *pair_list, int cnt, double *H,
-                           hipStream_t s);
+// or pair_list[c], for c < cnt (or c < *ncnt when ncnt is given).  FP64.
+hipError_t launch_comm_f64(const double *V, int d, int64_t p0, const int64_t *pair_list, const int *ncnt, int cnt,
+                           const DevState *st, double *H, hipStream_t s);
 
-// Projection pass on rows H[0..cnt):  C = H V^T (N columns), R = H - C V written over H,
-// and per-row squared norms of R and of the input H into rho2[c], h2[c] (FP64).
-// `part` is split-K scratch of at least proj_scratch_doubles(...) doubles.
 struct ProjShape {
     int64_t D;      // elements per operator (d*d)
-    int cnt;        // rows in this call
-    int64_t n_hi;   // host upper bound of N (grid sizing)
+    int cnt;        // rows in this call (upper bound when a row count lives on the device)
+    int64_t n_hi;   // host upper bound of N (grid sizing, coefficient leading dimension)
 };
 size_t proj_scratch_doubles(int64_t D, int cnt_max, int64_t cap);
 int project_split_k(int64_t D, int cnt, int64_t n_hi);
-// C[c][k] = <H_c, V_k>, ldc = n_hi
-hipError_t launch_dot_f64(const double *V, const int64_t *dN, const double *H, double *C, ProjShape sh, hipStream_t s);
+// C[r][k] = <H_row(r), V_k>, leading dimension n_hi
+hipError_t launch_dot_f64(const double *V, const DevState *st, const double *H, const int *rows, const int *nrows,
+                          double *C, ProjShape sh, hipStream_t s);
 // split-K partial products of C V into `part`
-hipError_t launch_sub_f64(const double *V, const int64_t *dN, const double *C, double *part, ProjShape sh,
-                          hipStream_t s);
-// R = H - sum(part) over H, and the squared norms of R and H
-hipError_t launch_reduce_f64(double *H, double *part, double *rho2, double *h2, ProjShape sh, hipStream_t s);
+hipError_t launch_sub_f64(const double *V, const DevState *st, const double *C, const int *nrows, double *part,
+                          ProjShape sh, hipStream_t s);
+// R = H - sum(part) written over H_row(r); squared norms of R and of the input into rho2[r], h2[r]
+hipError_t launch_reduce_f64(double *H, const int *rows, const int *nrows, double *part, const DevState *st,
+                             double *rho2, double *h2, ProjShape sh, hipStream_t s);
 
-// Sequential acceptance of a block (one workgroup): candidate c in order, FP64.
-// mode 0: generator (accept iff ||R|| > tol*||H||); mode 1: bracket (||R|| > tol).
-// Survivors are orthogonalised twice against elements accepted earlier in the
-// same call, normalised and appended at V[N]; N and the counters advance.
-hipError_t launch_accept_f64(double *V, DevState *st, double *H, const double *rho2, const double *h2, int cnt,
-                             int64_t D, int64_t cap, int64_t ambient, double tol, int mode, int early_exit,
-                             hipStream_t s);
+// Acceptance of one block (one workgroup): see kernels_f64.hip.
+struct AcceptArgs {
+    double *V;
+    float *Vs;               // FP32 shadow basis (may be null)
+    DevState *st;
+    double *H;               // FP64 residual rows of survivors
+    const int *rrow;         // survivor r -> H row (null: r)
+    const double *cand_a2;   // per candidate: screened (or FP64 first-pass) squared residual
+    const double *cand_n2;   // per candidate: squared candidate norm (screen or FP64)
+    const int *slot;         // per candidate: survivor index or -1
+    const int *nsurv;
+    const int *surv_cand;    // survivor r -> candidate c
+    const double *h2;        // per survivor: squared FP64 candidate norm (null: cand_n2 of its candidate)
+    const double *rho2;      // per survivor: squared FP64 residual against the block's basis snapshot
+    int cnt;
+    int64_t D, cap, ambient;
+    double tol;
+    int mode;                // 0: generator (relative threshold), 1: bracket
+    int screened;            // 1: non-survivors were rejected by the screen
+    int early_exit;
+};
+hipError_t launch_accept_f64(const AcceptArgs &args, hipStream_t s);
 
-// G = V V^T (n x n) then ||G - I||_F into *out (device), using `work` of n*n doubles.
+// G = V V^T (n x n) then ||G - I||_F into *out (device), using `work` of n*n + 256 doubles.
 hipError_t launch_orth_loss(const double *V, int64_t n, int64_t D, double *work, double *out, hipStream_t s);
+
+// ------------------------------------------------------------- FP32 screening kernels (kernels_screen.hip)
+// Hs[c] = fp32 packed [Vs_l, Vs_m] for pair p0 + c, hs2[c] = ||Hs[c]||^2.
+hipError_t launch_comm_f32(const float *Vs, int d, int64_t p0, int cnt, const DevState *st, float *Hs, double *hs2,
+                           hipStream_t s);
+// C[c][k] = <Hs_c, Vs_k> (FP32 MFMA), leading dimension n_hi.
+hipError_t launch_dot_f32(const float *Vs, const DevState *st, const float *Hs, int cnt, int64_t D, int64_t n_hi,
+                          float *C, hipStream_t s);
+// rs2[c] = ||Hs_c - sum_k C[c][k] Vs_k||^2 (FP32 MFMA, FP64 tile sums); normpart holds cnt * sub_f32_tiles(D).
+int sub_f32_tiles(int64_t D);
+hipError_t launch_sub_f32(const float *Vs, const DevState *st, const float *Hs, const float *C, int64_t n_hi, int cnt,
+                          int64_t D, double *normpart, double *rs2, hipStream_t s);
+// Survivor compaction under a policy (cnt <= 1024).
+hipError_t launch_classify(const double *a2, const double *n2, int cnt, int64_t p0, int policy, double thr,
+                           const DevState *st, int *rows, int64_t *pairs, int *slot, int *nsurv, hipStream_t s);
+// Vs[from..N) = fp32(V64[from..N)), N read from the device state; to_hi bounds the grid.
+hipError_t launch_shadow_f32(const double *V64, float *Vs, int64_t D, int64_t from, int64_t to_hi, const DevState *st,
+                             hipStream_t s);
 
 }  // namespace lie

@@ -139,3 +139,68 @@ def test_basis_device_matches_host():
         assert dev.device.type == "cuda"
         np.testing.assert_array_equal(dev.cpu().numpy(), host)
         torch.cuda.synchronize()
+
+
+# ------------------------------------------------------------------ FP32-screened path
+#
+# The screen (FP32 bracket + projection on MFMA) only filters candidates; every
+# decision that keeps a candidate, the appended vector and its normalisation
+# are FP64.  Bar: dimensions identical to the reference, span distance
+# <= 1e-5 (mixed-precision bar), orthogonality <= 1e-10.
+SPAN_TOL_MIXED = 1e-5
+
+SCREEN_MODES = [("fp32", "fp64"), ("fp32", "strict"), ("fp32", "screen")]
+
+
+_REF_CACHE = {}
+
+
+def reference(gens, tol, early_exit):
+    key = (gens.tobytes(), gens.shape, tol, early_exit)
+    if key not in _REF_CACHE:
+        _REF_CACHE[key] = O.closure(gens, tol, early_exit=early_exit)
+    return _REF_CACHE[key]
+
+
+def assert_parity_mixed(gens, tol, *, early_exit=False, expected=None, **cfg):
+    ref = reference(gens, tol, early_exit)
+    dim, v, st, orth = gpu_closure(gens, tol, early_exit=early_exit, **cfg)
+    assert dim == ref.dim, (dim, ref.dim, st)
+    if expected is not None:
+        assert dim == expected
+    assert pins.span_distance(v, ref.basis) <= SPAN_TOL_MIXED
+    assert orth <= ORTH_TOL_FP64
+    assert st["done"] == 1
+    if not early_exit:
+        assert st["candidates"] == ref.candidates
+    return dim, v, st
+
+
+@pytest.mark.parametrize("precision,decide", SCREEN_MODES)
+@pytest.mark.parametrize("case", ["ising3", "ising5", "pair8", "xxyy5", "pauli4x6", "pair5_ragged"])
+def test_screened_small(case, precision, decide):
+    gens, tol, block = {
+        "ising3": (W.ising(3), 1e-10, 7),
+        "ising5": (W.ising(5), 1e-10, 64),
+        "pair8": (W.rand_pair(8, seed=21), 1e-10, 256),
+        "xxyy5": (W.xxyy(5), 1e-10, 32),
+        "pauli4x6": (W.pauli_set(4, 6, 11), 1e-10, 100),
+        "pair5_ragged": (W.rand_pair(5, seed=22), 1e-10, 33),
+    }[case]
+    assert_parity_mixed(gens, tol, precision=precision, decide=decide, block=block)
+
+
+@pytest.mark.parametrize("precision,decide", SCREEN_MODES)
+def test_screened_su32_early_exit(precision, decide):
+    """d=32 random pair (seed 3), tol 1e-8, early exit at d^2-1 = 1023, against the reference."""
+    assert_parity_mixed(W.rand_pair(32, seed=3), 1e-8, early_exit=True, expected=1023, precision=precision,
+                        decide=decide, block=256)
+
+
+def test_screen_audit_margin_su16():
+    """FP64-decided run with the FP32 screen recorded: every dependent candidate screens far below
+    every independent one, so the SCREEN threshold separates them."""
+    dim, v, st, _ = gpu_closure(W.rand_pair(16, seed=2), 1e-10, precision="fp32", decide="fp64", block=256)
+    assert dim == 255
+    print("screen margin:", st["screen_max_dependent"], st["screen_min_independent"])
+    assert st["screen_max_dependent"] < 1e-4 < st["screen_min_independent"]
