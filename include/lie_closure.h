@@ -70,7 +70,8 @@ typedef struct lie_closure_config {
     uint32_t struct_size;  /* must be sizeof(lie_closure_config) */
     int32_t precision;     /* lie_precision, default LIE_PREC_FP64 */
     int32_t decide;        /* lie_decide, default LIE_DECIDE_SCREEN for screened precisions */
-    int32_t block;         /* candidates per block: 1 = plain one-at-a-time form, 0 = default */
+    int32_t block;         /* candidates per block: 1 = plain one-at-a-time form, 2..1024 fixed, 0 = adaptive
+                              (small blocks while most candidates are accepted, large blocks after) */
     int32_t early_exit;    /* 1: stop once |V| equals the ambient bound (exact; d^2-1 for traceless inputs) */
     int32_t device;        /* HIP device ordinal; -1 = the calling thread's current device */
     double tau_rej;        /* SCREEN reject threshold on the screened residual; 0 = precision default */
@@ -113,7 +114,9 @@ typedef struct lie_closure_stats {
                                      same basis snapshot is <= tol (the audit of the screen) */
     double screen_min_independent;/* smallest first-pass residual of a survivor whose FP64 snapshot residual is > tol */
     double run_ms;                /* wall time spent inside lie_closure_run* calls */
-    int32_t precision, decide, block, early_exit;
+    int32_t precision, decide;
+    int32_t block;                /* fixed block size, or -(saturated size) when adaptive */
+    int32_t early_exit;
     /* Per kernel class (lie_kernel_id), accumulated over the run: launches, and
      * the algorithmic floating-point operations and bytes those launches must
      * perform (formulas in the engine source).  kernel_ms is the summed

@@ -42,7 +42,8 @@ lie_status fail(lie_status st, const char *fmt, ...)
                         #expr, hipGetErrorString(e_), __FILE__, __LINE__);                                \
     } while (0)
 
-constexpr int kDefaultBlock = 256;
+// Blocks of at most this many rows use the split-K GEMV projection; larger ones the matrix-core GEMMs.
+constexpr int kGemvRows = 16;
 // Default SCREEN reject threshold on the FP32-screened residual (paper norm).
 constexpr double kDefaultTauFp32 = 1e-4;
 constexpr int kMaxBlock = 1024;
@@ -136,7 +137,10 @@ struct lie_closure {
     int64_t cap = 0;
     int64_t ambient = 0;
     lie_closure_config cfg{};
-    int block = 1;
+    int block = 1;           // fixed block size, or 0: adaptive (growth / saturated sizes below)
+    int block_growth = 32;   // adaptive: block size while most candidates are accepted
+    int block_sat = 1024;    // adaptive: block size once acceptances are rare
+    int bmax = 1;            // allocation bound of any block
     bool screened = false;   // FP32 screening pass in front of the FP64 decisions
     int policy = lie::POL_ALL;
     double policy_thr = 0.0;
@@ -229,6 +233,19 @@ struct lie_closure {
     {
         lie::ProjShape sh{D, cnt, std::min(std::max<int64_t>(n_hi, 1), cap)};
         const double N = (double)n_lo, Dd = (double)D, c = cnt, w = sizeof(double);
+        if (cnt > kGemvRows) {
+            // matrix-core path: coefficients, then residual with fused norms, then the norm sums
+            timer.begin(stream);
+            HIP_TRY(lie::launch_gemm_dot_f64(V64, st, H64, rows, nrows, cnt, D, sh.n_hi, C, stream));
+            timer.end(kid_dot, stream, 2.0 * N * Dd * c, (N * Dd + c * Dd + c * N) * w);
+            timer.begin(stream);
+            HIP_TRY(lie::launch_gemm_sub_f64(V64, st, H64, rows, nrows, C, sh.n_hi, cnt, D, part, stream));
+            timer.end(kid_sub, stream, 2.0 * N * Dd * c, (N * Dd + c * N + 2.0 * c * Dd) * w);
+            timer.begin(stream);
+            HIP_TRY(lie::launch_norm_final(part, nrows, cnt, lie::gemm_sub_tiles_f64(D), st, rho2_out, h2_out, stream));
+            timer.end(kid_red, stream, 0, 0);
+            return LIE_OK;
+        }
         timer.begin(stream);
         HIP_TRY(lie::launch_dot_f64(V64, st, H64, rows, nrows, C, sh, stream));
         timer.end(kid_dot, stream, 2.0 * N * Dd * c, (N * Dd + c * Dd + c * N) * w);
@@ -344,12 +361,17 @@ struct lie_closure {
         timer.begin(stream);
         HIP_TRY(lie::launch_comm_f32(Vs, d, cursor, cnt, st, Hs, cand_n2, stream));
         timer.end(LIE_K_COMM, stream, 8.0 * dd * dd * dd * c, 3.0 * c * Dd * w);
+        const int tile_dot = lie::gemm_tile_f32(cnt, nh), tile_sub = lie::gemm_tile_f32(cnt, D);
         timer.begin(stream);
-        HIP_TRY(lie::launch_dot_f32(Vs, st, Hs, cnt, D, nh, Cs, stream));
+        HIP_TRY(lie::launch_gemm_dot_f32(Vs, st, Hs, cnt, D, nh, Cs, tile_dot, stream));
         timer.end(LIE_K_DOT, stream, 2.0 * N * Dd * c, (N * Dd + c * Dd + c * N) * w);
         timer.begin(stream);
-        HIP_TRY(lie::launch_sub_f32(Vs, st, Hs, Cs, nh, cnt, D, normpart_s, cand_a2, stream));
+        HIP_TRY(lie::launch_gemm_sub_f32(Vs, st, Hs, Cs, nh, cnt, D, normpart_s, tile_sub, stream));
         timer.end(LIE_K_SUB, stream, 2.0 * N * Dd * c, (N * Dd + c * N + c * Dd) * w);
+        timer.begin(stream);
+        HIP_TRY(lie::launch_norm_final(normpart_s, nullptr, cnt, lie::gemm_sub_tiles_f32(D, tile_sub), st, cand_a2,
+                                       nullptr, stream));
+        timer.end(LIE_K_REDUCE, stream, 0, 0);
         lie_status s;
         if ((s = classify(cnt, cursor, policy, policy_thr)) != LIE_OK)
             return s;
@@ -374,7 +396,10 @@ struct lie_closure {
         constexpr int kMaxQueued = 64;
         int64_t spent = 0;
         int queued = 0;
+        int64_t queued_rows = 0;  // candidates enqueued since the last synchronisation
         int64_t n_lo = hs.N;  // |V| at the last synchronisation (a lower bound of the device value)
+        int cur = block > 0 ? block : block_growth;
+        int64_t last_cand = hs.n_cand, last_acc = hs.n_acc;
         lie_status s = LIE_OK;
         for (;;) {
             int64_t avail = lie::pairs_below(n_lo);
@@ -383,7 +408,16 @@ struct lie_closure {
                 if ((s = sync_state()) != LIE_OK || (s = check_state()) != LIE_OK)
                     break;
                 queued = 0;
+                queued_rows = 0;
                 n_lo = hs.N;
+                if (block == 0) {
+                    // adaptive block: small while candidates are mostly accepted, large otherwise
+                    const int64_t dc = hs.n_cand - last_cand, da = hs.n_acc - last_acc;
+                    if (dc > 0)
+                        cur = 8 * da > dc ? block_growth : block_sat;
+                    last_cand = hs.n_cand;
+                    last_acc = hs.n_acc;
+                }
                 avail = lie::pairs_below(n_lo);
                 if (hs.done || (cfg.early_exit && n_lo >= ambient) || cursor >= avail) {
                     done = true;
@@ -394,14 +428,15 @@ struct lie_closure {
                     break;
                 }
             }
-            const int cnt = (int)std::min<int64_t>(block, avail - cursor);
-            const int64_t n_hi = std::min<int64_t>(cap, n_lo + (int64_t)queued * block);
+            const int cnt = (int)std::min<int64_t>(cur, avail - cursor);
+            const int64_t n_hi = std::min<int64_t>(cap, n_lo + queued_rows);
             s = screened ? step_screen(cnt, n_lo, n_hi) : step_fp64(cnt, n_lo, n_hi);
             if (s != LIE_OK)
                 break;
             cursor += cnt;
             spent += cnt;
             ++queued;
+            queued_rows += cnt;
             ++blocks;
         }
         run_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
@@ -481,8 +516,6 @@ lie_status resolve_config(const lie_closure_config *in, lie_closure_config *out)
     for (int r : out->reserved)
         if (r != 0)
             return fail(LIE_ERR_ARG, "config.reserved must be zero");
-    if (out->block == 0)
-        out->block = kDefaultBlock;
     return LIE_OK;
 }
 
@@ -532,6 +565,13 @@ lie_status lie_closure_init(lie_closure **out, const double *generators, int32_t
     h->ambient = ambient;
     h->cfg = cfg;
     h->block = cfg.block;
+    if (h->block == 0) {
+        // adaptive sizes: the growth size bounds the sequential in-block work
+        // (about block^2/2 * d^2 * 32 bytes through one compute unit per block)
+        const int64_t D0 = (int64_t)d * d;
+        h->block_growth = D0 <= 256 ? 64 : (D0 <= 1024 ? 32 : 16);
+        h->block_sat = 1024;
+    }
     h->timer.on = cfg.profile != 0;
     h->screened = cfg.precision != LIE_PREC_FP64;
     if (cfg.precision == LIE_PREC_BF16X3) {
@@ -581,7 +621,8 @@ lie_status lie_closure_init(lie_closure **out, const double *generators, int32_t
         h->own_stream = true;
     }
     const int64_t D = h->D;
-    const int b = h->block;
+    const int b = h->block > 0 ? h->block : std::max(h->block_growth, h->block_sat);
+    h->bmax = b;
     auto alloc = [&](auto **p, size_t n) -> lie_status {
         using T = std::remove_pointer_t<std::remove_reference_t<decltype(*p)>>;
         hipError_t e = hipMalloc((void **)p, std::max<size_t>(n, 1) * sizeof(T));
@@ -591,10 +632,11 @@ lie_status lie_closure_init(lie_closure **out, const double *generators, int32_t
         return LIE_OK;
     };
     const int bmax = std::max(b, 1);
-    const size_t capr = (size_t)round_up(h->cap, 64);
+    const size_t capr = (size_t)lie::coef_ld(h->cap);
     if ((s = alloc(&h->V64, (size_t)h->cap * D)) != LIE_OK || (s = alloc(&h->H64, (size_t)bmax * D)) != LIE_OK ||
         (s = alloc(&h->C, (size_t)bmax * capr)) != LIE_OK ||
-        (s = alloc(&h->part, lie::proj_scratch_doubles(D, bmax, h->cap))) != LIE_OK ||
+        (s = alloc(&h->part, std::max(lie::proj_scratch_doubles(D, std::min(bmax, 64), h->cap),
+                                       (size_t)bmax * lie::gemm_sub_tiles_f64(D) * 2))) != LIE_OK ||
         (s = alloc(&h->cand_a2, bmax)) != LIE_OK || (s = alloc(&h->cand_n2, bmax)) != LIE_OK ||
         (s = alloc(&h->rho2, bmax)) != LIE_OK || (s = alloc(&h->h2, bmax)) != LIE_OK ||
         (s = alloc(&h->h2b, bmax)) != LIE_OK || (s = alloc(&h->surv_rows, bmax)) != LIE_OK ||
@@ -605,7 +647,7 @@ lie_status lie_closure_init(lie_closure **out, const double *generators, int32_t
     if (h->screened) {
         if ((s = alloc(&h->Vs, (size_t)h->cap * D)) != LIE_OK || (s = alloc(&h->Hs, (size_t)bmax * D)) != LIE_OK ||
             (s = alloc(&h->Cs, (size_t)bmax * capr)) != LIE_OK ||
-            (s = alloc(&h->normpart_s, (size_t)bmax * lie::sub_f32_tiles(D))) != LIE_OK)
+            (s = alloc(&h->normpart_s, (size_t)bmax * lie::gemm_sub_tiles_f32(D, 1) * 2)) != LIE_OK)
             return bail(s);
     }
     h->hs = lie::DevState{};
@@ -732,7 +774,7 @@ lie_status lie_closure_stats_get(const lie_closure *h, lie_closure_stats *out)
     out->run_ms = h->run_ms;
     out->precision = h->cfg.precision;
     out->decide = h->cfg.decide;
-    out->block = h->block;
+    out->block = h->block > 0 ? h->block : -h->block_sat;
     out->early_exit = h->cfg.early_exit;
     for (int k = 0; k < LIE_K_COUNT; ++k) {
         out->kernel_launches[k] = h->timer.n[k];

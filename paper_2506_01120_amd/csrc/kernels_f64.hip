@@ -467,11 +467,19 @@ __global__ void __launch_bounds__(kAccThreads) k_accept_f64(AcceptArgs a)
                     coef[q] = s;
             }
             __syncthreads();
+            const double *vb = a.V + N0 * a.D;
             for (int64_t j = threadIdx.x; j < a.D; j += blockDim.x) {
-                double s = 0.0;
-                for (int64_t q = 0; q < A; ++q)
-                    s += coef[q] * a.V[(N0 + q) * a.D + j];
-                R[j] -= s;
+                double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+                int64_t q = 0;
+                for (; q + 4 <= A; q += 4) {
+                    s0 += coef[q] * vb[q * a.D + j];
+                    s1 += coef[q + 1] * vb[(q + 1) * a.D + j];
+                    s2 += coef[q + 2] * vb[(q + 2) * a.D + j];
+                    s3 += coef[q + 3] * vb[(q + 3) * a.D + j];
+                }
+                for (; q < A; ++q)
+                    s0 += coef[q] * vb[q * a.D + j];
+                R[j] -= (s0 + s1) + (s2 + s3);
             }
             __syncthreads();
         }

@@ -1,0 +1,526 @@
+// Projection GEMMs on the matrix cores, FP32 (v_mfma_f32_32x32x2_f32) and
+// FP64 (v_mfma_f64_16x16x4_f64), for the two halves of a projection pass:
+//
+//   coefficients  C[m][n] = sum_k H[row(m)][k] V[n][k]      (m < M rows, n < N basis rows, k < D)
+//   residual      R[m][j] = H[row(m)][j] - sum_k C[m][k] V[k][j]   (j < D, k < N)
+//                 with the squared norms of R (and of H) summed per output tile,
+//                 R optionally written back over H.
+//
+// Workgroup: 4 waves as 2 x 2; each wave owns SM x SN matrix-core tiles.
+// K is staged through LDS in chunks of 16 with a register prefetch of the next
+// chunk (one barrier per chunk).  Both operands are stored k-major in LDS so
+// every fragment read is a run of consecutive addresses.
+#include "lie_internal.h"
+
+#include <algorithm>
+
+namespace lie {
+
+namespace {
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+template <typename T>
+struct Mma;
+
+// 32x32x2 f32: lane l supplies A[l%32][l/32] and B[l/32][l%32];
+// result register r of lane l is D[8(r/4) + 4(l/32) + r%4][l%32].
+template <>
+struct Mma<float> {
+    static constexpr int E = 32, KS = 2, NR = 16;
+    typedef f32x16 Acc;
+    __device__ static Acc zero() { return Acc{}; }
+    __device__ static Acc mma(float a, float b, Acc c) { return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0); }
+    __device__ static int frag_row(int lane) { return lane & 31; }
+    __device__ static int frag_k(int lane) { return lane >> 5; }
+    __device__ static int out_row(int lane, int r) { return 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3); }
+    __device__ static int out_col(int lane) { return lane & 31; }
+};
+
+// 16x16x4 f64: lane l supplies A[l%16][l/16] and B[l/16][l%16];
+// result register r of lane l is D[4r + l/16][l%16] (measured on gfx950; it
+// differs from the FP32 16x16x4 result layout).
+template <>
+struct Mma<double> {
+    static constexpr int E = 16, KS = 4, NR = 4;
+    typedef f64x4 Acc;
+    __device__ static Acc zero() { return Acc{0.0, 0.0, 0.0, 0.0}; }
+    __device__ static Acc mma(double a, double b, Acc c)
+    {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    __device__ static int frag_row(int lane) { return lane & 15; }
+    __device__ static int frag_k(int lane) { return lane >> 4; }
+    __device__ static int out_row(int lane, int r) { return 4 * r + (lane >> 4); }
+    __device__ static int out_col(int lane) { return lane & 15; }
+};
+
+constexpr int KC = 16;  // K chunk
+
+__device__ inline bool aborted(const DevState *st) { return st && (st->done | st->numeric_error | st->full); }
+
+// Tile loader of a K-contiguous operand: rows [r0, r0+BR) x k [k0, k0+KC) into LDS as S[k][row].
+template <typename T, int BR>
+struct KContigLoader {
+    static constexpr int VEC = 16 / sizeof(T);           // elements per 16-byte load
+    static constexpr int PER_ROW = KC / VEC;
+    static constexpr int TOTAL = BR * PER_ROW;           // vectors per tile
+    static constexpr int PER_THREAD = (TOTAL + 255) / 256;
+    T v[PER_THREAD][VEC];
+
+    template <typename RowFn>
+    __device__ void load(const T *__restrict__ base, int64_t ld, int64_t r0, int64_t rows, int64_t k0, int64_t K,
+                         bool vec_ok, RowFn rowmap)
+    {
+#pragma unroll
+        for (int i = 0; i < PER_THREAD; ++i) {
+            const int q = threadIdx.x + 256 * i;
+            const int r = q / PER_ROW, kv = (q % PER_ROW) * VEC;
+            const int64_t row = r0 + r, k = k0 + kv;
+            if (q < TOTAL && row < rows) {
+                const T *p = base + (int64_t)rowmap(row) * ld + k;
+                if (vec_ok && k + VEC <= K) {
+                    if constexpr (sizeof(T) == 4) {
+                        const float4 t = *reinterpret_cast<const float4 *>(p);
+                        v[i][0] = t.x;
+                        v[i][1] = t.y;
+                        v[i][2] = t.z;
+                        v[i][3] = t.w;
+                    } else {
+                        const double2 t = *reinterpret_cast<const double2 *>(p);
+                        v[i][0] = t.x;
+                        v[i][1] = t.y;
+                    }
+                } else {
+#pragma unroll
+                    for (int u = 0; u < VEC; ++u)
+                        v[i][u] = (k + u < K) ? p[u] : T(0);
+                }
+            } else {
+#pragma unroll
+                for (int u = 0; u < VEC; ++u)
+                    v[i][u] = T(0);
+            }
+        }
+    }
+    template <int LDW>
+    __device__ void store(T (*S)[LDW]) const
+    {
+#pragma unroll
+        for (int i = 0; i < PER_THREAD; ++i) {
+            const int q = threadIdx.x + 256 * i;
+            if (q < TOTAL) {
+                const int r = q / PER_ROW, kv = (q % PER_ROW) * VEC;
+#pragma unroll
+                for (int u = 0; u < VEC; ++u)
+                    S[kv + u][r] = v[i][u];
+            }
+        }
+    }
+};
+
+// Tile loader of a row-major K x N operand (rows k, contiguous n): k [k0, k0+KC) x n [n0, n0+BN) as S[k][n].
+template <typename T, int BN>
+struct KRowLoader {
+    static constexpr int VEC = 16 / sizeof(T);
+    static constexpr int PER_ROW = BN / VEC;
+    static constexpr int TOTAL = KC * PER_ROW;
+    static constexpr int PER_THREAD = (TOTAL + 255) / 256;
+    T v[PER_THREAD][VEC];
+
+    __device__ void load(const T *__restrict__ base, int64_t ld, int64_t k0, int64_t K, int64_t n0, int64_t Ncols,
+                         bool vec_ok)
+    {
+#pragma unroll
+        for (int i = 0; i < PER_THREAD; ++i) {
+            const int q = threadIdx.x + 256 * i;
+            const int kk = q / PER_ROW, nv = (q % PER_ROW) * VEC;
+            const int64_t k = k0 + kk, n = n0 + nv;
+            if (q < TOTAL && k < K) {
+                const T *p = base + k * ld + n;
+                if (vec_ok && n + VEC <= Ncols) {
+                    if constexpr (sizeof(T) == 4) {
+                        const float4 t = *reinterpret_cast<const float4 *>(p);
+                        v[i][0] = t.x;
+                        v[i][1] = t.y;
+                        v[i][2] = t.z;
+                        v[i][3] = t.w;
+                    } else {
+                        const double2 t = *reinterpret_cast<const double2 *>(p);
+                        v[i][0] = t.x;
+                        v[i][1] = t.y;
+                    }
+                } else {
+#pragma unroll
+                    for (int u = 0; u < VEC; ++u)
+                        v[i][u] = (n + u < Ncols) ? p[u] : T(0);
+                }
+            } else {
+#pragma unroll
+                for (int u = 0; u < VEC; ++u)
+                    v[i][u] = T(0);
+            }
+        }
+    }
+    template <int LDW>
+    __device__ void store(T (*S)[LDW]) const
+    {
+#pragma unroll
+        for (int i = 0; i < PER_THREAD; ++i) {
+            const int q = threadIdx.x + 256 * i;
+            if (q < TOTAL) {
+                const int kk = q / PER_ROW, nv = (q % PER_ROW) * VEC;
+#pragma unroll
+                for (int u = 0; u < VEC; ++u)
+                    S[kk][nv + u] = v[i][u];
+            }
+        }
+    }
+};
+
+struct GemmArgs {
+    const void *H;        // candidate rows (row stride D)
+    const int *rows;      // pass row -> H row (null: identity)
+    const int *nrows;     // device row count (null: cnt)
+    int cnt;
+    const void *V;        // basis (row stride D)
+    void *C;              // coefficients, row stride ldc
+    int64_t ldc;
+    int64_t D;
+    const DevState *st;   // basis size N and abort flags
+    int64_t N_fixed;      // used when st is null
+    double *normpart;     // residual: per (row, column tile) squared norms [rows][tiles][2]
+    int write_r;          // residual: write R over H
+};
+
+// ---------------------------------------------------------------- coefficients
+template <typename T, int SM, int SN>
+__global__ void __launch_bounds__(256) k_gemm_dot(GemmArgs g)
+{
+    using M = Mma<T>;
+    constexpr int BM = 2 * SM * M::E, BN = 2 * SN * M::E;
+    constexpr int PAD = 16 / sizeof(T);
+    if (aborted(g.st))
+        return;
+    const int64_t N = g.st ? g.st->N : g.N_fixed;
+    const int Mrows = g.nrows ? *g.nrows : g.cnt;
+    const int64_t n0 = (int64_t)blockIdx.x * BN;
+    const int m0 = blockIdx.y * BM;
+    if (n0 >= N || m0 >= Mrows)
+        return;
+    __shared__ T As[2][KC][BM + PAD];
+    __shared__ T Bs[2][KC][BN + PAD];
+    const T *H = static_cast<const T *>(g.H);
+    const T *V = static_cast<const T *>(g.V);
+    const int *rows = g.rows;
+    auto hmap = [rows](int64_t r) -> int64_t { return rows ? rows[r] : r; };
+    auto ident = [](int64_t r) -> int64_t { return r; };
+    const bool vec_ok = (g.D % (16 / sizeof(T))) == 0;
+    KContigLoader<T, BM> la;
+    KContigLoader<T, BN> lb;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int wm = w >> 1, wn = w & 1;
+    typename M::Acc acc[SM][SN];
+#pragma unroll
+    for (int i = 0; i < SM; ++i)
+#pragma unroll
+        for (int j = 0; j < SN; ++j)
+            acc[i][j] = M::zero();
+    const int nchunks = (int)((g.D + KC - 1) / KC);
+    la.load(H, g.D, m0, Mrows, 0, g.D, vec_ok, hmap);
+    lb.load(V, g.D, n0, N, 0, g.D, vec_ok, ident);
+    la.store(As[0]);
+    lb.store(Bs[0]);
+    __syncthreads();
+    for (int c = 0; c < nchunks; ++c) {
+        const int buf = c & 1;
+        if (c + 1 < nchunks) {
+            la.load(H, g.D, m0, Mrows, (int64_t)(c + 1) * KC, g.D, vec_ok, hmap);
+            lb.load(V, g.D, n0, N, (int64_t)(c + 1) * KC, g.D, vec_ok, ident);
+        }
+#pragma unroll
+        for (int kk = 0; kk < KC; kk += M::KS) {
+            T a[SM], b[SN];
+#pragma unroll
+            for (int i = 0; i < SM; ++i)
+                a[i] = As[buf][kk + M::frag_k(lane)][wm * SM * M::E + i * M::E + M::frag_row(lane)];
+#pragma unroll
+            for (int j = 0; j < SN; ++j)
+                b[j] = Bs[buf][kk + M::frag_k(lane)][wn * SN * M::E + j * M::E + M::frag_row(lane)];
+#pragma unroll
+            for (int i = 0; i < SM; ++i)
+#pragma unroll
+                for (int j = 0; j < SN; ++j)
+                    acc[i][j] = M::mma(a[i], b[j], acc[i][j]);
+        }
+        if (c + 1 < nchunks) {
+            la.store(As[buf ^ 1]);
+            lb.store(Bs[buf ^ 1]);
+        }
+        __syncthreads();
+    }
+    T *C = static_cast<T *>(g.C);
+#pragma unroll
+    for (int i = 0; i < SM; ++i)
+#pragma unroll
+        for (int j = 0; j < SN; ++j)
+#pragma unroll
+            for (int r = 0; r < M::NR; ++r) {
+                const int m = m0 + wm * SM * M::E + i * M::E + M::out_row(lane, r);
+                const int64_t n = n0 + wn * SN * M::E + j * M::E + M::out_col(lane);
+                if (m < Mrows && n < N)
+                    C[(int64_t)m * g.ldc + n] = acc[i][j][r];
+            }
+}
+
+// ---------------------------------------------------------------- residual + norms
+template <typename T, int SM, int SN>
+__global__ void __launch_bounds__(256) k_gemm_sub(GemmArgs g)
+{
+    using M = Mma<T>;
+    constexpr int BM = 2 * SM * M::E, BN = 2 * SN * M::E;
+    constexpr int PAD = 16 / sizeof(T);
+    if (aborted(g.st))
+        return;
+    const int64_t N = g.st ? g.st->N : g.N_fixed;
+    const int Mrows = g.nrows ? *g.nrows : g.cnt;
+    const int64_t j0 = (int64_t)blockIdx.x * BN;  // operator columns
+    const int m0 = blockIdx.y * BM;
+    if (m0 >= Mrows)
+        return;
+    __shared__ T As[2][KC][BM + PAD];
+    __shared__ T Bs[2][KC][BN + PAD];
+    __shared__ double red[BM][2][2];
+    const T *Cc = static_cast<const T *>(g.C);
+    const T *V = static_cast<const T *>(g.V);
+    auto ident = [](int64_t r) -> int64_t { return r; };
+    KContigLoader<T, BM> la;  // C rows (K = basis index, contiguous)
+    KRowLoader<T, BN> lb;     // V rows
+    const bool vec_c = (g.ldc % (16 / sizeof(T))) == 0;
+    const bool vec_v = (g.D % (16 / sizeof(T))) == 0;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int wm = w >> 1, wn = w & 1;
+    typename M::Acc acc[SM][SN];
+#pragma unroll
+    for (int i = 0; i < SM; ++i)
+#pragma unroll
+        for (int j = 0; j < SN; ++j)
+            acc[i][j] = M::zero();
+    const int nchunks = (int)((N + KC - 1) / KC);
+    if (nchunks > 0) {
+        la.load(Cc, g.ldc, m0, Mrows, 0, N, vec_c, ident);
+        lb.load(V, g.D, 0, N, j0, g.D, vec_v);
+        la.store(As[0]);
+        lb.store(Bs[0]);
+    }
+    __syncthreads();
+    for (int c = 0; c < nchunks; ++c) {
+        const int buf = c & 1;
+        if (c + 1 < nchunks) {
+            la.load(Cc, g.ldc, m0, Mrows, (int64_t)(c + 1) * KC, N, vec_c, ident);
+            lb.load(V, g.D, (int64_t)(c + 1) * KC, N, j0, g.D, vec_v);
+        }
+#pragma unroll
+        for (int kk = 0; kk < KC; kk += M::KS) {
+            T a[SM], b[SN];
+#pragma unroll
+            for (int i = 0; i < SM; ++i)
+                a[i] = As[buf][kk + M::frag_k(lane)][wm * SM * M::E + i * M::E + M::frag_row(lane)];
+#pragma unroll
+            for (int j = 0; j < SN; ++j)
+                b[j] = Bs[buf][kk + M::frag_k(lane)][wn * SN * M::E + j * M::E + M::frag_row(lane)];
+#pragma unroll
+            for (int i = 0; i < SM; ++i)
+#pragma unroll
+                for (int j = 0; j < SN; ++j)
+                    acc[i][j] = M::mma(a[i], b[j], acc[i][j]);
+        }
+        if (c + 1 < nchunks) {
+            la.store(As[buf ^ 1]);
+            lb.store(Bs[buf ^ 1]);
+        }
+        __syncthreads();
+    }
+    // epilogue: R = H - acc, squared norms of R and H summed over this wave's columns
+    T *H = const_cast<T *>(static_cast<const T *>(g.H));
+    const int *rows = g.rows;
+#pragma unroll
+    for (int i = 0; i < SM; ++i)
+#pragma unroll
+        for (int r = 0; r < M::NR; ++r) {
+            const int ml = wm * SM * M::E + i * M::E + M::out_row(lane, r);
+            const int m = m0 + ml;
+            double rs = 0.0, hsq = 0.0;
+            if (m < Mrows) {
+                const int64_t hr = rows ? rows[m] : m;
+#pragma unroll
+                for (int j = 0; j < SN; ++j) {
+                    const int64_t col = j0 + wn * SN * M::E + j * M::E + M::out_col(lane);
+                    if (col < g.D) {
+                        T *hp = H + hr * g.D + col;
+                        const T h = *hp;
+                        const T res = h - acc[i][j][r];
+                        if (g.write_r)
+                            *hp = res;
+                        rs += (double)res * (double)res;
+                        hsq += (double)h * (double)h;
+                    }
+                }
+            }
+            // sum over the lanes that hold the same output row
+            for (int off = M::E / 2; off > 0; off >>= 1) {
+                rs += __shfl_xor(rs, off, 64);
+                hsq += __shfl_xor(hsq, off, 64);
+            }
+            if (M::out_col(lane) == 0) {
+                red[ml][wn][0] = rs;
+                red[ml][wn][1] = hsq;
+            }
+        }
+    __syncthreads();
+    if (threadIdx.x < BM) {
+        const int m = m0 + threadIdx.x;
+        if (m < Mrows) {
+            double *o = g.normpart + ((int64_t)m * gridDim.x + blockIdx.x) * 2;
+            o[0] = red[threadIdx.x][0][0] + red[threadIdx.x][1][0];
+            o[1] = red[threadIdx.x][0][1] + red[threadIdx.x][1][1];
+        }
+    }
+}
+
+__global__ void k_gemm_norm_final(const double *__restrict__ normpart, const int *__restrict__ nrows, int cnt,
+                                  int tiles, const DevState *__restrict__ st, double *__restrict__ rho2,
+                                  double *__restrict__ h2)
+{
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    const int Mrows = nrows ? *nrows : cnt;
+    if (m >= Mrows || aborted(st))
+        return;
+    double a = 0.0, b = 0.0;
+    for (int t = 0; t < tiles; ++t) {
+        a += normpart[((int64_t)m * tiles + t) * 2];
+        b += normpart[((int64_t)m * tiles + t) * 2 + 1];
+    }
+    rho2[m] = a;
+    if (h2)
+        h2[m] = b;
+}
+
+template <typename T, int SM, int SN>
+hipError_t dot_impl(const GemmArgs &g, int64_t n_hi, hipStream_t s)
+{
+    constexpr int E = Mma<T>::E;
+    constexpr int BM = 2 * SM * E, BN = 2 * SN * E;
+    hipLaunchKernelGGL((k_gemm_dot<T, SM, SN>), dim3((unsigned)((n_hi + BN - 1) / BN), (g.cnt + BM - 1) / BM),
+                       dim3(256), 0, s, g);
+    return hipGetLastError();
+}
+
+template <typename T, int SM, int SN>
+hipError_t sub_impl(const GemmArgs &g, hipStream_t s)
+{
+    constexpr int E = Mma<T>::E;
+    constexpr int BM = 2 * SM * E, BN = 2 * SN * E;
+    const int tiles = (int)((g.D + BN - 1) / BN);
+    hipLaunchKernelGGL((k_gemm_sub<T, SM, SN>), dim3(tiles, (g.cnt + BM - 1) / BM), dim3(256), 0, s, g);
+    return hipGetLastError();
+}
+
+
+}  // namespace
+
+int64_t coef_ld(int64_t n_hi) { return (std::max<int64_t>(n_hi, 1) + 3) / 4 * 4; }
+
+// Tile choice: the larger workgroup tile when it still yields enough
+// workgroups to cover the compute units, the smaller one otherwise.
+int gemm_tile_f32(int64_t rows, int64_t cols) { return ((rows + 127) / 128) * ((cols + 127) / 128) >= 192 ? 2 : 1; }
+
+hipError_t launch_gemm_dot_f32(const float *Vs, const DevState *st, const float *Hs, int cnt, int64_t D, int64_t n_hi,
+                               float *C, int tile, hipStream_t s)
+{
+    if (cnt <= 0)
+        return hipSuccess;
+    GemmArgs g{};
+    g.H = Hs;
+    g.cnt = cnt;
+    g.V = Vs;
+    g.C = C;
+    g.ldc = coef_ld(n_hi);
+    g.D = D;
+    g.st = st;
+    n_hi = std::max<int64_t>(n_hi, 1);
+    return tile == 2 ? dot_impl<float, 2, 2>(g, n_hi, s) : dot_impl<float, 1, 1>(g, n_hi, s);
+}
+
+int gemm_sub_tiles_f32(int64_t D, int tile) { return (int)((D + (tile == 2 ? 128 : 64) - 1) / (tile == 2 ? 128 : 64)); }
+
+hipError_t launch_gemm_sub_f32(const float *Vs, const DevState *st, const float *Hs, const float *C, int64_t n_hi,
+                               int cnt, int64_t D, double *normpart, int tile, hipStream_t s)
+{
+    if (cnt <= 0)
+        return hipSuccess;
+    GemmArgs g{};
+    g.H = Hs;
+    g.cnt = cnt;
+    g.V = Vs;
+    g.C = const_cast<float *>(C);
+    g.ldc = coef_ld(n_hi);
+    g.D = D;
+    g.st = st;
+    g.normpart = normpart;
+    g.write_r = 0;
+    return tile == 2 ? sub_impl<float, 2, 2>(g, s) : sub_impl<float, 1, 1>(g, s);
+}
+
+int gemm_sub_tiles_f64(int64_t D) { return (int)((D + 63) / 64); }
+
+hipError_t launch_gemm_dot_f64(const double *V, const DevState *st, const double *H, const int *rows,
+                               const int *nrows, int cnt, int64_t D, int64_t n_hi, double *C, hipStream_t s)
+{
+    if (cnt <= 0)
+        return hipSuccess;
+    GemmArgs g{};
+    g.H = H;
+    g.rows = rows;
+    g.nrows = nrows;
+    g.cnt = cnt;
+    g.V = V;
+    g.C = C;
+    g.ldc = coef_ld(n_hi);
+    g.D = D;
+    g.st = st;
+    return dot_impl<double, 2, 2>(g, std::max<int64_t>(n_hi, 1), s);
+}
+
+hipError_t launch_gemm_sub_f64(const double *V, const DevState *st, double *H, const int *rows, const int *nrows,
+                               const double *C, int64_t n_hi, int cnt, int64_t D, double *normpart, hipStream_t s)
+{
+    if (cnt <= 0)
+        return hipSuccess;
+    GemmArgs g{};
+    g.H = H;
+    g.rows = rows;
+    g.nrows = nrows;
+    g.cnt = cnt;
+    g.V = V;
+    g.C = const_cast<double *>(C);
+    g.ldc = coef_ld(n_hi);
+    g.D = D;
+    g.st = st;
+    g.normpart = normpart;
+    g.write_r = 1;
+    return sub_impl<double, 2, 2>(g, s);
+}
+
+hipError_t launch_norm_final(const double *normpart, const int *nrows, int cnt, int tiles, const DevState *st,
+                             double *rho2, double *h2, hipStream_t s)
+{
+    if (cnt <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_gemm_norm_final, dim3((cnt + 255) / 256), dim3(256), 0, s, normpart, nrows, cnt, tiles, st,
+                       rho2, h2);
+    return hipGetLastError();
+}
+
+}  // namespace lie

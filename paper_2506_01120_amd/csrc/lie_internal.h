@@ -123,6 +123,27 @@ hipError_t launch_accept_f64(const AcceptArgs &args, hipStream_t s);
 // G = V V^T (n x n) then ||G - I||_F into *out (device), using `work` of n*n + 256 doubles.
 hipError_t launch_orth_loss(const double *V, int64_t n, int64_t D, double *work, double *out, hipStream_t s);
 
+// ------------------------------------------------------------- matrix-core projection GEMMs (kernels_gemm.hip)
+// Coefficients C[m][n] = <H_row(m), V_n> and residual R = H - C V with per-tile
+// squared norms (normpart[m][tile][2] = {||R||^2, ||H||^2} partial sums).
+// The coefficient leading dimension is coef_ld(n_hi) in both halves.
+int64_t coef_ld(int64_t n_hi);
+int gemm_tile_f32(int64_t rows, int64_t cols);     // 2: 128x128 workgroup tile, 1: 64x64
+int gemm_sub_tiles_f32(int64_t D, int tile);
+int gemm_sub_tiles_f64(int64_t D);
+hipError_t launch_gemm_dot_f32(const float *Vs, const DevState *st, const float *Hs, int cnt, int64_t D, int64_t n_hi,
+                               float *C, int tile, hipStream_t s);
+hipError_t launch_gemm_sub_f32(const float *Vs, const DevState *st, const float *Hs, const float *C, int64_t n_hi,
+                               int cnt, int64_t D, double *normpart, int tile, hipStream_t s);
+hipError_t launch_gemm_dot_f64(const double *V, const DevState *st, const double *H, const int *rows,
+                               const int *nrows, int cnt, int64_t D, int64_t n_hi, double *C, hipStream_t s);
+// R written over H_row(m)
+hipError_t launch_gemm_sub_f64(const double *V, const DevState *st, double *H, const int *rows, const int *nrows,
+                               const double *C, int64_t n_hi, int cnt, int64_t D, double *normpart, hipStream_t s);
+// rho2[m] = sum of tile partials of ||R||^2, h2[m] (if non-null) of ||H||^2
+hipError_t launch_norm_final(const double *normpart, const int *nrows, int cnt, int tiles, const DevState *st,
+                             double *rho2, double *h2, hipStream_t s);
+
 // ------------------------------------------------------------- FP32 screening kernels (kernels_screen.hip)
 // Hs[c] = fp32 packed [Vs_l, Vs_m] for pair p0 + c, hs2[c] = ||Hs[c]||^2.
 hipError_t launch_comm_f32(const float *Vs, int d, int64_t p0, int cnt, const DevState *st, float *Hs, double *hs2,
