@@ -34,6 +34,10 @@ PEAK = {"hbm_GBps": 8000.0, "fp64_TF": 78.6, "fp32_TF": 157.3, "bf16_TF": 2500.0
 def workload(name: str):
     from paper_2506_01120_amd import workloads as W
 
+    if name == "batch64":
+        probs = W.batch_problems(tol=1e-8)
+        return probs, 1e-8, ("64 independent problems: Ising n=3..7, XX+YY n=3..6, 29 random Pauli-string sets "
+                             "on n=4..6 qubits, random pairs d=8..24 (seeds 1000+i)")
     if name == "su16":
         return W.rand_pair(16, seed=2), 1e-10, "random traceless anti-Hermitian pair d=16 seed 2 -> su(16)"
     if name == "ising3":
@@ -48,8 +52,21 @@ def workload(name: str):
 def run_steps(gens, tol, cfg, steps):
     import torch
 
-    from paper_2506_01120_amd import LieClosure
+    from paper_2506_01120_amd import BatchClosure, LieClosure
 
+    if isinstance(gens, list):  # a batch of problems: one step = the whole batch
+        batches = [BatchClosure([p.gens for p in gens], [p.tol for p in gens], **cfg) for _ in range(steps)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for b in batches:
+            b.run()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        stats = [b.stats(-1) for b in batches]  # batch aggregate: counters summed, grouped-launch timers
+        dims = [[b.dim(i) for i in range(b.n)] for b in batches]
+        for b in batches:
+            b.close()
+        return t1 - t0, stats, dims
     handles = [LieClosure(gens, tol, **cfg) for _ in range(steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -166,8 +183,11 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if args.precision == "fp64" else ("f32+f64" if args.precision == "fp32" else "bf16x3+f64"),
         "data": "synthetic (seeded generators)",
-        "config": {"workload": desc, "d": int(gens.shape[-1]), "n_gen": int(gens.shape[0]), "tol": tol,
-                   "dim": dims[0], "checks_per_step": checks // args.steps, "precision": args.precision,
+        "config": {"workload": desc,
+                   "d": (int(gens.shape[-1]) if not isinstance(gens, list) else "8..128"),
+                   "n_gen": (int(gens.shape[0]) if not isinstance(gens, list) else "2..13"), "tol": tol,
+                   "dim": (dims[0] if not isinstance(gens, list) else sum(dims[0])),
+                   "checks_per_step": checks // args.steps, "precision": args.precision,
                    "decide": args.decide if args.precision != "fp64" else "fp64",
                    "block": stats[0]["block"], "early_exit": bool(args.early_exit), "parallelism": "single GPU"},
         "roofline": roof,

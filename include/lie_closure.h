@@ -70,8 +70,9 @@ typedef struct lie_closure_config {
     uint32_t struct_size;  /* must be sizeof(lie_closure_config) */
     int32_t precision;     /* lie_precision, default LIE_PREC_FP64 */
     int32_t decide;        /* lie_decide, default LIE_DECIDE_SCREEN for screened precisions */
-    int32_t block;         /* candidates per block: 1 = plain one-at-a-time form, 2..1024 fixed, 0 = adaptive
-                              (small blocks while most candidates are accepted, large blocks after) */
+    int32_t block;         /* candidates per block: 1 = plain one-at-a-time form, 2..4096 fixed, 0 = adaptive
+                              (small FP64-decided blocks while most candidates are accepted, large
+                              screened blocks after) */
     int32_t early_exit;    /* 1: stop once |V| equals the ambient bound (exact; d^2-1 for traceless inputs) */
     int32_t device;        /* HIP device ordinal; -1 = the calling thread's current device */
     double tau_rej;        /* SCREEN reject threshold on the screened residual; 0 = precision default */
@@ -179,8 +180,10 @@ const char *lie_last_error(void);
 
 /*
  * Batched form: n_problems independent closures (uneven d and generator
- * counts) advanced together, one block step of every live problem per launch
- * sequence, so small problems fill the GPU together.
+ * counts) advanced together on one stream.  Each round advances every live
+ * problem by one block step, and each stage of that step is ONE grouped
+ * launch covering all problems of the round, so small problems fill the GPU
+ * together; finished problems leave the batch.
  *   generators[i] -- host, n_gen[i] * d[i] * d[i] complex128 (copied)
  *   tol[i]        -- per-problem tolerance
  *   cfg           -- shared configuration (precision, decide, block, early_exit)
@@ -192,6 +195,8 @@ lie_status lie_closure_batch_run(lie_closure_batch *b);
 lie_status lie_closure_batch_dim(const lie_closure_batch *b, int32_t i, int64_t *dim);
 lie_status lie_closure_batch_basis(const lie_closure_batch *b, int32_t i, double *out, int64_t capacity,
                                    int64_t *written);
+/* i >= 0: that problem's counters; i = -1: the whole batch (counters summed over
+ * problems, blocks = rounds, kernel timers of the grouped launches). */
 lie_status lie_closure_batch_stats_get(const lie_closure_batch *b, int32_t i, lie_closure_stats *out);
 void lie_closure_batch_free(lie_closure_batch *b);
 

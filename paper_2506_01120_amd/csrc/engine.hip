@@ -46,7 +46,7 @@ lie_status fail(lie_status st, const char *fmt, ...)
 constexpr int kGemvRows = 16;
 // Default SCREEN reject threshold on the FP32-screened residual (paper norm).
 constexpr double kDefaultTauFp32 = 1e-4;
-constexpr int kMaxBlock = 1024;
+constexpr int kMaxBlock = 4096;
 constexpr int kMaxD = 128;
 
 int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
@@ -176,6 +176,9 @@ struct lie_closure {
     int64_t host_syncs = 0;
     double run_ms = 0;
     KernelTimer timer;
+    // bookkeeping of the grouped (batched) executor
+    int64_t b_nlo = 0, b_qrows = 0, b_lastc = 0, b_lasta = 0;
+    int b_cur = 0;
 
     ~lie_closure()
     {
@@ -430,7 +433,9 @@ struct lie_closure {
             }
             const int cnt = (int)std::min<int64_t>(cur, avail - cursor);
             const int64_t n_hi = std::min<int64_t>(cap, n_lo + queued_rows);
-            s = screened ? step_screen(cnt, n_lo, n_hi) : step_fp64(cnt, n_lo, n_hi);
+            // while most candidates are accepted the screen filters nothing: decide in FP64 directly
+            const bool growth = block == 0 && cur == block_growth;
+            s = (screened && !growth) ? step_screen(cnt, n_lo, n_hi) : step_fp64(cnt, n_lo, n_hi);
             if (s != LIE_OK)
                 break;
             cursor += cnt;
@@ -570,7 +575,11 @@ lie_status lie_closure_init(lie_closure **out, const double *generators, int32_t
         // (about block^2/2 * d^2 * 32 bytes through one compute unit per block)
         const int64_t D0 = (int64_t)d * d;
         h->block_growth = D0 <= 256 ? 64 : (D0 <= 1024 ? 32 : 16);
-        h->block_sat = 1024;
+        // saturated size: enough 128-row candidate tiles that the coefficient GEMM
+        // (candidates x basis rows) spans about 256 workgroups
+        const int64_t ntiles = std::max<int64_t>(1, (std::max<int64_t>(ambient, 1) + 127) / 128);
+        const int64_t want = ((256 + ntiles - 1) / ntiles) * 128;
+        h->block_sat = (int)std::min<int64_t>(kMaxBlock, std::max<int64_t>(1024, want));
     }
     h->timer.on = cfg.profile != 0;
     h->screened = cfg.precision != LIE_PREC_FP64;
@@ -810,12 +819,495 @@ const char *lie_last_error(void) { return g_last_error.c_str(); }
 
 }  // extern "C"
 
+// Grouped executor: every round advances each live problem by one block step,
+// and each stage of the step is one launch for all problems of the round
+// (workgroups find their problem through a prefix table).  Problems leave the
+// batch when they complete; the driver synchronises once for all problems when
+// any of them runs out of known pairs (or after 64 rounds).
 struct lie_closure_batch {
     std::vector<lie_closure *> probs;
+    int device = -1;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    // staging ring for the per-round argument tables (pinned host -> device)
+    static constexpr int kSlots = 65;
+    size_t slot_bytes = 0;
+    char *host_ring = nullptr, *dev_ring = nullptr;
+    int slot = 0;
+    size_t used = 0;
+    hipEvent_t slot_free[kSlots] = {};
+    // state read-back
+    lie::DevState **d_stptrs = nullptr;
+    lie::DevState *d_states = nullptr, *h_states = nullptr;
+    KernelTimer timer;
+    int64_t rounds = 0, host_syncs = 0;
+    double run_ms = 0;
+    bool done = false;
+    lie_status first_status = LIE_OK;
+    std::string first_error;
+
     ~lie_closure_batch()
     {
+        if (device >= 0)
+            (void)hipSetDevice(device);
+        if (stream)
+            (void)hipStreamSynchronize(stream);
         for (auto *p : probs)
             delete p;
+        for (hipEvent_t e : slot_free)
+            if (e)
+                (void)hipEventDestroy(e);
+        if (host_ring)
+            (void)hipHostFree(host_ring);
+        if (h_states)
+            (void)hipHostFree(h_states);
+        for (void *p : {(void *)dev_ring, (void *)d_stptrs, (void *)d_states})
+            if (p)
+                (void)hipFree(p);
+        if (own_stream && stream)
+            (void)hipStreamDestroy(stream);
+    }
+
+    lie_status setup()
+    {
+        const int n = (int)probs.size();
+        // argument tables of one round: at most ~24 stage tables of n entries each
+        slot_bytes = (size_t)n * 32 * 256 + 64 * 1024;
+        HIP_TRY(hipHostMalloc((void **)&host_ring, slot_bytes * kSlots, hipHostMallocDefault));
+        HIP_TRY(hipMalloc(&dev_ring, slot_bytes * kSlots));
+        for (auto &e : slot_free)
+            HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        HIP_TRY(hipMalloc(&d_stptrs, n * sizeof(lie::DevState *)));
+        HIP_TRY(hipMalloc(&d_states, n * sizeof(lie::DevState)));
+        HIP_TRY(hipHostMalloc((void **)&h_states, n * sizeof(lie::DevState), hipHostMallocDefault));
+        std::vector<lie::DevState *> ptrs(n);
+        for (int i = 0; i < n; ++i)
+            ptrs[i] = probs[i]->st;
+        HIP_TRY(hipMemcpyAsync(d_stptrs, ptrs.data(), n * sizeof(lie::DevState *), hipMemcpyHostToDevice, stream));
+        HIP_TRY(hipStreamSynchronize(stream));
+        return LIE_OK;
+    }
+
+    // Append a table to the current round's slot; returns its device address.
+    template <typename T>
+    const T *put(const std::vector<T> &v)
+    {
+        used = (used + 15) & ~size_t(15);
+        const size_t bytes = v.size() * sizeof(T);
+        if (used + bytes > slot_bytes)
+            return nullptr;
+        std::memcpy(host_ring + (size_t)slot * slot_bytes + used, v.data(), bytes);
+        const T *dev = reinterpret_cast<const T *>(dev_ring + (size_t)slot * slot_bytes + used);
+        used += bytes;
+        return dev;
+    }
+
+    // A grouped launch under construction.
+    template <typename A>
+    struct Group {
+        std::vector<A> args;
+        std::vector<int> start{0};
+        std::vector<int> gx;
+        void add(const A &a, int wgs, int gridx)
+        {
+            args.push_back(a);
+            start.push_back(start.back() + std::max(wgs, 0));
+            gx.push_back(std::max(gridx, 1));
+        }
+        bool empty() const { return args.empty(); }
+    };
+
+    template <typename A>
+    lie_status make(const Group<A> &g, lie::Batch *out)
+    {
+        out->args = put(g.args);
+        out->start = put(g.start);
+        out->gx = put(g.gx);
+        out->nprob = (int)g.args.size();
+        out->total = g.start.back();
+        if (!out->args || !out->start || !out->gx)
+            return fail(LIE_ERR_OOM, "batched launch table exceeds its staging slot");
+        return LIE_OK;
+    }
+
+    lie_status sync_all()
+    {
+        const int n = (int)probs.size();
+        HIP_TRY(lie::launch_gather_states(d_stptrs, n, d_states, stream));
+        HIP_TRY(hipMemcpyAsync(h_states, d_states, n * sizeof(lie::DevState), hipMemcpyDeviceToHost, stream));
+        HIP_TRY(hipStreamSynchronize(stream));
+        ++host_syncs;
+        timer.harvest();
+        for (int i = 0; i < n; ++i) {
+            lie_closure *h = probs[i];
+            if (h->done || h->failed)
+                continue;
+            h->hs = h_states[i];
+            ++h->host_syncs;
+            lie_status s = h->check_state();
+            if (s != LIE_OK) {
+                if (first_status == LIE_OK) {
+                    first_status = s;
+                    first_error = "problem " + std::to_string(i) + ": " + g_last_error;
+                }
+                continue;
+            }
+            h->b_nlo = h->hs.N;
+            h->b_qrows = 0;
+            if (h->block == 0) {
+                const int64_t dc = h->hs.n_cand - h->b_lastc, da = h->hs.n_acc - h->b_lasta;
+                if (dc > 0)
+                    h->b_cur = 8 * da > dc ? h->block_growth : h->block_sat;
+                h->b_lastc = h->hs.n_cand;
+                h->b_lasta = h->hs.n_acc;
+            }
+            if (h->hs.done || (h->cfg.early_exit && h->b_nlo >= h->ambient) ||
+                h->cursor >= lie::pairs_below(h->b_nlo))
+                h->done = true;
+        }
+        return LIE_OK;
+    }
+
+    struct Item {
+        lie_closure *h;
+        int cnt;
+        int64_t n_hi;
+    };
+
+    lie_status run()
+    {
+        if (done)
+            return LIE_OK;
+        if (first_status != LIE_OK)
+            return fail(LIE_ERR_STATE, "a previous run of this batch failed");
+        HIP_TRY(hipSetDevice(device));
+        const auto t0 = std::chrono::steady_clock::now();
+        constexpr int kMaxQueued = 64;
+        for (lie_closure *h : probs) {
+            h->b_nlo = h->hs.N;
+            h->b_qrows = 0;
+            h->b_cur = h->block > 0 ? h->block : h->block_growth;
+            h->b_lastc = h->hs.n_cand;
+            h->b_lasta = h->hs.n_acc;
+            if (h->cursor >= lie::pairs_below(h->b_nlo) || (h->cfg.early_exit && h->b_nlo >= h->ambient))
+                h->done = true;
+        }
+        int queued = 0;
+        lie_status s = LIE_OK;
+        for (;;) {
+            bool need = queued >= kMaxQueued;
+            for (lie_closure *h : probs)
+                if (!h->done && !h->failed && h->cursor >= lie::pairs_below(h->b_nlo))
+                    need = true;
+            if (need) {
+                if ((s = sync_all()) != LIE_OK)
+                    break;
+                queued = 0;
+            }
+            std::vector<Item> f64, scr;
+            for (lie_closure *h : probs) {
+                if (h->done || h->failed)
+                    continue;
+                const int64_t avail = lie::pairs_below(h->b_nlo);
+                if (h->cursor >= avail)
+                    continue;
+                const int cnt = (int)std::min<int64_t>(h->b_cur, avail - h->cursor);
+                const int64_t n_hi = std::min<int64_t>(h->cap, h->b_nlo + h->b_qrows);
+                const bool growth = h->block == 0 && h->b_cur == h->block_growth;
+                (h->screened && !growth ? scr : f64).push_back(Item{h, cnt, n_hi});
+            }
+            if (f64.empty() && scr.empty())
+                break;
+            // a slot is reused kSlots rounds later; its event proves the copy out of it has run
+            HIP_TRY(hipEventSynchronize(slot_free[slot]));
+            if ((s = build_and_launch(f64, scr)) != LIE_OK)
+                break;
+            for (auto *v : {&f64, &scr})
+                for (const Item &it : *v) {
+                    it.h->cursor += it.cnt;
+                    it.h->b_qrows += it.cnt;
+                    ++it.h->blocks;
+                }
+            ++queued;
+            ++rounds;
+        }
+        if (s == LIE_OK && first_status == LIE_OK) {
+            if ((s = sync_all()) == LIE_OK && first_status == LIE_OK)
+                done = true;
+        }
+        run_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        if (s == LIE_OK && first_status != LIE_OK) {
+            std::string msg = first_error;
+            return fail(first_status, "%s", msg.c_str());
+        }
+        return s;
+    }
+
+    // A recorded grouped launch of the round being built.
+    enum Kind { COMM_F64, COMM_F32, ROWNORM_F32, DOT_F64, DOT_F32, SUB_F64, SUB_F32, NORM, CLASSIFY, ACCEPT };
+    struct Rec {
+        Kind kind;
+        lie::Batch b;
+        bool lds;
+        int dmax;
+        int kid;
+        double flops;
+    };
+    std::vector<Rec> recs;
+
+    template <typename A>
+    lie_status record(Kind kind, const Group<A> &g, bool lds, int dmax, int kid, double flops)
+    {
+        if (g.empty())
+            return LIE_OK;
+        Rec r{kind, {}, lds, dmax, kid, flops};
+        lie_status s = make(g, &r.b);
+        if (s != LIE_OK)
+            return s;
+        recs.push_back(r);
+        return LIE_OK;
+    }
+
+    // FP64 bracket of the block (or of the survivors) into H64 of each item.
+    lie_status group_comm_f64(const std::vector<Item> &items, bool from_survivors)
+    {
+        Group<lie::CommArgs> lds, glob;
+        int dmax = 1;
+        double fl = 0;
+        for (const Item &it : items) {
+            lie_closure *h = it.h;
+            lie::CommArgs a{h->V64, h->d, from_survivors ? 0 : h->cursor, from_survivors ? h->surv_pairs : nullptr,
+                            from_survivors ? h->nsurv : nullptr, it.cnt, h->st, h->H64, nullptr};
+            if (lie::comm_f64_fits_lds(h->d)) {
+                lds.add(a, it.cnt, 1);
+                dmax = std::max(dmax, h->d);
+            } else {
+                const int tiles = (int)((h->D + 255) / 256);
+                glob.add(a, tiles * it.cnt, tiles);
+            }
+            if (!from_survivors)
+                fl += 8.0 * h->d * h->d * (double)h->d * it.cnt;
+        }
+        const int kid = from_survivors ? LIE_K_VERIFY : LIE_K_COMM;
+        lie_status s = record(COMM_F64, lds, true, dmax, kid, fl);
+        if (s == LIE_OK)
+            s = record(COMM_F64, glob, false, 0, kid, lds.empty() ? fl : 0);
+        return s;
+    }
+
+    // FP64 projection pass over H64 rows (all cnt, or the survivor list / count).
+    lie_status group_project_f64(const std::vector<Item> &items, bool survivors_rows, bool survivors_count,
+                                 bool first, bool verify)
+    {
+        Group<lie::GemmArgs> dot, sub;
+        Group<lie::NormArgs> nrm;
+        double fl = 0;
+        const int bm = lie::gemm_group_m(false), bn = lie::gemm_group_n(false);
+        for (const Item &it : items) {
+            lie_closure *h = it.h;
+            const int64_t nh = std::min(std::max<int64_t>(it.n_hi, 1), h->cap);
+            lie::GemmArgs g{};
+            g.H = h->H64;
+            g.rows = survivors_rows ? h->surv_rows : nullptr;
+            g.nrows = survivors_count ? h->nsurv : nullptr;
+            g.cnt = it.cnt;
+            g.V = h->V64;
+            g.C = h->C;
+            g.ldc = lie::coef_ld(nh);
+            g.D = h->D;
+            g.st = h->st;
+            const int mt = (it.cnt + bm - 1) / bm;
+            const int nt = (int)((nh + bn - 1) / bn);
+            dot.add(g, nt * mt, nt);
+            g.normpart = h->part;
+            g.write_r = 1;
+            const int jt = (int)((h->D + bn - 1) / bn);
+            sub.add(g, jt * mt, jt);
+            double *r2 = first ? h->cand_a2 : h->rho2;
+            double *n2 = first ? h->cand_n2 : (verify_first_ ? h->h2 : h->h2b);
+            nrm.add(lie::NormArgs{h->part, g.nrows, it.cnt, jt, h->st, r2, n2}, (it.cnt + 255) / 256, 1);
+            if (!verify)
+                fl += 2.0 * (double)h->b_nlo * (double)h->D * it.cnt;
+        }
+        lie_status s = record(DOT_F64, dot, false, 0, verify ? LIE_K_VERIFY : LIE_K_DOT, fl);
+        if (s == LIE_OK)
+            s = record(SUB_F64, sub, false, 0, verify ? LIE_K_VERIFY : LIE_K_SUB, fl);
+        if (s == LIE_OK)
+            s = record(NORM, nrm, false, 0, verify ? LIE_K_VERIFY : LIE_K_REDUCE, 0);
+        return s;
+    }
+    bool verify_first_ = false;  // screened verification: first FP64 pass keeps the candidate norms in h2
+
+    lie_status group_classify(const std::vector<Item> &items, bool screen)
+    {
+        Group<lie::ClassifyArgs> g;
+        for (const Item &it : items) {
+            lie_closure *h = it.h;
+            const int pol = screen ? h->policy : lie::POL_ABS;
+            const double thr = screen ? h->policy_thr : h->tol;
+            g.add(lie::ClassifyArgs{h->cand_a2, h->cand_n2, it.cnt, h->cursor, pol, thr, h->st, h->surv_rows,
+                                    h->surv_pairs, h->slot, h->nsurv},
+                  1, 1);
+        }
+        return record(CLASSIFY, g, false, 0, LIE_K_REDUCE, 0);
+    }
+
+    lie_status group_accept(const std::vector<Item> &items, bool screen)
+    {
+        Group<lie::AcceptArgs> g;
+        for (const Item &it : items) {
+            lie_closure *h = it.h;
+            lie::AcceptArgs a{};
+            a.V = h->V64;
+            a.Vs = h->Vs;
+            a.st = h->st;
+            a.H = h->H64;
+            a.rrow = screen ? nullptr : h->surv_rows;
+            a.cand_a2 = h->cand_a2;
+            a.cand_n2 = h->cand_n2;
+            a.slot = h->slot;
+            a.nsurv = h->nsurv;
+            a.surv_cand = h->surv_rows;
+            a.h2 = screen ? h->h2 : nullptr;
+            a.rho2 = h->rho2;
+            a.cnt = it.cnt;
+            a.D = h->D;
+            a.cap = h->cap;
+            a.ambient = h->ambient;
+            a.tol = h->tol;
+            a.mode = 1;
+            a.screened = screen && h->policy != lie::POL_ALL ? 1 : 0;
+            a.early_exit = h->cfg.early_exit;
+            g.add(a, 1, 1);
+        }
+        return record(ACCEPT, g, false, 0, LIE_K_ACCEPT, 0);
+    }
+
+    lie_status round_fp64(const std::vector<Item> &items)
+    {
+        if (items.empty())
+            return LIE_OK;
+        lie_status s;
+        if ((s = group_comm_f64(items, false)) != LIE_OK)
+            return s;
+        if ((s = group_project_f64(items, false, false, true, false)) != LIE_OK)
+            return s;
+        if ((s = group_classify(items, false)) != LIE_OK)
+            return s;
+        verify_first_ = false;
+        if ((s = group_project_f64(items, true, true, false, true)) != LIE_OK)
+            return s;
+        return group_accept(items, false);
+    }
+
+    lie_status round_screen(const std::vector<Item> &items)
+    {
+        if (items.empty())
+            return LIE_OK;
+        Group<lie::CommArgs> lds, glob, rn;
+        Group<lie::GemmArgs> dot, sub;
+        Group<lie::NormArgs> nrm;
+        int dmax = 1;
+        double flc = 0, flp = 0;
+        const int bm = lie::gemm_group_m(true), bn = lie::gemm_group_n(true);
+        for (const Item &it : items) {
+            lie_closure *h = it.h;
+            lie::CommArgs a{h->Vs, h->d, h->cursor, nullptr, nullptr, it.cnt, h->st, h->Hs, h->cand_n2};
+            if (lie::comm_f32_fits_lds(h->d)) {
+                lds.add(a, it.cnt, 1);
+                dmax = std::max(dmax, h->d);
+            } else {
+                const int tiles = (int)((h->D + 255) / 256);
+                glob.add(a, tiles * it.cnt, tiles);
+                rn.add(a, it.cnt, 1);
+            }
+            const int64_t nh = std::min(std::max<int64_t>(it.n_hi, 1), h->cap);
+            lie::GemmArgs g{};
+            g.H = h->Hs;
+            g.cnt = it.cnt;
+            g.V = h->Vs;
+            g.C = h->Cs;
+            g.ldc = lie::coef_ld(nh);
+            g.D = h->D;
+            g.st = h->st;
+            const int mt = (it.cnt + bm - 1) / bm;
+            const int nt = (int)((nh + bn - 1) / bn);
+            dot.add(g, nt * mt, nt);
+            g.normpart = h->normpart_s;
+            g.write_r = 0;
+            const int jt = (int)((h->D + bn - 1) / bn);
+            sub.add(g, jt * mt, jt);
+            nrm.add(lie::NormArgs{h->normpart_s, nullptr, it.cnt, jt, h->st, h->cand_a2, nullptr}, (it.cnt + 255) / 256,
+                    1);
+            flc += 8.0 * h->d * h->d * (double)h->d * it.cnt;
+            flp += 2.0 * (double)h->b_nlo * (double)h->D * it.cnt;
+        }
+        lie_status s = LIE_OK;
+        if ((s = record(COMM_F32, lds, true, dmax, LIE_K_COMM, flc)) != LIE_OK ||
+            (s = record(COMM_F32, glob, false, 0, LIE_K_COMM, lds.empty() ? flc : 0)) != LIE_OK ||
+            (s = record(ROWNORM_F32, rn, false, 0, LIE_K_COMM, 0)) != LIE_OK ||
+            (s = record(DOT_F32, dot, false, 0, LIE_K_DOT, flp)) != LIE_OK ||
+            (s = record(SUB_F32, sub, false, 0, LIE_K_SUB, flp)) != LIE_OK ||
+            (s = record(NORM, nrm, false, 0, LIE_K_REDUCE, 0)) != LIE_OK)
+            return s;
+        if ((s = group_classify(items, true)) != LIE_OK)
+            return s;
+        if ((s = group_comm_f64(items, true)) != LIE_OK)
+            return s;
+        verify_first_ = true;  // first FP64 pass: candidate norms into h2
+        if ((s = group_project_f64(items, false, true, false, true)) != LIE_OK)
+            return s;
+        verify_first_ = false;  // second pass: norms into h2b
+        if ((s = group_project_f64(items, false, true, false, true)) != LIE_OK)
+            return s;
+        return group_accept(items, true);
+    }
+
+    lie_status execute(const Rec &r)
+    {
+        switch (r.kind) {
+        case COMM_F64: return status_of(lie::launch_comm_f64_batched(r.b, r.lds, r.dmax, stream));
+        case COMM_F32: return status_of(lie::launch_comm_f32_batched(r.b, r.lds, r.dmax, stream));
+        case ROWNORM_F32: return status_of(lie::launch_rownorm_f32_batched(r.b, stream));
+        case DOT_F64: return status_of(lie::launch_gemm_dot_batched(r.b, false, stream));
+        case DOT_F32: return status_of(lie::launch_gemm_dot_batched(r.b, true, stream));
+        case SUB_F64: return status_of(lie::launch_gemm_sub_batched(r.b, false, stream));
+        case SUB_F32: return status_of(lie::launch_gemm_sub_batched(r.b, true, stream));
+        case NORM: return status_of(lie::launch_norm_final_batched(r.b, stream));
+        case CLASSIFY: return status_of(lie::launch_classify_batched(r.b, stream));
+        case ACCEPT: return status_of(lie::launch_accept_batched(r.b, stream));
+        }
+        return LIE_OK;
+    }
+    static lie_status status_of(hipError_t e)
+    {
+        if (e == hipSuccess)
+            return LIE_OK;
+        return fail(LIE_ERR_DEVICE, "grouped launch failed: %s", hipGetErrorString(e));
+    }
+
+    // Build every table of the round into the current slot, copy the slot once,
+    // then launch the recorded stages in order.
+    lie_status build_and_launch(const std::vector<Item> &f64, const std::vector<Item> &scr)
+    {
+        recs.clear();
+        used = 0;
+        lie_status s = round_fp64(f64);
+        if (s == LIE_OK)
+            s = round_screen(scr);
+        if (s != LIE_OK)
+            return s;
+        HIP_TRY(hipMemcpyAsync(dev_ring + (size_t)slot * slot_bytes, host_ring + (size_t)slot * slot_bytes, used,
+                               hipMemcpyHostToDevice, stream));
+        for (const Rec &r : recs) {
+            timer.begin(stream);
+            if ((s = execute(r)) != LIE_OK)
+                return s;
+            timer.end(r.kid, stream, r.flops, 0);
+        }
+        HIP_TRY(hipEventRecord(slot_free[slot], stream));
+        slot = (slot + 1) % kSlots;
+        return LIE_OK;
     }
 };
 
@@ -823,25 +1315,66 @@ extern "C" {
 
 lie_status lie_closure_batch_init(lie_closure_batch **out, int32_t n_problems, const double *const *generators,
                                   const int32_t *n_gen, const int32_t *d, const double *tol,
-                                  const lie_closure_config *cfg)
+                                  const lie_closure_config *cfg_in)
 {
+    g_last_error.clear();
     if (!out || !generators || !n_gen || !d || !tol)
         return fail(LIE_ERR_ARG, "NULL argument");
     *out = nullptr;
     if (n_problems < 1)
         return fail(LIE_ERR_ARG, "n_problems must be >= 1");
+    lie_closure_config cfg;
+    lie_status s = resolve_config(cfg_in, &cfg);
+    if (s != LIE_OK)
+        return s;
+    // validate every problem before any device work
+    for (int32_t i = 0; i < n_problems; ++i) {
+        int64_t amb = 0;
+        if ((s = validate_generators(generators[i], n_gen[i], d[i], tol[i], &amb)) != LIE_OK) {
+            std::string msg = g_last_error;
+            return fail(s, "problem %d: %s", i, msg.c_str());
+        }
+    }
     auto *b = new (std::nothrow) lie_closure_batch();
     if (!b)
         return fail(LIE_ERR_OOM, "host allocation failed");
+    int dev = cfg.device;
+    if (dev < 0 && hipGetDevice(&dev) != hipSuccess) {
+        delete b;
+        return fail(LIE_ERR_DEVICE, "hipGetDevice failed");
+    }
+    b->device = dev;
+    if (hipSetDevice(dev) != hipSuccess) {
+        delete b;
+        return fail(LIE_ERR_DEVICE, "hipSetDevice(%d) failed", dev);
+    }
+    if (cfg.stream) {
+        b->stream = (hipStream_t)cfg.stream;
+    } else {
+        if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete b;
+            return fail(LIE_ERR_DEVICE, "hipStreamCreate failed");
+        }
+        b->own_stream = true;
+    }
+    lie_closure_config pc = cfg;
+    pc.stream = b->stream;  // every problem runs on the batch's stream
+    pc.device = dev;
     for (int32_t i = 0; i < n_problems; ++i) {
         lie_closure *h = nullptr;
-        lie_status s = lie_closure_init(&h, generators[i], n_gen[i], d[i], tol[i], cfg);
+        s = lie_closure_init(&h, generators[i], n_gen[i], d[i], tol[i], &pc);
         if (s != LIE_OK) {
             std::string msg = g_last_error;
             delete b;
             return fail(s, "problem %d: %s", i, msg.c_str());
         }
+        h->timer.on = false;  // grouped launches are timed by the batch
         b->probs.push_back(h);
+    }
+    b->timer.on = cfg.profile != 0;
+    if ((s = b->setup()) != LIE_OK) {
+        delete b;
+        return s;
     }
     *out = b;
     return LIE_OK;
@@ -851,12 +1384,7 @@ lie_status lie_closure_batch_run(lie_closure_batch *b)
 {
     if (!b)
         return fail(LIE_ERR_ARG, "batch is NULL");
-    for (size_t i = 0; i < b->probs.size(); ++i) {
-        lie_status s = b->probs[i]->run(-1);
-        if (s != LIE_OK)
-            return s;
-    }
-    return LIE_OK;
+    return b->run();
 }
 
 lie_status lie_closure_batch_dim(const lie_closure_batch *b, int32_t i, int64_t *dim)
@@ -876,9 +1404,52 @@ lie_status lie_closure_batch_basis(const lie_closure_batch *b, int32_t i, double
 
 lie_status lie_closure_batch_stats_get(const lie_closure_batch *b, int32_t i, lie_closure_stats *out)
 {
-    if (!b || i < 0 || i >= (int32_t)b->probs.size())
+    if (!b || i < -1 || i >= (int32_t)b->probs.size())
         return fail(LIE_ERR_ARG, "bad batch index");
-    return lie_closure_stats_get(b->probs[i], out);
+    if (i >= 0)
+        return lie_closure_stats_get(b->probs[i], out);
+    // aggregate over the batch: summed counters, the batch's own launch timers
+    if (!out || out->struct_size != sizeof(lie_closure_stats))
+        return fail(LIE_ERR_ARG, "stats.struct_size must be %zu", sizeof(lie_closure_stats));
+    lie_closure_stats agg;
+    std::memset(&agg, 0, sizeof agg);
+    agg.struct_size = sizeof agg;
+    agg.done = b->done ? 1 : 0;
+    agg.min_accepted_residual = INFINITY;
+    agg.screen_min_independent = INFINITY;
+    for (lie_closure *h : b->probs) {
+        lie_closure_stats one;
+        one.struct_size = sizeof one;
+        lie_closure_stats_get(h, &one);
+        agg.dim += one.dim;
+        agg.ambient += one.ambient;
+        agg.candidates += one.candidates;
+        agg.generator_checks += one.generator_checks;
+        agg.zero_brackets += one.zero_brackets;
+        agg.screen_rejected += one.screen_rejected;
+        agg.fp64_decided += one.fp64_decided;
+        agg.accepted += one.accepted;
+        agg.min_accepted_residual = std::min(agg.min_accepted_residual, one.min_accepted_residual);
+        agg.max_rejected_residual = std::max(agg.max_rejected_residual, one.max_rejected_residual);
+        agg.max_screen_rejected = std::max(agg.max_screen_rejected, one.max_screen_rejected);
+        agg.screen_max_dependent = std::max(agg.screen_max_dependent, one.screen_max_dependent);
+        agg.screen_min_independent = std::min(agg.screen_min_independent, one.screen_min_independent);
+        agg.precision = one.precision;
+        agg.decide = one.decide;
+        agg.block = one.block;
+        agg.early_exit = one.early_exit;
+    }
+    agg.blocks = b->rounds;
+    agg.host_syncs = b->host_syncs;
+    agg.run_ms = b->run_ms;
+    for (int k = 0; k < LIE_K_COUNT; ++k) {
+        agg.kernel_launches[k] = b->timer.n[k];
+        agg.kernel_ms[k] = b->timer.ms[k];
+        agg.kernel_flops[k] = b->timer.flops[k];
+        agg.kernel_bytes[k] = b->timer.bytes[k];
+    }
+    *out = agg;
+    return LIE_OK;
 }
 
 void lie_closure_batch_free(lie_closure_batch *b) { delete b; }

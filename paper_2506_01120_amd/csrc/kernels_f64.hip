@@ -105,14 +105,17 @@ __device__ inline double unp_im(const double *p, int d, int i, int k)
 }
 
 // One workgroup per candidate; both operands unpacked into LDS (d <= 64).
-__global__ void __launch_bounds__(kThreads) k_comm_f64_lds(const double *__restrict__ V, int d, int64_t p0,
-                                                           const int64_t *__restrict__ pair_list,
-                                                           const int *__restrict__ ncnt, int cnt,
-                                                           const DevState *__restrict__ st, double *__restrict__ H)
+__device__ void comm_f64_lds_body(const CommArgs &A, int c)
 {
     extern __shared__ double lds[];
-    const int c = blockIdx.x;
-    if (c >= (ncnt ? *ncnt : cnt) || (st && (st->done | st->numeric_error | st->full)))
+    const double *V = static_cast<const double *>(A.V);
+    const int d = A.d;
+    const int64_t p0 = A.p0;
+    const int64_t *pair_list = A.pair_list;
+    const int cnt = A.cnt;
+    const DevState *st = A.st;
+    double *H = static_cast<double *>(A.H);
+    if (c >= (A.ncnt ? *A.ncnt : cnt) || (st && (st->done | st->numeric_error | st->full)))
         return;
     const int64_t D = (int64_t)d * d;
     int64_t l, m;
@@ -160,22 +163,24 @@ __global__ void __launch_bounds__(kThreads) k_comm_f64_lds(const double *__restr
 }
 
 // Same bracket reading operands directly from global memory (any d).
-__global__ void __launch_bounds__(kThreads) k_comm_f64_global(const double *__restrict__ V, int d, int64_t p0,
-                                                              const int64_t *__restrict__ pair_list,
-                                                              const int *__restrict__ ncnt, int cnt,
-                                                              const DevState *__restrict__ st,
-                                                              double *__restrict__ H)
+__device__ void comm_f64_global_body(const CommArgs &A, int bx, int c)
 {
+    const double *V = static_cast<const double *>(A.V);
+    const int d = A.d;
+    const int64_t p0 = A.p0;
+    const int64_t *pair_list = A.pair_list;
+    const int cnt = A.cnt;
+    const DevState *st = A.st;
+    double *H = static_cast<double *>(A.H);
     const int64_t D = (int64_t)d * d;
-    const int c = blockIdx.y;
-    if (c >= (ncnt ? *ncnt : cnt) || (st && (st->done | st->numeric_error | st->full)))
+    if (c >= (A.ncnt ? *A.ncnt : cnt) || (st && (st->done | st->numeric_error | st->full)))
         return;
     int64_t l, m;
     decode_pair(pair_list ? pair_list[c] : p0 + c, l, m);
     const double *pa = V + l * D, *pb = V + m * D;
     const double so = sqrt(d / 2.0), sd = sqrt((double)d);
     double *out = H + (int64_t)c * D;
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t idx = (int64_t)bx * blockDim.x + threadIdx.x;
     if (idx >= D)
         return;
     const int i = (int)(idx / d), j = (int)(idx % d);
@@ -198,6 +203,25 @@ __global__ void __launch_bounds__(kThreads) k_comm_f64_global(const double *__re
     } else {
         out[i * d + i] = sd * piij;
     }
+}
+
+__global__ void __launch_bounds__(kThreads) k_comm_f64_lds(CommArgs a) { comm_f64_lds_body(a, blockIdx.x); }
+__global__ void __launch_bounds__(kThreads) k_comm_f64_global(CommArgs a)
+{
+    comm_f64_global_body(a, blockIdx.x, blockIdx.y);
+}
+__global__ void __launch_bounds__(kThreads) k_comm_f64_lds_b(Batch b)
+{
+    const int p = batch_find(b.start, b.nprob, blockIdx.x);
+    const CommArgs a = static_cast<const CommArgs *>(b.args)[p];
+    comm_f64_lds_body(a, blockIdx.x - b.start[p]);
+}
+__global__ void __launch_bounds__(kThreads) k_comm_f64_global_b(Batch b)
+{
+    const int p = batch_find(b.start, b.nprob, blockIdx.x);
+    const CommArgs a = static_cast<const CommArgs *>(b.args)[p];
+    const int l = blockIdx.x - b.start[p], gx = b.gx[p];
+    comm_f64_global_body(a, l % gx, l / gx);
 }
 
 // ------------------------------------------------------------------ projection
@@ -366,7 +390,7 @@ int split_k(int64_t D, int cnt, int64_t n_hi)
 // normalised and appended as V[N] (and its FP32 rounding as Vs[N]).
 
 constexpr int kAccThreads = 1024;
-constexpr int kMaxBlock = 1024;
+constexpr int kMaxBlock = 4096;
 
 
 
@@ -380,7 +404,7 @@ __device__ inline void atomic_min_pos(double *addr, double v)
     atomicMin(reinterpret_cast<unsigned long long *>(addr), (unsigned long long)__double_as_longlong(v));
 }
 
-__global__ void __launch_bounds__(kAccThreads) k_accept_f64(AcceptArgs a)
+__device__ void accept_body(const AcceptArgs &a)
 {
     __shared__ double coef[kMaxBlock];
     __shared__ double red[16];
@@ -551,6 +575,20 @@ __global__ void __launch_bounds__(kAccThreads) k_accept_f64(AcceptArgs a)
         st->N = sN;
 }
 
+__global__ void __launch_bounds__(kAccThreads) k_accept_f64(AcceptArgs a) { accept_body(a); }
+__global__ void __launch_bounds__(kAccThreads) k_accept_b(Batch b)
+{
+    const AcceptArgs a = static_cast<const AcceptArgs *>(b.args)[blockIdx.x];
+    accept_body(a);
+}
+
+__global__ void k_gather_states(const DevState *const *src, int n, DevState *dst)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n)
+        dst[i] = *src[i];
+}
+
 // ------------------------------------------------------------------ orthogonality
 
 __global__ void __launch_bounds__(kThreads) k_gram_loss_part(const double *__restrict__ G, int64_t n,
@@ -626,13 +664,62 @@ hipError_t launch_comm_f64(const double *V, int d, int64_t p0, const int64_t *pa
         else
             (void)hipGetLastError();  // clear the failed request; the fallback kernel is used
     }
+    CommArgs a{V, d, p0, pair_list, ncnt, cnt, st, H, nullptr};
     if (d <= 64 && lds <= granted) {
-        hipLaunchKernelGGL(k_comm_f64_lds, dim3(cnt), dim3(kThreads), lds, s, V, d, p0, pair_list, ncnt, cnt, st, H);
+        hipLaunchKernelGGL(k_comm_f64_lds, dim3(cnt), dim3(kThreads), lds, s, a);
     } else {
         const int64_t D = (int64_t)d * d;
         hipLaunchKernelGGL(k_comm_f64_global, dim3((unsigned)((D + kThreads - 1) / kThreads), cnt), dim3(kThreads), 0,
-                           s, V, d, p0, pair_list, ncnt, cnt, st, H);
+                           s, a);
     }
+    return hipGetLastError();
+}
+
+bool comm_f64_fits_lds(int d)
+{
+    if (d > 64)
+        return false;
+    // the first launch of the single-problem kernel raises the limit; mirror its rule
+    int dev = 0, v = 65536;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+        v = 65536;
+    return (size_t)4 * d * (d + 1) * sizeof(double) + 1024 <= (size_t)v;
+}
+
+hipError_t launch_comm_f64_batched(const Batch &b, bool lds_variant, int dmax, hipStream_t s)
+{
+    if (b.total <= 0)
+        return hipSuccess;
+    if (lds_variant) {
+        const size_t lds = (size_t)4 * dmax * (dmax + 1) * sizeof(double);
+        static size_t granted = 65536;
+        if (lds > granted) {
+            if (hipFuncSetAttribute((const void *)k_comm_f64_lds_b, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)lds) != hipSuccess)
+                return hipGetLastError();
+            granted = lds;
+        }
+        hipLaunchKernelGGL(k_comm_f64_lds_b, dim3(b.total), dim3(kThreads), lds, s, b);
+    } else {
+        hipLaunchKernelGGL(k_comm_f64_global_b, dim3(b.total), dim3(kThreads), 0, s, b);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_accept_batched(const Batch &b, hipStream_t s)
+{
+    if (b.nprob <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_accept_b, dim3(b.nprob), dim3(kAccThreads), 0, s, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_states(const DevState *const *src, int n, DevState *dst, hipStream_t s)
+{
+    if (n <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_gather_states, dim3((n + 63) / 64), dim3(64), 0, s, src, n, dst);
     return hipGetLastError();
 }
 

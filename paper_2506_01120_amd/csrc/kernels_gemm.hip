@@ -179,24 +179,11 @@ struct KRowLoader {
     }
 };
 
-struct GemmArgs {
-    const void *H;        // candidate rows (row stride D)
-    const int *rows;      // pass row -> H row (null: identity)
-    const int *nrows;     // device row count (null: cnt)
-    int cnt;
-    const void *V;        // basis (row stride D)
-    void *C;              // coefficients, row stride ldc
-    int64_t ldc;
-    int64_t D;
-    const DevState *st;   // basis size N and abort flags
-    int64_t N_fixed;      // used when st is null
-    double *normpart;     // residual: per (row, column tile) squared norms [rows][tiles][2]
-    int write_r;          // residual: write R over H
-};
+
 
 // ---------------------------------------------------------------- coefficients
 template <typename T, int SM, int SN>
-__global__ void __launch_bounds__(256) k_gemm_dot(GemmArgs g)
+__device__ void gemm_dot_body(const GemmArgs &g, int bx, int by)
 {
     using M = Mma<T>;
     constexpr int BM = 2 * SM * M::E, BN = 2 * SN * M::E;
@@ -205,8 +192,8 @@ __global__ void __launch_bounds__(256) k_gemm_dot(GemmArgs g)
         return;
     const int64_t N = g.st ? g.st->N : g.N_fixed;
     const int Mrows = g.nrows ? *g.nrows : g.cnt;
-    const int64_t n0 = (int64_t)blockIdx.x * BN;
-    const int m0 = blockIdx.y * BM;
+    const int64_t n0 = (int64_t)bx * BN;
+    const int m0 = by * BM;
     if (n0 >= N || m0 >= Mrows)
         return;
     __shared__ T As[2][KC][BM + PAD];
@@ -276,7 +263,7 @@ __global__ void __launch_bounds__(256) k_gemm_dot(GemmArgs g)
 
 // ---------------------------------------------------------------- residual + norms
 template <typename T, int SM, int SN>
-__global__ void __launch_bounds__(256) k_gemm_sub(GemmArgs g)
+__device__ void gemm_sub_body(const GemmArgs &g, int bx, int by, int ntiles)
 {
     using M = Mma<T>;
     constexpr int BM = 2 * SM * M::E, BN = 2 * SN * M::E;
@@ -285,8 +272,8 @@ __global__ void __launch_bounds__(256) k_gemm_sub(GemmArgs g)
         return;
     const int64_t N = g.st ? g.st->N : g.N_fixed;
     const int Mrows = g.nrows ? *g.nrows : g.cnt;
-    const int64_t j0 = (int64_t)blockIdx.x * BN;  // operator columns
-    const int m0 = blockIdx.y * BM;
+    const int64_t j0 = (int64_t)bx * BN;  // operator columns
+    const int m0 = by * BM;
     if (m0 >= Mrows)
         return;
     __shared__ T As[2][KC][BM + PAD];
@@ -382,29 +369,66 @@ __global__ void __launch_bounds__(256) k_gemm_sub(GemmArgs g)
     if (threadIdx.x < BM) {
         const int m = m0 + threadIdx.x;
         if (m < Mrows) {
-            double *o = g.normpart + ((int64_t)m * gridDim.x + blockIdx.x) * 2;
+            double *o = g.normpart + ((int64_t)m * ntiles + bx) * 2;
             o[0] = red[threadIdx.x][0][0] + red[threadIdx.x][1][0];
             o[1] = red[threadIdx.x][0][1] + red[threadIdx.x][1][1];
         }
     }
 }
 
-__global__ void k_gemm_norm_final(const double *__restrict__ normpart, const int *__restrict__ nrows, int cnt,
-                                  int tiles, const DevState *__restrict__ st, double *__restrict__ rho2,
-                                  double *__restrict__ h2)
+template <typename T, int SM, int SN>
+__global__ void __launch_bounds__(256) k_gemm_dot(GemmArgs g)
 {
-    const int m = blockIdx.x * blockDim.x + threadIdx.x;
-    const int Mrows = nrows ? *nrows : cnt;
-    if (m >= Mrows || aborted(st))
+    gemm_dot_body<T, SM, SN>(g, blockIdx.x, blockIdx.y);
+}
+
+template <typename T, int SM, int SN>
+__global__ void __launch_bounds__(256) k_gemm_sub(GemmArgs g)
+{
+    gemm_sub_body<T, SM, SN>(g, blockIdx.x, blockIdx.y, gridDim.x);
+}
+
+template <typename T, int SM, int SN>
+__global__ void __launch_bounds__(256) k_gemm_dot_b(Batch b)
+{
+    const int p = batch_find(b.start, b.nprob, blockIdx.x);
+    const GemmArgs g = static_cast<const GemmArgs *>(b.args)[p];
+    const int l = blockIdx.x - b.start[p], gx = b.gx[p];
+    gemm_dot_body<T, SM, SN>(g, l % gx, l / gx);
+}
+
+template <typename T, int SM, int SN>
+__global__ void __launch_bounds__(256) k_gemm_sub_b(Batch b)
+{
+    const int p = batch_find(b.start, b.nprob, blockIdx.x);
+    const GemmArgs g = static_cast<const GemmArgs *>(b.args)[p];
+    const int l = blockIdx.x - b.start[p], gx = b.gx[p];
+    gemm_sub_body<T, SM, SN>(g, l % gx, l / gx, gx);
+}
+
+__device__ void norm_final_body(const NormArgs &a, int bx)
+{
+    const int m = bx * 256 + threadIdx.x;
+    const int Mrows = a.nrows ? *a.nrows : a.cnt;
+    if (m >= Mrows || aborted(a.st))
         return;
-    double a = 0.0, b = 0.0;
-    for (int t = 0; t < tiles; ++t) {
-        a += normpart[((int64_t)m * tiles + t) * 2];
-        b += normpart[((int64_t)m * tiles + t) * 2 + 1];
+    double s0 = 0.0, s1 = 0.0;
+    for (int t = 0; t < a.tiles; ++t) {
+        s0 += a.normpart[((int64_t)m * a.tiles + t) * 2];
+        s1 += a.normpart[((int64_t)m * a.tiles + t) * 2 + 1];
     }
-    rho2[m] = a;
-    if (h2)
-        h2[m] = b;
+    a.rho2[m] = s0;
+    if (a.h2)
+        a.h2[m] = s1;
+}
+
+__global__ void __launch_bounds__(256) k_gemm_norm_final(NormArgs a) { norm_final_body(a, blockIdx.x); }
+
+__global__ void __launch_bounds__(256) k_norm_final_b(Batch b)
+{
+    const int p = batch_find(b.start, b.nprob, blockIdx.x);
+    const NormArgs a = static_cast<const NormArgs *>(b.args)[p];
+    norm_final_body(a, blockIdx.x - b.start[p]);
 }
 
 template <typename T, int SM, int SN>
@@ -518,8 +542,41 @@ hipError_t launch_norm_final(const double *normpart, const int *nrows, int cnt, 
 {
     if (cnt <= 0)
         return hipSuccess;
-    hipLaunchKernelGGL(k_gemm_norm_final, dim3((cnt + 255) / 256), dim3(256), 0, s, normpart, nrows, cnt, tiles, st,
-                       rho2, h2);
+    NormArgs a{normpart, nrows, cnt, tiles, st, rho2, h2};
+    hipLaunchKernelGGL(k_gemm_norm_final, dim3((cnt + 255) / 256), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+int gemm_group_m(bool) { return 64; }
+int gemm_group_n(bool) { return 64; }
+
+hipError_t launch_gemm_dot_batched(const Batch &b, bool f32, hipStream_t s)
+{
+    if (b.total <= 0)
+        return hipSuccess;
+    if (f32)
+        hipLaunchKernelGGL((k_gemm_dot_b<float, 1, 1>), dim3(b.total), dim3(256), 0, s, b);
+    else
+        hipLaunchKernelGGL((k_gemm_dot_b<double, 2, 2>), dim3(b.total), dim3(256), 0, s, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_gemm_sub_batched(const Batch &b, bool f32, hipStream_t s)
+{
+    if (b.total <= 0)
+        return hipSuccess;
+    if (f32)
+        hipLaunchKernelGGL((k_gemm_sub_b<float, 1, 1>), dim3(b.total), dim3(256), 0, s, b);
+    else
+        hipLaunchKernelGGL((k_gemm_sub_b<double, 2, 2>), dim3(b.total), dim3(256), 0, s, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_norm_final_batched(const Batch &b, hipStream_t s)
+{
+    if (b.total <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_norm_final_b, dim3(b.total), dim3(256), 0, s, b);
     return hipGetLastError();
 }
 

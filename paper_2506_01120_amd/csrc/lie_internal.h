@@ -54,6 +54,83 @@ __host__ __device__ inline void decode_pair(int64_t p, int64_t &l, int64_t &m)
 
 inline int64_t pairs_below(int64_t n) { return n * (n - 1) / 2; }
 
+// ------------------------------------------------------------- grouped (batched) launches
+// One launch serves several problems: workgroup b belongs to problem p with
+// start[p] <= b < start[p+1]; its local index b - start[p] is split into
+// (b_local % gx[p], b_local / gx[p]) for two-dimensional stage grids.  `args`
+// points at nprob argument structs of the stage in device memory.
+struct Batch {
+    const void *args;
+    const int *start;  // nprob + 1 prefix offsets
+    const int *gx;     // per-problem grid width
+    int nprob;
+    int total;         // start[nprob]
+};
+
+__device__ inline int batch_find(const int *start, int n, int b)
+{
+    int lo = 0, hi = n;  // start[lo] <= b < start[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (start[mid] <= b)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+// Per-stage argument structs (one problem each).
+struct CommArgs {
+    const void *V;             // basis rows (double or float, packed layout)
+    int d;
+    int64_t p0;                // pair index of candidate 0 (when pair_list is null)
+    const int64_t *pair_list;  // candidate c -> pair index (null: p0 + c)
+    const int *ncnt;           // device candidate count (null: cnt)
+    int cnt;
+    const DevState *st;
+    void *H;                   // output rows (packed, row stride d*d)
+    double *hs2;               // FP32 bracket: squared norms of the output rows
+};
+
+struct NormArgs {
+    const double *normpart;    // [rows][tiles][2]
+    const int *nrows;
+    int cnt;
+    int tiles;
+    const DevState *st;
+    double *rho2;
+    double *h2;                // may be null
+};
+
+struct ClassifyArgs {
+    const double *a2, *n2;
+    int cnt;
+    int64_t p0;
+    int policy;
+    double thr;
+    const DevState *st;
+    int *rows;
+    int64_t *pairs;
+    int *slot;
+    int *nsurv;
+};
+
+struct GemmArgs {
+    const void *H;        // candidate rows (row stride D)
+    const int *rows;      // pass row -> H row (null: identity)
+    const int *nrows;     // device row count (null: cnt)
+    int cnt;
+    const void *V;        // basis (row stride D)
+    void *C;              // coefficients, row stride ldc
+    int64_t ldc;
+    int64_t D;
+    const DevState *st;   // basis size N and abort flags
+    int64_t N_fixed;      // used when st is null
+    double *normpart;     // residual: per (row, column tile) squared norms [rows][tiles][2]
+    int write_r;          // residual: write R over H
+};
+
 // Candidate policies of the classification kernel (a2: squared residual, n2: squared norm).
 enum Policy {
     POL_ALL = 0,  // every candidate survives
@@ -143,23 +220,31 @@ hipError_t launch_gemm_sub_f64(const double *V, const DevState *st, double *H, c
 // rho2[m] = sum of tile partials of ||R||^2, h2[m] (if non-null) of ||H||^2
 hipError_t launch_norm_final(const double *normpart, const int *nrows, int cnt, int tiles, const DevState *st,
                              double *rho2, double *h2, hipStream_t s);
+// Geometry of the grouped GEMM launches (fixed tiles: FP32 64x64, FP64 64x64).
+int gemm_group_m(bool f32);   // rows per workgroup
+int gemm_group_n(bool f32);   // columns per workgroup
+hipError_t launch_gemm_dot_batched(const Batch &b, bool f32, hipStream_t s);
+hipError_t launch_gemm_sub_batched(const Batch &b, bool f32, hipStream_t s);
+hipError_t launch_norm_final_batched(const Batch &b, hipStream_t s);
+// Grouped versions of the other stage kernels (one workgroup per candidate for the
+// LDS brackets, per (element tile, candidate) for the global ones, per problem for
+// classification and acceptance).
+hipError_t launch_comm_f64_batched(const Batch &b, bool lds_variant, int dmax, hipStream_t s);
+hipError_t launch_comm_f32_batched(const Batch &b, bool lds_variant, int dmax, hipStream_t s);
+hipError_t launch_rownorm_f32_batched(const Batch &b, hipStream_t s);
+hipError_t launch_classify_batched(const Batch &b, hipStream_t s);
+hipError_t launch_accept_batched(const Batch &b, hipStream_t s);
+bool comm_f64_fits_lds(int d);
+bool comm_f32_fits_lds(int d);
+// DevState copies of several problems into one array (for one read-back).
+hipError_t launch_gather_states(const DevState *const *src, int n, DevState *dst, hipStream_t s);
 
 // ------------------------------------------------------------- FP32 screening kernels (kernels_screen.hip)
 // Hs[c] = fp32 packed [Vs_l, Vs_m] for pair p0 + c, hs2[c] = ||Hs[c]||^2.
 hipError_t launch_comm_f32(const float *Vs, int d, int64_t p0, int cnt, const DevState *st, float *Hs, double *hs2,
                            hipStream_t s);
-// C[c][k] = <Hs_c, Vs_k> (FP32 MFMA), leading dimension n_hi.
-hipError_t launch_dot_f32(const float *Vs, const DevState *st, const float *Hs, int cnt, int64_t D, int64_t n_hi,
-                          float *C, hipStream_t s);
-// rs2[c] = ||Hs_c - sum_k C[c][k] Vs_k||^2 (FP32 MFMA, FP64 tile sums); normpart holds cnt * sub_f32_tiles(D).
-int sub_f32_tiles(int64_t D);
-hipError_t launch_sub_f32(const float *Vs, const DevState *st, const float *Hs, const float *C, int64_t n_hi, int cnt,
-                          int64_t D, double *normpart, double *rs2, hipStream_t s);
 // Survivor compaction under a policy (cnt <= 1024).
 hipError_t launch_classify(const double *a2, const double *n2, int cnt, int64_t p0, int policy, double thr,
                            const DevState *st, int *rows, int64_t *pairs, int *slot, int *nsurv, hipStream_t s);
-// Vs[from..N) = fp32(V64[from..N)), N read from the device state; to_hi bounds the grid.
-hipError_t launch_shadow_f32(const double *V64, float *Vs, int64_t D, int64_t from, int64_t to_hi, const DevState *st,
-                             hipStream_t s);
 
 }  // namespace lie

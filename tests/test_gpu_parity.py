@@ -204,3 +204,27 @@ def test_screen_audit_margin_su16():
     assert dim == 255
     print("screen margin:", st["screen_max_dependent"], st["screen_min_independent"])
     assert st["screen_max_dependent"] < 1e-4 < st["screen_min_independent"]
+
+
+@pytest.mark.parametrize("precision,decide,block", [("fp64", "fp64", 2048), ("fp32", "screen", 3000),
+                                                    ("fp32", "strict", 4096)])
+def test_large_blocks_su16(precision, decide, block):
+    """Blocks above 1024 candidates (chunked classification, large acceptance blocks)."""
+    gens = W.rand_pair(16, seed=2)
+    ref = reference(gens, 1e-10, False)
+    dim, v, st, orth = gpu_closure(gens, 1e-10, precision=precision, decide=decide, block=block)
+    assert dim == ref.dim == 255
+    assert st["candidates"] == ref.candidates
+    assert pins.span_distance(v, ref.basis) <= (SPAN_TOL_FP64 if precision == "fp64" else SPAN_TOL_MIXED)
+    assert orth <= ORTH_TOL_FP64
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_adaptive_default_su16(precision):
+    """Default (adaptive) block schedule against the reference."""
+    gens = W.rand_pair(16, seed=2)
+    ref = reference(gens, 1e-10, False)
+    dim, v, st, orth = gpu_closure(gens, 1e-10, precision=precision)
+    assert dim == ref.dim == 255 and st["candidates"] == ref.candidates
+    assert pins.span_distance(v, ref.basis) <= SPAN_TOL_MIXED
+    assert st["block"] < 0  # adaptive
