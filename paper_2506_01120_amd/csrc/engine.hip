@@ -46,6 +46,8 @@ lie_status fail(lie_status st, const char *fmt, ...)
 constexpr int kGemvRows = 16;
 // Default SCREEN reject threshold on the FP32-screened residual (paper norm).
 constexpr double kDefaultTauFp32 = 1e-4;
+// Default SCREEN reject threshold on the split-BF16-screened residual.
+constexpr double kDefaultTauBf16x3 = 1e-2;
 constexpr int kMaxBlock = 4096;
 constexpr int kMaxD = 128;
 
@@ -365,15 +367,19 @@ struct lie_closure {
         HIP_TRY(lie::launch_comm_f32(Vs, d, cursor, cnt, st, Hs, cand_n2, stream));
         timer.end(LIE_K_COMM, stream, 8.0 * dd * dd * dd * c, 3.0 * c * Dd * w);
         const int tile_dot = lie::gemm_tile_f32(cnt, nh), tile_sub = lie::gemm_tile_f32(cnt, D);
+        const bool bf = cfg.precision == LIE_PREC_BF16X3;
         timer.begin(stream);
-        HIP_TRY(lie::launch_gemm_dot_f32(Vs, st, Hs, cnt, D, nh, Cs, tile_dot, stream));
+        HIP_TRY(bf ? lie::launch_gemm_dot_bf16x3(Vs, st, Hs, cnt, D, nh, Cs, tile_dot, stream)
+                   : lie::launch_gemm_dot_f32(Vs, st, Hs, cnt, D, nh, Cs, tile_dot, stream));
         timer.end(LIE_K_DOT, stream, 2.0 * N * Dd * c, (N * Dd + c * Dd + c * N) * w);
         timer.begin(stream);
-        HIP_TRY(lie::launch_gemm_sub_f32(Vs, st, Hs, Cs, nh, cnt, D, normpart_s, tile_sub, stream));
+        HIP_TRY(bf ? lie::launch_gemm_sub_bf16x3(Vs, st, Hs, Cs, nh, cnt, D, normpart_s, tile_sub, stream)
+                   : lie::launch_gemm_sub_f32(Vs, st, Hs, Cs, nh, cnt, D, normpart_s, tile_sub, stream));
         timer.end(LIE_K_SUB, stream, 2.0 * N * Dd * c, (N * Dd + c * N + c * Dd) * w);
         timer.begin(stream);
-        HIP_TRY(lie::launch_norm_final(normpart_s, nullptr, cnt, lie::gemm_sub_tiles_f32(D, tile_sub), st, cand_a2,
-                                       nullptr, stream));
+        HIP_TRY(lie::launch_norm_final(normpart_s, nullptr, cnt,
+                                       bf ? lie::gemm_sub_tiles_bf16(D, tile_sub) : lie::gemm_sub_tiles_f32(D, tile_sub),
+                                       st, cand_a2, nullptr, stream));
         timer.end(LIE_K_REDUCE, stream, 0, 0);
         lie_status s;
         if ((s = classify(cnt, cursor, policy, policy_thr)) != LIE_OK)
@@ -583,10 +589,6 @@ lie_status lie_closure_init(lie_closure **out, const double *generators, int32_t
     }
     h->timer.on = cfg.profile != 0;
     h->screened = cfg.precision != LIE_PREC_FP64;
-    if (cfg.precision == LIE_PREC_BF16X3) {
-        delete h;
-        return fail(LIE_ERR_ARG, "LIE_PREC_BF16X3 is not available in this build");
-    }
     if (h->screened) {
         switch (cfg.decide) {
         case LIE_DECIDE_FP64:
@@ -598,7 +600,8 @@ lie_status lie_closure_init(lie_closure **out, const double *generators, int32_t
             break;
         default:
             h->policy = lie::POL_GE;
-            h->policy_thr = cfg.tau_rej > 0 ? cfg.tau_rej : kDefaultTauFp32;
+            h->policy_thr = cfg.tau_rej > 0 ? cfg.tau_rej
+                                            : (cfg.precision == LIE_PREC_BF16X3 ? kDefaultTauBf16x3 : kDefaultTauFp32);
             break;
         }
     }
@@ -1044,7 +1047,8 @@ struct lie_closure_batch {
     }
 
     // A recorded grouped launch of the round being built.
-    enum Kind { COMM_F64, COMM_F32, ROWNORM_F32, DOT_F64, DOT_F32, SUB_F64, SUB_F32, NORM, CLASSIFY, ACCEPT };
+    enum Kind { COMM_F64, COMM_F32, ROWNORM_F32, DOT_F64, DOT_F32, DOT_BF, SUB_F64, SUB_F32, SUB_BF, NORM, CLASSIFY,
+                ACCEPT };
     struct Rec {
         Kind kind;
         lie::Batch b;
@@ -1200,6 +1204,8 @@ struct lie_closure_batch {
         return group_accept(items, false);
     }
 
+    bool bf_items = false;  // the screened items of this round use split-BF16 GEMMs
+
     lie_status round_screen(const std::vector<Item> &items)
     {
         if (items.empty())
@@ -1246,8 +1252,8 @@ struct lie_closure_batch {
         if ((s = record(COMM_F32, lds, true, dmax, LIE_K_COMM, flc)) != LIE_OK ||
             (s = record(COMM_F32, glob, false, 0, LIE_K_COMM, lds.empty() ? flc : 0)) != LIE_OK ||
             (s = record(ROWNORM_F32, rn, false, 0, LIE_K_COMM, 0)) != LIE_OK ||
-            (s = record(DOT_F32, dot, false, 0, LIE_K_DOT, flp)) != LIE_OK ||
-            (s = record(SUB_F32, sub, false, 0, LIE_K_SUB, flp)) != LIE_OK ||
+            (s = record(bf_items ? DOT_BF : DOT_F32, dot, false, 0, LIE_K_DOT, flp)) != LIE_OK ||
+            (s = record(bf_items ? SUB_BF : SUB_F32, sub, false, 0, LIE_K_SUB, flp)) != LIE_OK ||
             (s = record(NORM, nrm, false, 0, LIE_K_REDUCE, 0)) != LIE_OK)
             return s;
         if ((s = group_classify(items, true)) != LIE_OK)
@@ -1271,6 +1277,8 @@ struct lie_closure_batch {
         case ROWNORM_F32: return status_of(lie::launch_rownorm_f32_batched(r.b, stream));
         case DOT_F64: return status_of(lie::launch_gemm_dot_batched(r.b, false, stream));
         case DOT_F32: return status_of(lie::launch_gemm_dot_batched(r.b, true, stream));
+        case DOT_BF: return status_of(lie::launch_gemm_dot_bf16x3_batched(r.b, stream));
+        case SUB_BF: return status_of(lie::launch_gemm_sub_bf16x3_batched(r.b, stream));
         case SUB_F64: return status_of(lie::launch_gemm_sub_batched(r.b, false, stream));
         case SUB_F32: return status_of(lie::launch_gemm_sub_batched(r.b, true, stream));
         case NORM: return status_of(lie::launch_norm_final_batched(r.b, stream));
@@ -1293,6 +1301,8 @@ struct lie_closure_batch {
         recs.clear();
         used = 0;
         lie_status s = round_fp64(f64);
+        // screened problems share the batch configuration, hence one precision
+        bf_items = !scr.empty() && scr.front().h->cfg.precision == LIE_PREC_BF16X3;
         if (s == LIE_OK)
             s = round_screen(scr);
         if (s != LIE_OK)

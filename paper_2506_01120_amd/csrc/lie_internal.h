@@ -239,6 +239,17 @@ bool comm_f32_fits_lds(int d);
 // DevState copies of several problems into one array (for one read-back).
 hipError_t launch_gather_states(const DevState *const *src, int n, DevState *dst, hipStream_t s);
 
+// ------------------------------------------------------------- split-BF16 projection GEMMs (kernels_bf16.hip)
+// Same contracts as the FP32 coefficient / residual GEMMs; FP32 operands are
+// split into bf16 hi + lo while staged, products are hi*hi + hi*lo + lo*hi.
+int gemm_sub_tiles_bf16(int64_t D, int tile);
+hipError_t launch_gemm_dot_bf16x3(const float *Vs, const DevState *st, const float *Hs, int cnt, int64_t D,
+                                  int64_t n_hi, float *C, int tile, hipStream_t s);
+hipError_t launch_gemm_sub_bf16x3(const float *Vs, const DevState *st, const float *Hs, const float *C, int64_t n_hi,
+                                  int cnt, int64_t D, double *normpart, int tile, hipStream_t s);
+hipError_t launch_gemm_dot_bf16x3_batched(const Batch &b, hipStream_t s);  // 64 x 64 tiles
+hipError_t launch_gemm_sub_bf16x3_batched(const Batch &b, hipStream_t s);
+
 // ------------------------------------------------------------- FP32 screening kernels (kernels_screen.hip)
 // Hs[c] = fp32 packed [Vs_l, Vs_m] for pair p0 + c, hs2[c] = ||Hs[c]||^2.
 hipError_t launch_comm_f32(const float *Vs, int d, int64_t p0, int cnt, const DevState *st, float *Hs, double *hs2,

@@ -33,7 +33,7 @@ def expected_dims(probs):
     return out
 
 
-@pytest.mark.parametrize("precision,decide", [("fp64", "fp64"), ("fp32", "screen")])
+@pytest.mark.parametrize("precision,decide", [("fp64", "fp64"), ("fp32", "screen"), ("bf16x3", "screen")])
 def test_batch64(precision, decide):
     probs = W.batch_problems(tol=1e-8)
     want = expected_dims(probs)

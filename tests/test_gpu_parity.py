@@ -149,7 +149,8 @@ def test_basis_device_matches_host():
 # <= 1e-5 (mixed-precision bar), orthogonality <= 1e-10.
 SPAN_TOL_MIXED = 1e-5
 
-SCREEN_MODES = [("fp32", "fp64"), ("fp32", "strict"), ("fp32", "screen")]
+SCREEN_MODES = [("fp32", "fp64"), ("fp32", "strict"), ("fp32", "screen"),
+                ("bf16x3", "fp64"), ("bf16x3", "strict"), ("bf16x3", "screen")]
 
 
 _REF_CACHE = {}
@@ -197,6 +198,17 @@ def test_screened_su32_early_exit(precision, decide):
                         decide=decide, block=256)
 
 
+@pytest.mark.parametrize("precision,tau", [("fp32", 1e-4), ("bf16x3", 1e-2)])
+def test_screen_audit_margin_su32_early(precision, tau):
+    """Audit of the screen at d=32: the default SCREEN threshold lies between the largest screened
+    residual of a snapshot-dependent candidate and the smallest of a snapshot-independent one."""
+    dim, v, st, _ = gpu_closure(W.rand_pair(32, seed=3), 1e-8, precision=precision, decide="fp64", block=512,
+                                early_exit=True)
+    assert dim == 1023
+    print("screen margin:", precision, st["screen_max_dependent"], st["screen_min_independent"])
+    assert st["screen_max_dependent"] < tau < st["screen_min_independent"]
+
+
 def test_screen_audit_margin_su16():
     """FP64-decided run with the FP32 screen recorded: every dependent candidate screens far below
     every independent one, so the SCREEN threshold separates them."""
@@ -207,7 +219,7 @@ def test_screen_audit_margin_su16():
 
 
 @pytest.mark.parametrize("precision,decide,block", [("fp64", "fp64", 2048), ("fp32", "screen", 3000),
-                                                    ("fp32", "strict", 4096)])
+                                                    ("fp32", "strict", 4096), ("bf16x3", "screen", 4096)])
 def test_large_blocks_su16(precision, decide, block):
     """Blocks above 1024 candidates (chunked classification, large acceptance blocks)."""
     gens = W.rand_pair(16, seed=2)
@@ -219,7 +231,7 @@ def test_large_blocks_su16(precision, decide, block):
     assert orth <= ORTH_TOL_FP64
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3"])
 def test_adaptive_default_su16(precision):
     """Default (adaptive) block schedule against the reference."""
     gens = W.rand_pair(16, seed=2)
