@@ -44,6 +44,8 @@ lie_status fail(lie_status st, const char *fmt, ...)
 
 // Blocks of at most this many rows use the split-K GEMV projection; larger ones the matrix-core GEMMs.
 constexpr int kGemvRows = 16;
+// Block steps enqueued between two synchronisations: growth-size blocks, saturated blocks.
+constexpr int kGrowthQueued = 4;
 // Default SCREEN reject threshold on the FP32-screened residual (paper norm).
 constexpr double kDefaultTauFp32 = 1e-4;
 // Default SCREEN reject threshold on the split-BF16-screened residual.
@@ -178,6 +180,18 @@ struct lie_closure {
     int64_t host_syncs = 0;
     double run_ms = 0;
     KernelTimer timer;
+    // captured steady-state block step (hipGraph), replayed with a device pair cursor
+    int64_t *d_cursor = nullptr;
+    bool cursor_on_device = false;
+    struct {
+        hipGraphExec_t exec = nullptr;
+        int cnt = 0;
+        int64_t n_hi = -1;
+        bool screen = false;
+        int64_t n[LIE_K_COUNT] = {};
+        double flops[LIE_K_COUNT] = {}, bytes[LIE_K_COUNT] = {};
+    } graph;
+    int64_t graph_replays = 0;
     // bookkeeping of the grouped (batched) executor
     int64_t b_nlo = 0, b_qrows = 0, b_lastc = 0, b_lasta = 0;
     int b_cur = 0;
@@ -188,7 +202,10 @@ struct lie_closure {
             (void)hipSetDevice(device);
         if (stream)
             (void)hipStreamSynchronize(stream);
-        for (void *p : {(void *)V64, (void *)Vs, (void *)H64, (void *)Hs, (void *)C, (void *)Cs, (void *)part,
+        if (graph.exec)
+            (void)hipGraphExecDestroy(graph.exec);
+        for (void *p : {(void *)d_cursor, (void *)V64, (void *)Vs, (void *)H64, (void *)Hs, (void *)C, (void *)Cs,
+                        (void *)part,
                         (void *)normpart_s, (void *)cand_a2, (void *)cand_n2, (void *)rho2, (void *)h2, (void *)h2b,
                         (void *)surv_rows, (void *)surv_pairs, (void *)slot, (void *)nsurv, (void *)st,
                         (void *)scalar})
@@ -239,12 +256,14 @@ struct lie_closure {
         lie::ProjShape sh{D, cnt, std::min(std::max<int64_t>(n_hi, 1), cap)};
         const double N = (double)n_lo, Dd = (double)D, c = cnt, w = sizeof(double);
         if (cnt > kGemvRows) {
-            // matrix-core path: coefficients, then residual with fused norms, then the norm sums
+            // matrix-core path: coefficients, then residual with fused norms, then the norm sums;
+            // the coefficient rows span the capacity so that any basis size fits
+            const int64_t ldc = lie::coef_ld(cap);
             timer.begin(stream);
-            HIP_TRY(lie::launch_gemm_dot_f64(V64, st, H64, rows, nrows, cnt, D, sh.n_hi, C, stream));
+            HIP_TRY(lie::launch_gemm_dot_f64(V64, st, H64, rows, nrows, cnt, D, sh.n_hi, ldc, C, stream));
             timer.end(kid_dot, stream, 2.0 * N * Dd * c, (N * Dd + c * Dd + c * N) * w);
             timer.begin(stream);
-            HIP_TRY(lie::launch_gemm_sub_f64(V64, st, H64, rows, nrows, C, sh.n_hi, cnt, D, part, stream));
+            HIP_TRY(lie::launch_gemm_sub_f64(V64, st, H64, rows, nrows, C, sh.n_hi, ldc, cnt, D, part, stream));
             timer.end(kid_sub, stream, 2.0 * N * Dd * c, (N * Dd + c * N + 2.0 * c * Dd) * w);
             timer.begin(stream);
             HIP_TRY(lie::launch_norm_final(part, nrows, cnt, lie::gemm_sub_tiles_f64(D), st, rho2_out, h2_out, stream));
@@ -264,11 +283,11 @@ struct lie_closure {
         return LIE_OK;
     }
 
-    lie_status classify(int cnt, int64_t p0, int pol, double thr)
+    lie_status classify(int cnt, int64_t p0, int pol, double thr, const int64_t *dp0 = nullptr)
     {
         timer.begin(stream);
         HIP_TRY(lie::launch_classify(cand_a2, cand_n2, cnt, p0, pol, thr, st, surv_rows, surv_pairs, slot, nsurv,
-                                     stream));
+                                     stream, dp0));
         timer.end(LIE_K_REDUCE, stream, 0, 0);
         return LIE_OK;
     }
@@ -296,6 +315,7 @@ struct lie_closure {
         a.mode = mode;
         a.screened = screen_first ? 1 : 0;
         a.early_exit = mode == 1 ? cfg.early_exit : 0;
+        a.lds_doubles = lie::accept_lds_doubles(cnt, D);
         timer.begin(stream);
         HIP_TRY(lie::launch_accept_f64(a, stream));
         timer.end(kid, stream, 0, 0);
@@ -338,17 +358,17 @@ struct lie_closure {
     // FP64 block step over pair indices [cursor, cursor + cnt).
     // Bracket work per candidate: one complex d x d product (8 d^3 flops), since
     // [a,b] = ab - (ab)^H for anti-Hermitian a, b; bytes: two operands read, one result written.
-    lie_status step_fp64(int cnt, int64_t n_lo, int64_t n_hi)
+    lie_status step_fp64(int cnt, int64_t n_lo, int64_t n_hi, const int64_t *dp0 = nullptr)
     {
         const double c = cnt, Dd = (double)D, dd = d;
         timer.begin(stream);
-        HIP_TRY(lie::launch_comm_f64(V64, d, cursor, nullptr, nullptr, cnt, st, H64, stream));
+        HIP_TRY(lie::launch_comm_f64(V64, d, cursor, nullptr, nullptr, cnt, st, H64, stream, dp0));
         timer.end(LIE_K_COMM, stream, 8.0 * dd * dd * dd * c, 3.0 * c * Dd * sizeof(double));
         lie_status s;
         if ((s = project(nullptr, nullptr, cand_a2, cand_n2, cnt, n_lo, n_hi, LIE_K_DOT, LIE_K_SUB, LIE_K_REDUCE)) !=
             LIE_OK)
             return s;
-        if ((s = classify(cnt, cursor, lie::POL_ABS, tol)) != LIE_OK)
+        if ((s = classify(cnt, cursor, lie::POL_ABS, tol, dp0)) != LIE_OK)
             return s;
         // re-orthogonalisation pass for the survivors only (twice is enough)
         if ((s = project(surv_rows, nsurv, rho2, h2b, cnt, 0, n_hi, LIE_K_VERIFY, LIE_K_VERIFY, LIE_K_VERIFY)) !=
@@ -359,22 +379,23 @@ struct lie_closure {
 
     // Screened block step: FP32 bracket and projection on MFMA, classification,
     // then FP64 recomputation (bracket + two projection passes) of the survivors.
-    lie_status step_screen(int cnt, int64_t n_lo, int64_t n_hi)
+    lie_status step_screen(int cnt, int64_t n_lo, int64_t n_hi, const int64_t *dp0 = nullptr)
     {
         const double c = cnt, Dd = (double)D, dd = d, N = (double)n_lo, w = sizeof(float);
         const int64_t nh = std::min(std::max<int64_t>(n_hi, 1), cap);
         timer.begin(stream);
-        HIP_TRY(lie::launch_comm_f32(Vs, d, cursor, cnt, st, Hs, cand_n2, stream));
+        HIP_TRY(lie::launch_comm_f32(Vs, d, cursor, cnt, st, Hs, cand_n2, stream, dp0));
         timer.end(LIE_K_COMM, stream, 8.0 * dd * dd * dd * c, 3.0 * c * Dd * w);
         const int tile_dot = lie::gemm_tile_f32(cnt, nh), tile_sub = lie::gemm_tile_f32(cnt, D);
         const bool bf = cfg.precision == LIE_PREC_BF16X3;
+        const int64_t ldc = lie::coef_ld(cap);
         timer.begin(stream);
-        HIP_TRY(bf ? lie::launch_gemm_dot_bf16x3(Vs, st, Hs, cnt, D, nh, Cs, tile_dot, stream)
-                   : lie::launch_gemm_dot_f32(Vs, st, Hs, cnt, D, nh, Cs, tile_dot, stream));
+        HIP_TRY(bf ? lie::launch_gemm_dot_bf16x3(Vs, st, Hs, cnt, D, nh, ldc, Cs, tile_dot, stream)
+                   : lie::launch_gemm_dot_f32(Vs, st, Hs, cnt, D, nh, ldc, Cs, tile_dot, stream));
         timer.end(LIE_K_DOT, stream, 2.0 * N * Dd * c, (N * Dd + c * Dd + c * N) * w);
         timer.begin(stream);
-        HIP_TRY(bf ? lie::launch_gemm_sub_bf16x3(Vs, st, Hs, Cs, nh, cnt, D, normpart_s, tile_sub, stream)
-                   : lie::launch_gemm_sub_f32(Vs, st, Hs, Cs, nh, cnt, D, normpart_s, tile_sub, stream));
+        HIP_TRY(bf ? lie::launch_gemm_sub_bf16x3(Vs, st, Hs, Cs, nh, ldc, cnt, D, normpart_s, tile_sub, stream)
+                   : lie::launch_gemm_sub_f32(Vs, st, Hs, Cs, nh, ldc, cnt, D, normpart_s, tile_sub, stream));
         timer.end(LIE_K_SUB, stream, 2.0 * N * Dd * c, (N * Dd + c * N + c * Dd) * w);
         timer.begin(stream);
         HIP_TRY(lie::launch_norm_final(normpart_s, nullptr, cnt,
@@ -382,7 +403,7 @@ struct lie_closure {
                                        st, cand_a2, nullptr, stream));
         timer.end(LIE_K_REDUCE, stream, 0, 0);
         lie_status s;
-        if ((s = classify(cnt, cursor, policy, policy_thr)) != LIE_OK)
+        if ((s = classify(cnt, cursor, policy, policy_thr, dp0)) != LIE_OK)
             return s;
         timer.begin(stream);
         HIP_TRY(lie::launch_comm_f64(V64, d, 0, surv_pairs, nsurv, cnt, st, H64, stream));
@@ -392,6 +413,77 @@ struct lie_closure {
         if ((s = project(nullptr, nsurv, rho2, h2b, cnt, 0, n_hi, LIE_K_VERIFY, LIE_K_VERIFY, LIE_K_VERIFY)) != LIE_OK)
             return s;
         return accept(cnt, 1, policy != lie::POL_ALL, nullptr, h2, LIE_K_ACCEPT);
+    }
+
+    // Capture one block step (kernels reading the pair cursor from d_cursor, then
+    // the cursor advance) and instantiate it; the work counters of the captured
+    // launches are kept so that each replay can be accounted.
+    lie_status capture(int cnt, int64_t n_lo, int64_t n_hi, bool screen)
+    {
+        if (graph.exec) {
+            HIP_TRY(hipGraphExecDestroy(graph.exec));
+            graph.exec = nullptr;
+        }
+        int64_t n0[LIE_K_COUNT];
+        double f0[LIE_K_COUNT], b0[LIE_K_COUNT];
+        std::memcpy(n0, timer.n, sizeof n0);
+        std::memcpy(f0, timer.flops, sizeof f0);
+        std::memcpy(b0, timer.bytes, sizeof b0);
+        HIP_TRY(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+        lie_status s = screen ? step_screen(cnt, n_lo, n_hi, d_cursor) : step_fp64(cnt, n_lo, n_hi, d_cursor);
+        hipError_t e = s == LIE_OK ? lie::launch_advance_cursor(d_cursor, cnt, stream) : hipSuccess;
+        hipGraph_t g = nullptr;
+        hipError_t e2 = hipStreamEndCapture(stream, &g);
+        for (int k = 0; k < LIE_K_COUNT; ++k) {
+            graph.n[k] = timer.n[k] - n0[k];
+            graph.flops[k] = timer.flops[k] - f0[k];
+            graph.bytes[k] = timer.bytes[k] - b0[k];
+        }
+        std::memcpy(timer.n, n0, sizeof n0);  // capture executes nothing
+        std::memcpy(timer.flops, f0, sizeof f0);
+        std::memcpy(timer.bytes, b0, sizeof b0);
+        if (s != LIE_OK) {
+            if (g)
+                (void)hipGraphDestroy(g);
+            return s;
+        }
+        if (e != hipSuccess || e2 != hipSuccess) {
+            if (g)
+                (void)hipGraphDestroy(g);
+            return fail(LIE_ERR_DEVICE, "graph capture failed: %s",
+                        hipGetErrorString(e != hipSuccess ? e : e2));
+        }
+        hipError_t e3 = hipGraphInstantiate(&graph.exec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e3 != hipSuccess) {
+            graph.exec = nullptr;
+            return fail(LIE_ERR_DEVICE, "graph instantiation failed: %s", hipGetErrorString(e3));
+        }
+        graph.cnt = cnt;
+        graph.n_hi = n_hi;
+        graph.screen = screen;
+        return LIE_OK;
+    }
+
+    lie_status replay(int cnt, int64_t n_lo, int64_t n_hi, bool screen)
+    {
+        if (!graph.exec || graph.cnt != cnt || graph.n_hi != n_hi || graph.screen != screen) {
+            lie_status s = capture(cnt, n_lo, n_hi, screen);
+            if (s != LIE_OK)
+                return s;
+        }
+        if (!cursor_on_device) {
+            HIP_TRY(lie::launch_set_cursor(d_cursor, cursor, stream));
+            cursor_on_device = true;
+        }
+        HIP_TRY(hipGraphLaunch(graph.exec, stream));
+        for (int k = 0; k < LIE_K_COUNT; ++k) {
+            timer.n[k] += graph.n[k];
+            timer.flops[k] += graph.flops[k];
+            timer.bytes[k] += graph.bytes[k];
+        }
+        ++graph_replays;
+        return LIE_OK;
     }
 
     lie_status run(int64_t budget)
@@ -413,17 +505,22 @@ struct lie_closure {
         for (;;) {
             int64_t avail = lie::pairs_below(n_lo);
             const bool over_budget = budget >= 0 && spent >= budget;
-            if (cursor >= avail || queued >= kMaxQueued || over_budget) {
+            // growth-size blocks are re-evaluated often; saturated ones can queue deep
+            const int max_queued = (block == 0 && cur == block_growth) ? kGrowthQueued : kMaxQueued;
+            if (cursor >= avail || queued >= max_queued || over_budget) {
                 if ((s = sync_state()) != LIE_OK || (s = check_state()) != LIE_OK)
                     break;
                 queued = 0;
                 queued_rows = 0;
                 n_lo = hs.N;
                 if (block == 0) {
-                    // adaptive block: small while candidates are mostly accepted, large otherwise
+                    // adaptive block: small while candidates are mostly accepted, large otherwise;
+                    // a basis at the ambient bound cannot grow, so it is saturated at once
                     const int64_t dc = hs.n_cand - last_cand, da = hs.n_acc - last_acc;
                     if (dc > 0)
                         cur = 8 * da > dc ? block_growth : block_sat;
+                    if (n_lo >= ambient)
+                        cur = block_sat;
                     last_cand = hs.n_cand;
                     last_acc = hs.n_acc;
                 }
@@ -441,7 +538,16 @@ struct lie_closure {
             const int64_t n_hi = std::min<int64_t>(cap, n_lo + queued_rows);
             // while most candidates are accepted the screen filters nothing: decide in FP64 directly
             const bool growth = block == 0 && cur == block_growth;
-            s = (screened && !growth) ? step_screen(cnt, n_lo, n_hi) : step_fp64(cnt, n_lo, n_hi);
+            const bool screen_step = screened && !growth;
+            // full-size steps of the steady state replay a captured graph; the grid bound
+            // is the synchronised basis size (the coefficient GEMMs stride beyond it)
+            const bool steady = cnt == cur && !growth && cnt > kGemvRows && cfg.use_graphs && !timer.on;
+            if (steady) {
+                s = replay(cnt, n_lo, std::max<int64_t>(n_lo, 1), screen_step);
+            } else {
+                s = screen_step ? step_screen(cnt, n_lo, n_hi) : step_fp64(cnt, n_lo, n_hi);
+                cursor_on_device = false;
+            }
             if (s != LIE_OK)
                 break;
             cursor += cnt;
@@ -633,6 +739,15 @@ lie_status lie_closure_init(lie_closure **out, const double *generators, int32_t
         h->own_stream = true;
     }
     const int64_t D = h->D;
+    {
+        const int maxb = lie::accept_max_block(D);
+        if (h->block > maxb)
+            return bail(fail(LIE_ERR_ARG, "block %d is too large for d = %d (at most %d)", h->block, d, maxb));
+        if (h->block == 0) {
+            h->block_sat = std::min(h->block_sat, maxb);
+            h->block_growth = std::min(h->block_growth, h->block_sat);
+        }
+    }
     const int b = h->block > 0 ? h->block : std::max(h->block_growth, h->block_sat);
     h->bmax = b;
     auto alloc = [&](auto **p, size_t n) -> lie_status {
@@ -654,6 +769,7 @@ lie_status lie_closure_init(lie_closure **out, const double *generators, int32_t
         (s = alloc(&h->h2b, bmax)) != LIE_OK || (s = alloc(&h->surv_rows, bmax)) != LIE_OK ||
         (s = alloc(&h->surv_pairs, bmax)) != LIE_OK || (s = alloc(&h->slot, bmax)) != LIE_OK ||
         (s = alloc(&h->nsurv, 1)) != LIE_OK || (s = alloc(&h->scalar, 1)) != LIE_OK ||
+        (s = alloc(&h->d_cursor, 1)) != LIE_OK ||
         (s = alloc(&h->st, 1)) != LIE_OK)
         return bail(s);
     if (h->screened) {
@@ -961,6 +1077,8 @@ struct lie_closure_batch {
                 const int64_t dc = h->hs.n_cand - h->b_lastc, da = h->hs.n_acc - h->b_lasta;
                 if (dc > 0)
                     h->b_cur = 8 * da > dc ? h->block_growth : h->block_sat;
+                if (h->b_nlo >= h->ambient)
+                    h->b_cur = h->block_sat;
                 h->b_lastc = h->hs.n_cand;
                 h->b_lasta = h->hs.n_acc;
             }
@@ -999,9 +1117,17 @@ struct lie_closure_batch {
         lie_status s = LIE_OK;
         for (;;) {
             bool need = queued >= kMaxQueued;
-            for (lie_closure *h : probs)
-                if (!h->done && !h->failed && h->cursor >= lie::pairs_below(h->b_nlo))
+            bool growing = false;
+            for (lie_closure *h : probs) {
+                if (h->done || h->failed)
+                    continue;
+                if (h->cursor >= lie::pairs_below(h->b_nlo))
                     need = true;
+                if (h->block == 0 && h->b_cur == h->block_growth)
+                    growing = true;
+            }
+            if (growing && queued >= kGrowthQueued)
+                need = true;
             if (need) {
                 if ((s = sync_all()) != LIE_OK)
                     break;
@@ -1056,6 +1182,7 @@ struct lie_closure_batch {
         int dmax;
         int kid;
         double flops;
+        int64_t lds_doubles;
     };
     std::vector<Rec> recs;
 
@@ -1064,7 +1191,9 @@ struct lie_closure_batch {
     {
         if (g.empty())
             return LIE_OK;
-        Rec r{kind, {}, lds, dmax, kid, flops};
+        Rec r{kind, {}, lds, dmax, kid, flops, 0};
+        if constexpr (std::is_same<A, lie::AcceptArgs>::value)
+            r.lds_doubles = g.args.front().lds_doubles;
         lie_status s = make(g, &r.b);
         if (s != LIE_OK)
             return s;
@@ -1080,8 +1209,9 @@ struct lie_closure_batch {
         double fl = 0;
         for (const Item &it : items) {
             lie_closure *h = it.h;
-            lie::CommArgs a{h->V64, h->d, from_survivors ? 0 : h->cursor, from_survivors ? h->surv_pairs : nullptr,
-                            from_survivors ? h->nsurv : nullptr, it.cnt, h->st, h->H64, nullptr};
+            lie::CommArgs a{h->V64,          h->d,        from_survivors ? 0 : h->cursor,
+                            from_survivors ? h->surv_pairs : nullptr, nullptr,
+                            from_survivors ? h->nsurv : nullptr,      it.cnt, h->st, h->H64, nullptr};
             if (lie::comm_f64_fits_lds(h->d)) {
                 lds.add(a, it.cnt, 1);
                 dmax = std::max(dmax, h->d);
@@ -1117,7 +1247,7 @@ struct lie_closure_batch {
             g.cnt = it.cnt;
             g.V = h->V64;
             g.C = h->C;
-            g.ldc = lie::coef_ld(nh);
+            g.ldc = lie::coef_ld(h->cap);
             g.D = h->D;
             g.st = h->st;
             const int mt = (it.cnt + bm - 1) / bm;
@@ -1149,8 +1279,8 @@ struct lie_closure_batch {
             lie_closure *h = it.h;
             const int pol = screen ? h->policy : lie::POL_ABS;
             const double thr = screen ? h->policy_thr : h->tol;
-            g.add(lie::ClassifyArgs{h->cand_a2, h->cand_n2, it.cnt, h->cursor, pol, thr, h->st, h->surv_rows,
-                                    h->surv_pairs, h->slot, h->nsurv},
+            g.add(lie::ClassifyArgs{h->cand_a2, h->cand_n2, it.cnt, h->cursor, nullptr, pol, thr, h->st,
+                                    h->surv_rows, h->surv_pairs, h->slot, h->nsurv},
                   1, 1);
         }
         return record(CLASSIFY, g, false, 0, LIE_K_REDUCE, 0);
@@ -1159,6 +1289,7 @@ struct lie_closure_batch {
     lie_status group_accept(const std::vector<Item> &items, bool screen)
     {
         Group<lie::AcceptArgs> g;
+        int64_t lds_acc = 0;
         for (const Item &it : items) {
             lie_closure *h = it.h;
             lie::AcceptArgs a{};
@@ -1182,8 +1313,12 @@ struct lie_closure_batch {
             a.mode = 1;
             a.screened = screen && h->policy != lie::POL_ALL ? 1 : 0;
             a.early_exit = h->cfg.early_exit;
+            a.lds_doubles = 0;  // set below to the launch-wide size
             g.add(a, 1, 1);
+            lds_acc = std::max<int64_t>(lds_acc, lie::accept_lds_doubles(it.cnt, h->D));
         }
+        for (auto &a : g.args)
+            a.lds_doubles = lds_acc;
         return record(ACCEPT, g, false, 0, LIE_K_ACCEPT, 0);
     }
 
@@ -1218,7 +1353,7 @@ struct lie_closure_batch {
         const int bm = lie::gemm_group_m(true), bn = lie::gemm_group_n(true);
         for (const Item &it : items) {
             lie_closure *h = it.h;
-            lie::CommArgs a{h->Vs, h->d, h->cursor, nullptr, nullptr, it.cnt, h->st, h->Hs, h->cand_n2};
+            lie::CommArgs a{h->Vs, h->d, h->cursor, nullptr, nullptr, nullptr, it.cnt, h->st, h->Hs, h->cand_n2};
             if (lie::comm_f32_fits_lds(h->d)) {
                 lds.add(a, it.cnt, 1);
                 dmax = std::max(dmax, h->d);
@@ -1233,7 +1368,7 @@ struct lie_closure_batch {
             g.cnt = it.cnt;
             g.V = h->Vs;
             g.C = h->Cs;
-            g.ldc = lie::coef_ld(nh);
+            g.ldc = lie::coef_ld(h->cap);
             g.D = h->D;
             g.st = h->st;
             const int mt = (it.cnt + bm - 1) / bm;
@@ -1283,7 +1418,7 @@ struct lie_closure_batch {
         case SUB_F32: return status_of(lie::launch_gemm_sub_batched(r.b, true, stream));
         case NORM: return status_of(lie::launch_norm_final_batched(r.b, stream));
         case CLASSIFY: return status_of(lie::launch_classify_batched(r.b, stream));
-        case ACCEPT: return status_of(lie::launch_accept_batched(r.b, stream));
+        case ACCEPT: return status_of(lie::launch_accept_batched(r.b, r.lds_doubles, stream));
         }
         return LIE_OK;
     }

@@ -172,7 +172,7 @@ __device__ inline void mma_chunk(const Tiles<SM, SN> &t, int buf, int wm, int wn
 }
 
 template <int SM, int SN>
-__device__ void bf_dot_body(const GemmArgs &g, int bx, int by)
+__device__ void bf_dot_body(const GemmArgs &g, int bx0, int by, int gxs)
 {
     using TT = Tiles<SM, SN>;
     constexpr int BM = TT::BM, BN = TT::BN;
@@ -180,9 +180,8 @@ __device__ void bf_dot_body(const GemmArgs &g, int bx, int by)
         return;
     const int64_t N = g.st ? g.st->N : g.N_fixed;
     const int Mrows = g.nrows ? *g.nrows : g.cnt;
-    const int64_t n0 = (int64_t)bx * BN;
     const int m0 = by * BM;
-    if (n0 >= N || m0 >= Mrows)
+    if ((int64_t)bx0 * BN >= N || m0 >= Mrows)
         return;
     __shared__ TT t;
     const float *H = static_cast<const float *>(g.H);
@@ -192,43 +191,45 @@ __device__ void bf_dot_body(const GemmArgs &g, int bx, int by)
     SplitRowLoader<BN> lb;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int wm = w >> 1, wn = w & 1;
-    f32x16 acc[SM][SN];
+    for (int64_t n0 = (int64_t)bx0 * BN; n0 < N; n0 += (int64_t)gxs * BN) {
+        f32x16 acc[SM][SN];
 #pragma unroll
-    for (int i = 0; i < SM; ++i)
+        for (int i = 0; i < SM; ++i)
 #pragma unroll
-        for (int j = 0; j < SN; ++j)
-            acc[i][j] = f32x16{};
-    const int nchunks = (int)((g.D + KC - 1) / KC);
-    la.load(H, g.D, m0, Mrows, 0, g.D, vec_ok);
-    lb.load(V, g.D, n0, N, 0, g.D, vec_ok);
-    la.store(t.Ah[0], t.Al[0]);
-    lb.store(t.Bh[0], t.Bl[0]);
-    __syncthreads();
-    for (int c = 0; c < nchunks; ++c) {
-        const int buf = c & 1;
-        if (c + 1 < nchunks) {
-            la.load(H, g.D, m0, Mrows, (int64_t)(c + 1) * KC, g.D, vec_ok);
-            lb.load(V, g.D, n0, N, (int64_t)(c + 1) * KC, g.D, vec_ok);
-        }
-        mma_chunk<SM, SN>(t, buf, wm, wn, lane, acc);
-        if (c + 1 < nchunks) {
-            la.store(t.Ah[buf ^ 1], t.Al[buf ^ 1]);
-            lb.store(t.Bh[buf ^ 1], t.Bl[buf ^ 1]);
-        }
+            for (int j = 0; j < SN; ++j)
+                acc[i][j] = f32x16{};
+        const int nchunks = (int)((g.D + KC - 1) / KC);
+        la.load(H, g.D, m0, Mrows, 0, g.D, vec_ok);
+        lb.load(V, g.D, n0, N, 0, g.D, vec_ok);
+        la.store(t.Ah[0], t.Al[0]);
+        lb.store(t.Bh[0], t.Bl[0]);
         __syncthreads();
-    }
-    float *C = static_cast<float *>(g.C);
-#pragma unroll
-    for (int i = 0; i < SM; ++i)
-#pragma unroll
-        for (int j = 0; j < SN; ++j)
-#pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int m = m0 + wm * SM * 32 + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-                const int64_t n = n0 + wn * SN * 32 + j * 32 + (lane & 31);
-                if (m < Mrows && n < N)
-                    C[(int64_t)m * g.ldc + n] = acc[i][j][r];
+        for (int c = 0; c < nchunks; ++c) {
+            const int buf = c & 1;
+            if (c + 1 < nchunks) {
+                la.load(H, g.D, m0, Mrows, (int64_t)(c + 1) * KC, g.D, vec_ok);
+                lb.load(V, g.D, n0, N, (int64_t)(c + 1) * KC, g.D, vec_ok);
             }
+            mma_chunk<SM, SN>(t, buf, wm, wn, lane, acc);
+            if (c + 1 < nchunks) {
+                la.store(t.Ah[buf ^ 1], t.Al[buf ^ 1]);
+                lb.store(t.Bh[buf ^ 1], t.Bl[buf ^ 1]);
+            }
+            __syncthreads();
+        }
+        float *C = static_cast<float *>(g.C);
+#pragma unroll
+        for (int i = 0; i < SM; ++i)
+#pragma unroll
+            for (int j = 0; j < SN; ++j)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int m = m0 + wm * SM * 32 + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                    const int64_t n = n0 + wn * SN * 32 + j * 32 + (lane & 31);
+                    if (m < Mrows && n < N)
+                        C[(int64_t)m * g.ldc + n] = acc[i][j][r];
+                }
+    }
 }
 
 template <int SM, int SN>
@@ -324,7 +325,7 @@ __device__ void bf_sub_body(const GemmArgs &g, int bx, int by, int ntiles)
 template <int SM, int SN>
 __global__ void __launch_bounds__(256) k_bf_dot(GemmArgs g)
 {
-    bf_dot_body<SM, SN>(g, blockIdx.x, blockIdx.y);
+    bf_dot_body<SM, SN>(g, blockIdx.x, blockIdx.y, gridDim.x);
 }
 template <int SM, int SN>
 __global__ void __launch_bounds__(256) k_bf_sub(GemmArgs g)
@@ -337,7 +338,7 @@ __global__ void __launch_bounds__(256) k_bf_dot_b(Batch b)
     const int p = batch_find(b.start, b.nprob, blockIdx.x);
     const GemmArgs g = static_cast<const GemmArgs *>(b.args)[p];
     const int l = blockIdx.x - b.start[p], gx = b.gx[p];
-    bf_dot_body<SM, SN>(g, l % gx, l / gx);
+    bf_dot_body<SM, SN>(g, l % gx, l / gx, gx);
 }
 template <int SM, int SN>
 __global__ void __launch_bounds__(256) k_bf_sub_b(Batch b)
@@ -353,7 +354,7 @@ __global__ void __launch_bounds__(256) k_bf_sub_b(Batch b)
 int gemm_sub_tiles_bf16(int64_t D, int tile) { return (int)((D + (tile == 2 ? 128 : 64) - 1) / (tile == 2 ? 128 : 64)); }
 
 hipError_t launch_gemm_dot_bf16x3(const float *Vs, const DevState *st, const float *Hs, int cnt, int64_t D,
-                                  int64_t n_hi, float *C, int tile, hipStream_t s)
+                                  int64_t n_hi, int64_t ldc, float *C, int tile, hipStream_t s)
 {
     if (cnt <= 0)
         return hipSuccess;
@@ -362,7 +363,7 @@ hipError_t launch_gemm_dot_bf16x3(const float *Vs, const DevState *st, const flo
     g.cnt = cnt;
     g.V = Vs;
     g.C = C;
-    g.ldc = coef_ld(n_hi);
+    g.ldc = ldc;
     g.D = D;
     g.st = st;
     n_hi = std::max<int64_t>(n_hi, 1);
@@ -375,7 +376,7 @@ hipError_t launch_gemm_dot_bf16x3(const float *Vs, const DevState *st, const flo
 }
 
 hipError_t launch_gemm_sub_bf16x3(const float *Vs, const DevState *st, const float *Hs, const float *C, int64_t n_hi,
-                                  int cnt, int64_t D, double *normpart, int tile, hipStream_t s)
+                                  int64_t ldc, int cnt, int64_t D, double *normpart, int tile, hipStream_t s)
 {
     if (cnt <= 0)
         return hipSuccess;
@@ -384,7 +385,7 @@ hipError_t launch_gemm_sub_bf16x3(const float *Vs, const DevState *st, const flo
     g.cnt = cnt;
     g.V = Vs;
     g.C = const_cast<float *>(C);
-    g.ldc = coef_ld(n_hi);
+    g.ldc = ldc;
     g.D = D;
     g.st = st;
     g.normpart = normpart;

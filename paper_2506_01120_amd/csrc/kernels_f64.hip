@@ -12,6 +12,17 @@ namespace {
 
 constexpr int kThreads = 256;
 
+// Workgroup barrier that orders LDS traffic only: it waits for this wave's LDS
+// operations (lgkmcnt = 0) but not for outstanding global loads or stores, so a
+// prefetch or a result store in flight does not stall every barrier.  Use it
+// only where no thread reads global data another thread of the workgroup just wrote.
+// s_waitcnt encoding (gfx9): vmcnt[3:0] | expcnt[6:4] | lgkmcnt[11:8] | vmcnt[5:4] << 14.
+__device__ inline void lds_barrier()
+{
+    __builtin_amdgcn_s_waitcnt(0xC07F);  // vmcnt = 63, expcnt = 7, lgkmcnt = 0
+    __builtin_amdgcn_s_barrier();
+}
+
 __device__ inline double wave_sum(double v)
 {
     for (int off = 32; off > 0; off >>= 1)
@@ -110,7 +121,7 @@ __device__ void comm_f64_lds_body(const CommArgs &A, int c)
     extern __shared__ double lds[];
     const double *V = static_cast<const double *>(A.V);
     const int d = A.d;
-    const int64_t p0 = A.p0;
+    const int64_t p0 = A.dp0 ? *A.dp0 : A.p0;
     const int64_t *pair_list = A.pair_list;
     const int cnt = A.cnt;
     const DevState *st = A.st;
@@ -167,7 +178,7 @@ __device__ void comm_f64_global_body(const CommArgs &A, int bx, int c)
 {
     const double *V = static_cast<const double *>(A.V);
     const int d = A.d;
-    const int64_t p0 = A.p0;
+    const int64_t p0 = A.dp0 ? *A.dp0 : A.p0;
     const int64_t *pair_list = A.pair_list;
     const int cnt = A.cnt;
     const DevState *st = A.st;
@@ -404,17 +415,26 @@ __device__ inline void atomic_min_pos(double *addr, double v)
     atomicMin(reinterpret_cast<unsigned long long *>(addr), (unsigned long long)__double_as_longlong(v));
 }
 
+// Dynamic LDS layout of the acceptance kernel: coef[cnt] | R[D] | slots x D
+// cached copies of the vectors appended earlier in the block (the rest are
+// read from the basis in global memory).
 __device__ void accept_body(const AcceptArgs &a)
 {
-    __shared__ double coef[kMaxBlock];
+    extern __shared__ double dyn[];
     __shared__ double red[16];
     __shared__ int64_t sN;
     __shared__ int stop, verdict, ns;
     __shared__ double rr_s;
     __shared__ unsigned long long s_cnt[4];  // zero, screen_rej, fp64_rej, nonfinite
     __shared__ double s_max[2];              // max rejected FP64 residual, max screen-rejected residual
+    __shared__ double gacc[1024];            // per-group partial sums of the in-block subtraction (G * D <= 1024)
     DevState *st = a.st;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int64_t D = a.D;
+    double *coef = dyn;
+    double *R = dyn + a.cnt;
+    double *cache = R + D;
+    const int64_t slots = a.lds_doubles > a.cnt + D ? (a.lds_doubles - a.cnt - D) / D : 0;
     if (threadIdx.x == 0) {
         sN = st->N;
         stop = aborted(st);
@@ -427,20 +447,40 @@ __device__ void accept_body(const AcceptArgs &a)
     if (stop)
         return;
     // ---- phase A
-    for (int c = threadIdx.x; c < a.cnt; c += blockDim.x) {
-        if (a.slot[c] >= 0)
-            continue;
-        const double r = sqrt(a.cand_a2[c]), h = sqrt(a.cand_n2[c]);
-        if (!isfinite(r) || !isfinite(h)) {
-            atomicAdd(&s_cnt[3], 1ull);
-        } else if (h == 0.0) {
-            atomicAdd(&s_cnt[0], 1ull);
-        } else if (a.screened) {
-            atomicAdd(&s_cnt[1], 1ull);
-            atomic_max_pos(&s_max[1], r);
-        } else {
-            atomicAdd(&s_cnt[2], 1ull);
-            atomic_max_pos(&s_max[0], r);
+    {
+        unsigned long long k0 = 0, k1 = 0, k2 = 0, k3 = 0;
+        double m0 = 0.0, m1 = 0.0;
+        for (int c = threadIdx.x; c < a.cnt; c += blockDim.x) {
+            if (a.slot[c] >= 0)
+                continue;
+            const double r = sqrt(a.cand_a2[c]), h = sqrt(a.cand_n2[c]);
+            if (!isfinite(r) || !isfinite(h)) {
+                ++k3;
+            } else if (h == 0.0) {
+                ++k0;
+            } else if (a.screened) {
+                ++k1;
+                m1 = fmax(m1, r);
+            } else {
+                ++k2;
+                m0 = fmax(m0, r);
+            }
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            k0 += __shfl_down(k0, off, 64);
+            k1 += __shfl_down(k1, off, 64);
+            k2 += __shfl_down(k2, off, 64);
+            k3 += __shfl_down(k3, off, 64);
+            m0 = fmax(m0, __shfl_down(m0, off, 64));
+            m1 = fmax(m1, __shfl_down(m1, off, 64));
+        }
+        if (lane == 0) {
+            atomicAdd(&s_cnt[0], k0);
+            atomicAdd(&s_cnt[1], k1);
+            atomicAdd(&s_cnt[2], k2);
+            atomicAdd(&s_cnt[3], k3);
+            atomic_max_pos(&s_max[0], m0);
+            atomic_max_pos(&s_max[1], m1);
         }
     }
     __syncthreads();
@@ -461,76 +501,187 @@ __device__ void accept_body(const AcceptArgs &a)
     if (stop)
         return;
     // ---- phase B
+    // per-survivor scalars go to LDS first, counters stay in LDS until the end,
+    // and the next survivor's residual is prefetched into registers
     const int64_t N0 = sN;
-    for (int r = 0; r < ns; ++r) {
-        __syncthreads();  // everyone has read the previous survivor's verdict
+    const int nsv = ns;
+    double *hn_a = cache, *rs_a = hn_a + nsv, *sn_a = rs_a + nsv;
+    double *cache2 = sn_a + nsv;
+    const int64_t slots2 = slots > 0 ? std::max<int64_t>(0, (slots * D - 3 * (int64_t)nsv) / D) : 0;
+    const bool meta_in_lds = slots * D >= 3 * (int64_t)nsv;
+    for (int r = threadIdx.x; r < nsv && meta_in_lds; r += blockDim.x) {
         const int c = a.surv_cand[r];
-        double *R = a.H + (int64_t)(a.rrow ? a.rrow[r] : r) * a.D;
-        const double hn = sqrt(a.h2 ? a.h2[r] : a.cand_n2[c]);
+        hn_a[r] = sqrt(a.h2 ? a.h2[r] : a.cand_n2[c]);
+        rs_a[r] = sqrt(a.cand_a2[c]);
+        sn_a[r] = a.rho2 ? sqrt(a.rho2[r]) : -1.0;
+    }
+    __shared__ int64_t l_fp64, l_zero, l_acc, l_gen;
+    __shared__ double l_maxrej, l_minacc, l_sdep, l_sind;
+    if (threadIdx.x == 0) {
+        l_fp64 = l_zero = l_acc = l_gen = 0;
+        l_maxrej = 0.0;
+        l_minacc = INFINITY;
+        l_sdep = 0.0;
+        l_sind = INFINITY;
+    }
+    double *cbase = meta_in_lds ? cache2 : cache;
+    const int64_t cslots = meta_in_lds ? slots2 : slots;
+    constexpr int PF = 16;  // residual elements prefetched per thread (D <= 16 * blockDim)
+    double pf[PF];
+    auto row_of = [&](int r) -> const double * { return a.H + (int64_t)(a.rrow ? a.rrow[r] : r) * D; };
+    if (nsv > 0) {
+        const double *Rg = row_of(0);
+#pragma unroll
+        for (int k = 0; k < PF; ++k) {
+            const int64_t j = threadIdx.x + (int64_t)k * blockDim.x;
+            pf[k] = j < D ? Rg[j] : 0.0;
+        }
+    }
+    // thread layout of the in-block subtraction: for D <= 256, G groups of D threads,
+    // thread (g, j) owns column j and sums the in-block vectors q = g, g + G, ...;
+    // the G partial sums of a column meet in gacc.  Larger D: one group.
+    const int G = D <= 256 ? (int)std::min<int64_t>(16, blockDim.x / D) : 1;
+    const int gid = G > 1 ? (int)(threadIdx.x / D) : 0;
+    const int64_t gt = G > 1 ? (int64_t)(threadIdx.x % D) : 0;
+    for (int r = 0; r < nsv; ++r) {
+        lds_barrier();  // everyone has read the previous survivor's verdict and R
+#pragma unroll
+        for (int k = 0; k < PF; ++k) {
+            const int64_t j = threadIdx.x + (int64_t)k * blockDim.x;
+            if (j < D)
+                R[j] = pf[k];
+        }
+        if (r + 1 < nsv) {
+            const double *Rg = row_of(r + 1);
+#pragma unroll
+            for (int k = 0; k < PF; ++k) {
+                const int64_t j = threadIdx.x + (int64_t)k * blockDim.x;
+                pf[k] = j < D ? Rg[j] : 0.0;
+            }
+        }
+        double hn, rs, snap;
+        if (meta_in_lds) {
+            hn = hn_a[r];
+            rs = rs_a[r];
+            snap = sn_a[r];
+        } else {
+            const int c = a.surv_cand[r];
+            hn = sqrt(a.h2 ? a.h2[r] : a.cand_n2[c]);
+            rs = sqrt(a.cand_a2[c]);
+            snap = a.rho2 ? sqrt(a.rho2[r]) : -1.0;
+        }
         const double thr = a.mode == 0 ? a.tol * hn : a.tol;
-        const double rs = sqrt(a.cand_a2[c]);  // screened (or first-pass) residual, for the audit
-        if (threadIdx.x == 0 && a.mode == 1 && a.rho2) {
+        if (threadIdx.x == 0 && a.mode == 1 && snap >= 0.0) {
             // audit against the same basis snapshot the screen used
-            const double snap = sqrt(a.rho2[r]);
             if (snap > thr)
-                st->scr_min_indep = fmin(st->scr_min_indep, rs);
+                l_sind = fmin(l_sind, rs);
             else
-                st->scr_max_dep = fmax(st->scr_max_dep, rs);
+                l_sdep = fmax(l_sdep, rs);
         }
-        for (int pass = 0; pass < 2; ++pass) {
-            const int64_t A = sN - N0;
-            if (A == 0)
-                break;
-            for (int64_t q = w; q < A; q += nw) {
-                const double *va = a.V + (N0 + q) * a.D;
-                double s = 0.0;
-                for (int64_t j = lane; j < a.D; j += 64)
-                    s += va[j] * R[j];
-                s = wave_sum(s);
-                if (lane == 0)
-                    coef[q] = s;
-            }
-            __syncthreads();
-            const double *vb = a.V + N0 * a.D;
-            for (int64_t j = threadIdx.x; j < a.D; j += blockDim.x) {
-                double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-                int64_t q = 0;
-                for (; q + 4 <= A; q += 4) {
-                    s0 += coef[q] * vb[q * a.D + j];
-                    s1 += coef[q + 1] * vb[(q + 1) * a.D + j];
-                    s2 += coef[q + 2] * vb[(q + 2) * a.D + j];
-                    s3 += coef[q + 3] * vb[(q + 3) * a.D + j];
-                }
-                for (; q < A; ++q)
-                    s0 += coef[q] * vb[q * a.D + j];
-                R[j] -= (s0 + s1) + (s2 + s3);
-            }
-            __syncthreads();
-        }
-        double loc = 0.0;
-        for (int64_t j = threadIdx.x; j < a.D; j += blockDim.x)
-            loc += R[j] * R[j];
-        loc = wave_sum(loc);
-        if (lane == 0)
-            red[w] = loc;
-        __syncthreads();
-        if (threadIdx.x == 0) {
+        const int64_t A = sN - N0;
+        const int64_t AL = A < cslots ? A : cslots;
+        double nrm2 = -1.0;  // squared norm of R after the last pass (block-wide, valid in every thread)
+        lds_barrier();       // R is complete
+        if (A == 0) {
+            double loc = 0.0;
+            for (int64_t j = threadIdx.x; j < D; j += blockDim.x)
+                loc += R[j] * R[j];
+            loc = wave_sum(loc);
+            if (lane == 0)
+                red[w] = loc;
+            lds_barrier();
             double t = 0.0;
             for (int i = 0; i < nw; ++i)
                 t += red[i];
-            const double rr = sqrt(t);
+            nrm2 = t;
+        }
+        // orthogonalise against the elements appended earlier in this block: one pass,
+        // and a second one only if the first removed more than a 1/sqrt(2) fraction of the norm
+        double before2 = snap >= 0.0 ? snap * snap : -1.0;
+        for (int pass = 0; pass < 2 && A > 0; ++pass) {
+            for (int64_t q = w; q < A; q += nw) {
+                double sdot = 0.0;
+                if (q < AL) {
+                    const double *va = cbase + q * D;
+                    for (int64_t j = lane; j < D; j += 64)
+                        sdot += va[j] * R[j];
+                } else {
+                    const double *va = a.V + (N0 + q) * D;
+                    for (int64_t j = lane; j < D; j += 64)
+                        sdot += va[j] * R[j];
+                }
+                sdot = wave_sum(sdot);
+                if (lane == 0)
+                    coef[q] = sdot;
+            }
+            lds_barrier();
+            double loc = 0.0;
+            if (G > 1) {
+                if (gid < G) {
+                    double s0 = 0.0;
+                    int64_t q = gid;
+                    for (; q < AL; q += G)
+                        s0 += coef[q] * cbase[q * D + gt];
+                    for (; q < A; q += G)
+                        s0 += coef[q] * a.V[(N0 + q) * D + gt];
+                    gacc[gid * D + gt] = s0;
+                }
+                lds_barrier();
+                for (int64_t j = threadIdx.x; j < D; j += blockDim.x) {
+                    double t = 0.0;
+                    for (int g2 = 0; g2 < G; ++g2)
+                        t += gacc[g2 * D + j];
+                    const double v = R[j] - t;
+                    R[j] = v;
+                    loc += v * v;
+                }
+            } else {
+                for (int64_t j = threadIdx.x; j < D; j += blockDim.x) {
+                    double s0 = 0.0, s1 = 0.0;
+                    int64_t q = 0;
+                    for (; q + 2 <= AL; q += 2) {
+                        s0 += coef[q] * cbase[q * D + j];
+                        s1 += coef[q + 1] * cbase[(q + 1) * D + j];
+                    }
+                    if (q < AL) {
+                        s0 += coef[q] * cbase[q * D + j];
+                        ++q;
+                    }
+                    const double *vg = a.V + N0 * D;
+                    for (; q < A; ++q)
+                        s1 += coef[q] * vg[q * D + j];
+                    const double v = R[j] - (s0 + s1);
+                    R[j] = v;
+                    loc += v * v;
+                }
+            }
+            loc = wave_sum(loc);
+            if (lane == 0)
+                red[w] = loc;
+            lds_barrier();
+            double t = 0.0;
+            for (int i = 0; i < nw; ++i)
+                t += red[i];
+            nrm2 = t;
+            if (before2 >= 0.0 && nrm2 > 0.5 * before2)
+                break;  // little was removed: the vector is already orthogonal to working precision
+            before2 = nrm2;
+            lds_barrier();  // red[] and coef[] are reused by the second pass
+        }
+        if (threadIdx.x == 0) {
+            const double rr = sqrt(nrm2);
             rr_s = rr;
             verdict = 1;
             if (a.mode == 1)
-                st->n_fp64++;
+                l_fp64++;
             if (!isfinite(rr) || !isfinite(hn)) {
                 st->numeric_error = 1;
                 verdict = -1;
             } else if (hn == 0.0 || !(rr > thr)) {
                 if (a.mode == 1) {
                     if (hn == 0.0)
-                        st->n_zero++;
-                    st->max_rej = fmax(st->max_rej, rr);
+                        l_zero++;
+                    l_maxrej = fmax(l_maxrej, rr);
                 }
                 verdict = 0;
             } else if (a.mode == 1 && sN >= a.ambient) {
@@ -541,38 +692,57 @@ __device__ void accept_body(const AcceptArgs &a)
                 verdict = -1;
             }
         }
-        __syncthreads();
+        lds_barrier();
         if (verdict < 0)
             break;
         if (verdict == 0)
             continue;
         const double inv = 1.0 / rr_s;
-        double *dst = a.V + sN * a.D;
-        float *dsts = a.Vs ? a.Vs + sN * a.D : nullptr;
-        for (int64_t j = threadIdx.x; j < a.D; j += blockDim.x) {
+        const int64_t q_new = sN - N0;
+        double *dst = a.V + sN * D;
+        double *dstc = q_new < cslots ? cbase + q_new * D : nullptr;
+        float *dsts = a.Vs ? a.Vs + sN * D : nullptr;
+        for (int64_t j = threadIdx.x; j < D; j += blockDim.x) {
             const double v = R[j] * inv;
             dst[j] = v;
+            if (dstc)
+                dstc[j] = v;
             if (dsts)
                 dsts[j] = (float)v;
         }
-        __syncthreads();
+        // the appended vector is complete before sN moves; a vector that is not cached
+        // in LDS is read back from global memory later, so its stores must be visible
+        if (dstc)
+            lds_barrier();
+        else
+            __syncthreads();
         if (threadIdx.x == 0) {
             sN++;
             if (a.mode == 1) {
-                st->n_acc++;
-                st->min_acc = fmin(st->min_acc, rr_s);
+                l_acc++;
+                l_minacc = fmin(l_minacc, rr_s);
             } else {
-                st->n_gen_acc++;
+                l_gen++;
             }
             if (a.early_exit && sN >= a.ambient)
                 st->done = 1;
         }
-        __syncthreads();
+        lds_barrier();
         if (a.early_exit && sN >= a.ambient)
             break;
     }
-    if (threadIdx.x == 0)
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        st->n_fp64 += l_fp64;
+        st->n_zero += l_zero;
+        st->n_acc += l_acc;
+        st->n_gen_acc += l_gen;
+        st->max_rej = fmax(st->max_rej, l_maxrej);
+        st->min_acc = fmin(st->min_acc, l_minacc);
+        st->scr_max_dep = fmax(st->scr_max_dep, l_sdep);
+        st->scr_min_indep = fmin(st->scr_min_indep, l_sind);
         st->N = sN;
+    }
 }
 
 __global__ void __launch_bounds__(kAccThreads) k_accept_f64(AcceptArgs a) { accept_body(a); }
@@ -580,6 +750,18 @@ __global__ void __launch_bounds__(kAccThreads) k_accept_b(Batch b)
 {
     const AcceptArgs a = static_cast<const AcceptArgs *>(b.args)[blockIdx.x];
     accept_body(a);
+}
+
+__global__ void k_advance_cursor(int64_t *cursor, int cnt)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0)
+        *cursor += cnt;
+}
+
+__global__ void k_set_cursor(int64_t *cursor, int64_t value)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0)
+        *cursor = value;
 }
 
 __global__ void k_gather_states(const DevState *const *src, int n, DevState *dst)
@@ -620,6 +802,16 @@ __global__ void k_gram_loss_final(const double *__restrict__ part, int parts, do
 
 // ------------------------------------------------------------------ launchers
 
+static hipError_t grant_lds(const void *fn, size_t bytes, size_t &granted)
+{
+    if (bytes <= granted)
+        return hipSuccess;
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e == hipSuccess)
+        granted = bytes;
+    return e;
+}
+
 hipError_t launch_pack_c128(const double *src, double *dst, int count, int d, hipStream_t s)
 {
     const int64_t total = (int64_t)count * d * d;
@@ -641,7 +833,7 @@ hipError_t launch_unpack_c128(const double *src, double *dst, int64_t count, int
 }
 
 hipError_t launch_comm_f64(const double *V, int d, int64_t p0, const int64_t *pair_list, const int *ncnt, int cnt,
-                           const DevState *st, double *H, hipStream_t s)
+                           const DevState *st, double *H, hipStream_t s, const int64_t *dp0)
 {
     if (cnt <= 0)
         return hipSuccess;
@@ -664,7 +856,7 @@ hipError_t launch_comm_f64(const double *V, int d, int64_t p0, const int64_t *pa
         else
             (void)hipGetLastError();  // clear the failed request; the fallback kernel is used
     }
-    CommArgs a{V, d, p0, pair_list, ncnt, cnt, st, H, nullptr};
+    CommArgs a{V, d, p0, pair_list, dp0, ncnt, cnt, st, H, nullptr};
     if (d <= 64 && lds <= granted) {
         hipLaunchKernelGGL(k_comm_f64_lds, dim3(cnt), dim3(kThreads), lds, s, a);
     } else {
@@ -707,11 +899,28 @@ hipError_t launch_comm_f64_batched(const Batch &b, bool lds_variant, int dmax, h
     return hipGetLastError();
 }
 
-hipError_t launch_accept_batched(const Batch &b, hipStream_t s)
+hipError_t launch_accept_batched(const Batch &b, int64_t lds_doubles, hipStream_t s)
 {
     if (b.nprob <= 0)
         return hipSuccess;
-    hipLaunchKernelGGL(k_accept_b, dim3(b.nprob), dim3(kAccThreads), 0, s, b);
+    static size_t granted = 65536;
+    const size_t bytes = (size_t)lds_doubles * sizeof(double);
+    hipError_t e = grant_lds((const void *)k_accept_b, bytes, granted);
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(k_accept_b, dim3(b.nprob), dim3(kAccThreads), bytes, s, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_advance_cursor(int64_t *cursor, int cnt, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_advance_cursor, dim3(1), dim3(64), 0, s, cursor, cnt);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_cursor(int64_t *cursor, int64_t value, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_set_cursor, dim3(1), dim3(64), 0, s, cursor, value);
     return hipGetLastError();
 }
 
@@ -779,13 +988,49 @@ hipError_t launch_reduce_f64(double *H, const int *rows, const int *nrows, doubl
     return hipGetLastError();
 }
 
+// Dynamic LDS of the acceptance kernel: coefficients and the residual always,
+// plus as many cached in-block vectors as fit below the device limit.
+static int64_t accept_lds_avail()
+{
+    static int64_t avail = -1;
+    if (avail < 0) {
+        int dev = 0, v = 65536;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+            v = 65536;
+        // the dynamic part shares the limit with the kernel's static LDS
+        hipFuncAttributes fa{};
+        size_t static_bytes = 16384;
+        if (hipFuncGetAttributes(&fa, (const void *)k_accept_f64) == hipSuccess)
+            static_bytes = fa.sharedSizeBytes + 256;
+        else
+            (void)hipGetLastError();
+        avail = ((int64_t)v - (int64_t)static_bytes) / (int64_t)sizeof(double);
+    }
+    return avail;
+}
+
+int64_t accept_lds_doubles(int cnt, int64_t D)
+{
+    const int64_t need = cnt + D + (int64_t)cnt * D;
+    return std::max<int64_t>(cnt + D, std::min(accept_lds_avail(), need));
+}
+
+int accept_max_block(int64_t D) { return (int)std::max<int64_t>(0, std::min<int64_t>(kMaxBlock, accept_lds_avail() - D)); }
+
+
 hipError_t launch_accept_f64(const AcceptArgs &args, hipStream_t s)
 {
     if (args.cnt <= 0)
         return hipSuccess;
     if (args.cnt > kMaxBlock)
         return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_accept_f64, dim3(1), dim3(kAccThreads), 0, s, args);
+    static size_t granted = 65536;
+    const size_t bytes = (size_t)args.lds_doubles * sizeof(double);
+    hipError_t e = grant_lds((const void *)k_accept_f64, bytes, granted);
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(k_accept_f64, dim3(1), dim3(kAccThreads), bytes, s, args);
     return hipGetLastError();
 }
 

@@ -183,7 +183,7 @@ struct KRowLoader {
 
 // ---------------------------------------------------------------- coefficients
 template <typename T, int SM, int SN>
-__device__ void gemm_dot_body(const GemmArgs &g, int bx, int by)
+__device__ void gemm_dot_body(const GemmArgs &g, int bx0, int by, int gxs)
 {
     using M = Mma<T>;
     constexpr int BM = 2 * SM * M::E, BN = 2 * SN * M::E;
@@ -192,9 +192,8 @@ __device__ void gemm_dot_body(const GemmArgs &g, int bx, int by)
         return;
     const int64_t N = g.st ? g.st->N : g.N_fixed;
     const int Mrows = g.nrows ? *g.nrows : g.cnt;
-    const int64_t n0 = (int64_t)bx * BN;
     const int m0 = by * BM;
-    if (n0 >= N || m0 >= Mrows)
+    if ((int64_t)bx0 * BN >= N || m0 >= Mrows)
         return;
     __shared__ T As[2][KC][BM + PAD];
     __shared__ T Bs[2][KC][BN + PAD];
@@ -208,57 +207,59 @@ __device__ void gemm_dot_body(const GemmArgs &g, int bx, int by)
     KContigLoader<T, BN> lb;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int wm = w >> 1, wn = w & 1;
-    typename M::Acc acc[SM][SN];
+    for (int64_t n0 = (int64_t)bx0 * BN; n0 < N; n0 += (int64_t)gxs * BN) {
+        typename M::Acc acc[SM][SN];
 #pragma unroll
-    for (int i = 0; i < SM; ++i)
-#pragma unroll
-        for (int j = 0; j < SN; ++j)
-            acc[i][j] = M::zero();
-    const int nchunks = (int)((g.D + KC - 1) / KC);
-    la.load(H, g.D, m0, Mrows, 0, g.D, vec_ok, hmap);
-    lb.load(V, g.D, n0, N, 0, g.D, vec_ok, ident);
-    la.store(As[0]);
-    lb.store(Bs[0]);
-    __syncthreads();
-    for (int c = 0; c < nchunks; ++c) {
-        const int buf = c & 1;
-        if (c + 1 < nchunks) {
-            la.load(H, g.D, m0, Mrows, (int64_t)(c + 1) * KC, g.D, vec_ok, hmap);
-            lb.load(V, g.D, n0, N, (int64_t)(c + 1) * KC, g.D, vec_ok, ident);
-        }
-#pragma unroll
-        for (int kk = 0; kk < KC; kk += M::KS) {
-            T a[SM], b[SN];
-#pragma unroll
-            for (int i = 0; i < SM; ++i)
-                a[i] = As[buf][kk + M::frag_k(lane)][wm * SM * M::E + i * M::E + M::frag_row(lane)];
+        for (int i = 0; i < SM; ++i)
 #pragma unroll
             for (int j = 0; j < SN; ++j)
-                b[j] = Bs[buf][kk + M::frag_k(lane)][wn * SN * M::E + j * M::E + M::frag_row(lane)];
+                acc[i][j] = M::zero();
+        const int nchunks = (int)((g.D + KC - 1) / KC);
+        la.load(H, g.D, m0, Mrows, 0, g.D, vec_ok, hmap);
+        lb.load(V, g.D, n0, N, 0, g.D, vec_ok, ident);
+        la.store(As[0]);
+        lb.store(Bs[0]);
+        __syncthreads();
+        for (int c = 0; c < nchunks; ++c) {
+            const int buf = c & 1;
+            if (c + 1 < nchunks) {
+                la.load(H, g.D, m0, Mrows, (int64_t)(c + 1) * KC, g.D, vec_ok, hmap);
+                lb.load(V, g.D, n0, N, (int64_t)(c + 1) * KC, g.D, vec_ok, ident);
+            }
 #pragma unroll
-            for (int i = 0; i < SM; ++i)
+            for (int kk = 0; kk < KC; kk += M::KS) {
+                T a[SM], b[SN];
+#pragma unroll
+                for (int i = 0; i < SM; ++i)
+                    a[i] = As[buf][kk + M::frag_k(lane)][wm * SM * M::E + i * M::E + M::frag_row(lane)];
 #pragma unroll
                 for (int j = 0; j < SN; ++j)
-                    acc[i][j] = M::mma(a[i], b[j], acc[i][j]);
-        }
-        if (c + 1 < nchunks) {
-            la.store(As[buf ^ 1]);
-            lb.store(Bs[buf ^ 1]);
-        }
-        __syncthreads();
-    }
-    T *C = static_cast<T *>(g.C);
+                    b[j] = Bs[buf][kk + M::frag_k(lane)][wn * SN * M::E + j * M::E + M::frag_row(lane)];
 #pragma unroll
-    for (int i = 0; i < SM; ++i)
+                for (int i = 0; i < SM; ++i)
 #pragma unroll
-        for (int j = 0; j < SN; ++j)
-#pragma unroll
-            for (int r = 0; r < M::NR; ++r) {
-                const int m = m0 + wm * SM * M::E + i * M::E + M::out_row(lane, r);
-                const int64_t n = n0 + wn * SN * M::E + j * M::E + M::out_col(lane);
-                if (m < Mrows && n < N)
-                    C[(int64_t)m * g.ldc + n] = acc[i][j][r];
+                    for (int j = 0; j < SN; ++j)
+                        acc[i][j] = M::mma(a[i], b[j], acc[i][j]);
             }
+            if (c + 1 < nchunks) {
+                la.store(As[buf ^ 1]);
+                lb.store(Bs[buf ^ 1]);
+            }
+            __syncthreads();
+        }
+        T *C = static_cast<T *>(g.C);
+#pragma unroll
+        for (int i = 0; i < SM; ++i)
+#pragma unroll
+            for (int j = 0; j < SN; ++j)
+#pragma unroll
+                for (int r = 0; r < M::NR; ++r) {
+                    const int m = m0 + wm * SM * M::E + i * M::E + M::out_row(lane, r);
+                    const int64_t n = n0 + wn * SN * M::E + j * M::E + M::out_col(lane);
+                    if (m < Mrows && n < N)
+                        C[(int64_t)m * g.ldc + n] = acc[i][j][r];
+                }
+    }
 }
 
 // ---------------------------------------------------------------- residual + norms
@@ -379,7 +380,7 @@ __device__ void gemm_sub_body(const GemmArgs &g, int bx, int by, int ntiles)
 template <typename T, int SM, int SN>
 __global__ void __launch_bounds__(256) k_gemm_dot(GemmArgs g)
 {
-    gemm_dot_body<T, SM, SN>(g, blockIdx.x, blockIdx.y);
+    gemm_dot_body<T, SM, SN>(g, blockIdx.x, blockIdx.y, gridDim.x);
 }
 
 template <typename T, int SM, int SN>
@@ -394,7 +395,7 @@ __global__ void __launch_bounds__(256) k_gemm_dot_b(Batch b)
     const int p = batch_find(b.start, b.nprob, blockIdx.x);
     const GemmArgs g = static_cast<const GemmArgs *>(b.args)[p];
     const int l = blockIdx.x - b.start[p], gx = b.gx[p];
-    gemm_dot_body<T, SM, SN>(g, l % gx, l / gx);
+    gemm_dot_body<T, SM, SN>(g, l % gx, l / gx, gx);
 }
 
 template <typename T, int SM, int SN>
@@ -461,7 +462,7 @@ int64_t coef_ld(int64_t n_hi) { return (std::max<int64_t>(n_hi, 1) + 3) / 4 * 4;
 int gemm_tile_f32(int64_t rows, int64_t cols) { return ((rows + 127) / 128) * ((cols + 127) / 128) >= 192 ? 2 : 1; }
 
 hipError_t launch_gemm_dot_f32(const float *Vs, const DevState *st, const float *Hs, int cnt, int64_t D, int64_t n_hi,
-                               float *C, int tile, hipStream_t s)
+                               int64_t ldc, float *C, int tile, hipStream_t s)
 {
     if (cnt <= 0)
         return hipSuccess;
@@ -470,7 +471,7 @@ hipError_t launch_gemm_dot_f32(const float *Vs, const DevState *st, const float 
     g.cnt = cnt;
     g.V = Vs;
     g.C = C;
-    g.ldc = coef_ld(n_hi);
+    g.ldc = ldc;
     g.D = D;
     g.st = st;
     n_hi = std::max<int64_t>(n_hi, 1);
@@ -480,7 +481,7 @@ hipError_t launch_gemm_dot_f32(const float *Vs, const DevState *st, const float 
 int gemm_sub_tiles_f32(int64_t D, int tile) { return (int)((D + (tile == 2 ? 128 : 64) - 1) / (tile == 2 ? 128 : 64)); }
 
 hipError_t launch_gemm_sub_f32(const float *Vs, const DevState *st, const float *Hs, const float *C, int64_t n_hi,
-                               int cnt, int64_t D, double *normpart, int tile, hipStream_t s)
+                               int64_t ldc, int cnt, int64_t D, double *normpart, int tile, hipStream_t s)
 {
     if (cnt <= 0)
         return hipSuccess;
@@ -489,7 +490,7 @@ hipError_t launch_gemm_sub_f32(const float *Vs, const DevState *st, const float 
     g.cnt = cnt;
     g.V = Vs;
     g.C = const_cast<float *>(C);
-    g.ldc = coef_ld(n_hi);
+    g.ldc = ldc;
     g.D = D;
     g.st = st;
     g.normpart = normpart;
@@ -500,7 +501,8 @@ hipError_t launch_gemm_sub_f32(const float *Vs, const DevState *st, const float 
 int gemm_sub_tiles_f64(int64_t D) { return (int)((D + 63) / 64); }
 
 hipError_t launch_gemm_dot_f64(const double *V, const DevState *st, const double *H, const int *rows,
-                               const int *nrows, int cnt, int64_t D, int64_t n_hi, double *C, hipStream_t s)
+                               const int *nrows, int cnt, int64_t D, int64_t n_hi, int64_t ldc, double *C,
+                               hipStream_t s)
 {
     if (cnt <= 0)
         return hipSuccess;
@@ -511,14 +513,15 @@ hipError_t launch_gemm_dot_f64(const double *V, const DevState *st, const double
     g.cnt = cnt;
     g.V = V;
     g.C = C;
-    g.ldc = coef_ld(n_hi);
+    g.ldc = ldc;
     g.D = D;
     g.st = st;
     return dot_impl<double, 2, 2>(g, std::max<int64_t>(n_hi, 1), s);
 }
 
 hipError_t launch_gemm_sub_f64(const double *V, const DevState *st, double *H, const int *rows, const int *nrows,
-                               const double *C, int64_t n_hi, int cnt, int64_t D, double *normpart, hipStream_t s)
+                               const double *C, int64_t n_hi, int64_t ldc, int cnt, int64_t D, double *normpart,
+                               hipStream_t s)
 {
     if (cnt <= 0)
         return hipSuccess;
@@ -529,7 +532,7 @@ hipError_t launch_gemm_sub_f64(const double *V, const DevState *st, double *H, c
     g.cnt = cnt;
     g.V = V;
     g.C = const_cast<double *>(C);
-    g.ldc = coef_ld(n_hi);
+    g.ldc = ldc;
     g.D = D;
     g.st = st;
     g.normpart = normpart;

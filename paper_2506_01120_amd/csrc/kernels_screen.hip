@@ -41,7 +41,7 @@ __device__ void comm_f32_mfma_body(const CommArgs &A, int c)
     extern __shared__ float smem[];
     const float *Vs = static_cast<const float *>(A.V);
     const int d = A.d;
-    const int64_t p0 = A.p0;
+    const int64_t p0 = A.dp0 ? *A.dp0 : A.p0;
     const int cnt = A.cnt;
     const DevState *st = A.st;
     float *Hs = static_cast<float *>(A.H);
@@ -136,7 +136,7 @@ __device__ void comm_f32_global_body(const CommArgs &A, int bx, int c)
 {
     const float *Vs = static_cast<const float *>(A.V);
     const int d = A.d;
-    const int64_t p0 = A.p0;
+    const int64_t p0 = A.dp0 ? *A.dp0 : A.p0;
     const int cnt = A.cnt;
     const DevState *st = A.st;
     float *Hs = static_cast<float *>(A.H);
@@ -234,7 +234,7 @@ __device__ void classify_body(const ClassifyArgs &A)
 {
     const double *a2 = A.a2, *n2 = A.n2;
     const int cnt = A.cnt;
-    const int64_t p0 = A.p0;
+    const int64_t p0 = A.dp0 ? *A.dp0 : A.p0;
     const int policy = A.policy;
     const double thr = A.thr;
     const DevState *st = A.st;
@@ -307,7 +307,7 @@ __global__ void __launch_bounds__(1024) k_classify_b(Batch b)
 // ------------------------------------------------------------------ launchers
 
 hipError_t launch_comm_f32(const float *Vs, int d, int64_t p0, int cnt, const DevState *st, float *Hs, double *hs2,
-                           hipStream_t s)
+                           hipStream_t s, const int64_t *dp0)
 {
     if (cnt <= 0)
         return hipSuccess;
@@ -331,7 +331,7 @@ hipError_t launch_comm_f32(const float *Vs, int d, int64_t p0, int cnt, const De
         else
             (void)hipGetLastError();  // clear the failed request; the fallback kernel is used
     }
-    CommArgs a{Vs, d, p0, nullptr, nullptr, cnt, st, Hs, hs2};
+    CommArgs a{Vs, d, p0, nullptr, dp0, nullptr, cnt, st, Hs, hs2};
     if (lds <= granted) {
         hipLaunchKernelGGL(k_comm_f32_mfma, dim3(cnt), dim3(kThreads), lds, s, a);
     } else {
@@ -383,12 +383,13 @@ hipError_t launch_rownorm_f32_batched(const Batch &b, hipStream_t s)
 }
 
 hipError_t launch_classify(const double *a2, const double *n2, int cnt, int64_t p0, int policy, double thr,
-                           const DevState *st, int *rows, int64_t *pairs, int *slot, int *nsurv, hipStream_t s)
+                           const DevState *st, int *rows, int64_t *pairs, int *slot, int *nsurv, hipStream_t s,
+                           const int64_t *dp0)
 {
     if (cnt <= 0)
         return hipSuccess;
     const int threads = cnt >= 1024 ? 1024 : ((cnt + 63) / 64) * 64;
-    ClassifyArgs a{a2, n2, cnt, p0, policy, thr, st, rows, pairs, slot, nsurv};
+    ClassifyArgs a{a2, n2, cnt, p0, dp0, policy, thr, st, rows, pairs, slot, nsurv};
     hipLaunchKernelGGL(k_classify, dim3(1), dim3(threads), 0, s, a);
     return hipGetLastError();
 }

@@ -84,8 +84,9 @@ __device__ inline int batch_find(const int *start, int n, int b)
 struct CommArgs {
     const void *V;             // basis rows (double or float, packed layout)
     int d;
-    int64_t p0;                // pair index of candidate 0 (when pair_list is null)
+    int64_t p0;                // pair index of candidate 0 (when pair_list and dp0 are null)
     const int64_t *pair_list;  // candidate c -> pair index (null: p0 + c)
+    const int64_t *dp0;        // device pair cursor used instead of p0 (graph replays), or null
     const int *ncnt;           // device candidate count (null: cnt)
     int cnt;
     const DevState *st;
@@ -107,6 +108,7 @@ struct ClassifyArgs {
     const double *a2, *n2;
     int cnt;
     int64_t p0;
+    const int64_t *dp0;        // device pair cursor used instead of p0, or null
     int policy;
     double thr;
     const DevState *st;
@@ -155,7 +157,11 @@ hipError_t launch_unpack_c128(const double *src, double *dst, int64_t count, int
 // H[c] = pack([V_l, V_m]) for the pair of index p0 + c (pair_list == nullptr)
 // or pair_list[c], for c < cnt (or c < *ncnt when ncnt is given).  FP64.
 hipError_t launch_comm_f64(const double *V, int d, int64_t p0, const int64_t *pair_list, const int *ncnt, int cnt,
-                           const DevState *st, double *H, hipStream_t s);
+                           const DevState *st, double *H, hipStream_t s, const int64_t *dp0 = nullptr);
+// *cursor += cnt (one thread; keeps a device pair cursor in step with graph replays)
+hipError_t launch_advance_cursor(int64_t *cursor, int cnt, hipStream_t s);
+// *cursor = value (the value travels as a kernel argument, so no host buffer must outlive the call)
+hipError_t launch_set_cursor(int64_t *cursor, int64_t value, hipStream_t s);
 
 struct ProjShape {
     int64_t D;      // elements per operator (d*d)
@@ -194,8 +200,13 @@ struct AcceptArgs {
     int mode;                // 0: generator (relative threshold), 1: bracket
     int screened;            // 1: non-survivors were rejected by the screen
     int early_exit;
+    int64_t lds_doubles;     // dynamic LDS of the launch, in doubles (accept_lds_doubles)
 };
 hipError_t launch_accept_f64(const AcceptArgs &args, hipStream_t s);
+// Dynamic LDS (doubles) for an acceptance launch of cnt candidates of length D.
+int64_t accept_lds_doubles(int cnt, int64_t D);
+// Largest block whose acceptance launch fits in LDS (coefficients + one residual).
+int accept_max_block(int64_t D);
 
 // G = V V^T (n x n) then ||G - I||_F into *out (device), using `work` of n*n + 256 doubles.
 hipError_t launch_orth_loss(const double *V, int64_t n, int64_t D, double *work, double *out, hipStream_t s);
@@ -203,20 +214,24 @@ hipError_t launch_orth_loss(const double *V, int64_t n, int64_t D, double *work,
 // ------------------------------------------------------------- matrix-core projection GEMMs (kernels_gemm.hip)
 // Coefficients C[m][n] = <H_row(m), V_n> and residual R = H - C V with per-tile
 // squared norms (normpart[m][tile][2] = {||R||^2, ||H||^2} partial sums).
-// The coefficient leading dimension is coef_ld(n_hi) in both halves.
+// The coefficient GEMMs stride over basis tiles up to the device value of N,
+// so their grids may be sized for any bound; the coefficient leading dimension
+// `ldc` must cover the capacity (the engine passes coef_ld(capacity)).
 int64_t coef_ld(int64_t n_hi);
 int gemm_tile_f32(int64_t rows, int64_t cols);     // 2: 128x128 workgroup tile, 1: 64x64
 int gemm_sub_tiles_f32(int64_t D, int tile);
 int gemm_sub_tiles_f64(int64_t D);
 hipError_t launch_gemm_dot_f32(const float *Vs, const DevState *st, const float *Hs, int cnt, int64_t D, int64_t n_hi,
-                               float *C, int tile, hipStream_t s);
+                               int64_t ldc, float *C, int tile, hipStream_t s);
 hipError_t launch_gemm_sub_f32(const float *Vs, const DevState *st, const float *Hs, const float *C, int64_t n_hi,
-                               int cnt, int64_t D, double *normpart, int tile, hipStream_t s);
+                               int64_t ldc, int cnt, int64_t D, double *normpart, int tile, hipStream_t s);
 hipError_t launch_gemm_dot_f64(const double *V, const DevState *st, const double *H, const int *rows,
-                               const int *nrows, int cnt, int64_t D, int64_t n_hi, double *C, hipStream_t s);
+                               const int *nrows, int cnt, int64_t D, int64_t n_hi, int64_t ldc, double *C,
+                               hipStream_t s);
 // R written over H_row(m)
 hipError_t launch_gemm_sub_f64(const double *V, const DevState *st, double *H, const int *rows, const int *nrows,
-                               const double *C, int64_t n_hi, int cnt, int64_t D, double *normpart, hipStream_t s);
+                               const double *C, int64_t n_hi, int64_t ldc, int cnt, int64_t D, double *normpart,
+                               hipStream_t s);
 // rho2[m] = sum of tile partials of ||R||^2, h2[m] (if non-null) of ||H||^2
 hipError_t launch_norm_final(const double *normpart, const int *nrows, int cnt, int tiles, const DevState *st,
                              double *rho2, double *h2, hipStream_t s);
@@ -233,7 +248,7 @@ hipError_t launch_comm_f64_batched(const Batch &b, bool lds_variant, int dmax, h
 hipError_t launch_comm_f32_batched(const Batch &b, bool lds_variant, int dmax, hipStream_t s);
 hipError_t launch_rownorm_f32_batched(const Batch &b, hipStream_t s);
 hipError_t launch_classify_batched(const Batch &b, hipStream_t s);
-hipError_t launch_accept_batched(const Batch &b, hipStream_t s);
+hipError_t launch_accept_batched(const Batch &b, int64_t lds_doubles, hipStream_t s);
 bool comm_f64_fits_lds(int d);
 bool comm_f32_fits_lds(int d);
 // DevState copies of several problems into one array (for one read-back).
@@ -244,18 +259,19 @@ hipError_t launch_gather_states(const DevState *const *src, int n, DevState *dst
 // split into bf16 hi + lo while staged, products are hi*hi + hi*lo + lo*hi.
 int gemm_sub_tiles_bf16(int64_t D, int tile);
 hipError_t launch_gemm_dot_bf16x3(const float *Vs, const DevState *st, const float *Hs, int cnt, int64_t D,
-                                  int64_t n_hi, float *C, int tile, hipStream_t s);
+                                  int64_t n_hi, int64_t ldc, float *C, int tile, hipStream_t s);
 hipError_t launch_gemm_sub_bf16x3(const float *Vs, const DevState *st, const float *Hs, const float *C, int64_t n_hi,
-                                  int cnt, int64_t D, double *normpart, int tile, hipStream_t s);
+                                  int64_t ldc, int cnt, int64_t D, double *normpart, int tile, hipStream_t s);
 hipError_t launch_gemm_dot_bf16x3_batched(const Batch &b, hipStream_t s);  // 64 x 64 tiles
 hipError_t launch_gemm_sub_bf16x3_batched(const Batch &b, hipStream_t s);
 
 // ------------------------------------------------------------- FP32 screening kernels (kernels_screen.hip)
 // Hs[c] = fp32 packed [Vs_l, Vs_m] for pair p0 + c, hs2[c] = ||Hs[c]||^2.
 hipError_t launch_comm_f32(const float *Vs, int d, int64_t p0, int cnt, const DevState *st, float *Hs, double *hs2,
-                           hipStream_t s);
+                           hipStream_t s, const int64_t *dp0 = nullptr);
 // Survivor compaction under a policy (cnt <= 1024).
 hipError_t launch_classify(const double *a2, const double *n2, int cnt, int64_t p0, int policy, double thr,
-                           const DevState *st, int *rows, int64_t *pairs, int *slot, int *nsurv, hipStream_t s);
+                           const DevState *st, int *rows, int64_t *pairs, int *slot, int *nsurv, hipStream_t s,
+                           const int64_t *dp0 = nullptr);
 
 }  // namespace lie
