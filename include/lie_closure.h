@@ -106,6 +106,7 @@ typedef struct lie_closure_stats {
     int64_t screen_rejected;      /* candidates rejected from the screened residual alone */
     int64_t fp64_decided;         /* candidates whose decision used an FP64 residual */
     int64_t accepted;             /* elements appended by the bracket loop */
+    int64_t block_qr_accepted;    /* of those, appended by the block Cholesky-QR prefix of a block's survivors */
     int64_t blocks;               /* block steps executed */
     int64_t host_syncs;           /* device-to-host synchronisations of the driver */
     double min_accepted_residual; /* smallest FP64 residual that was accepted (bracket loop) */

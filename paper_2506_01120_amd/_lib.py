@@ -63,6 +63,7 @@ class Stats(ctypes.Structure):
         ("screen_rejected", ctypes.c_int64),
         ("fp64_decided", ctypes.c_int64),
         ("accepted", ctypes.c_int64),
+        ("block_qr_accepted", ctypes.c_int64),
         ("blocks", ctypes.c_int64),
         ("host_syncs", ctypes.c_int64),
         ("min_accepted_residual", ctypes.c_double),

@@ -415,10 +415,485 @@ __device__ inline void atomic_min_pos(double *addr, double v)
     atomicMin(reinterpret_cast<unsigned long long *>(addr), (unsigned long long)__double_as_longlong(v));
 }
 
+typedef double f64x4_t __attribute__((ext_vector_type(4)));
+
+// One 16 x 16 FP64 tile of A B^T over a K-extent of D: lane l supplies row l%16 of
+// A through pa and of B through pb (nullptr: a zero row).  Loads are issued 16 at a
+// time per operand so that their latencies overlap.
+__device__ inline f64x4_t dot_tile_f64(const double *pa, const double *pb, int64_t D, int lane)
+{
+    f64x4_t acc = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t k0 = 0; k0 < D; k0 += 64) {
+        double av[16], bv[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int64_t k = k0 + 4 * q + (lane >> 4);
+            av[q] = (pa && k < D) ? pa[k] : 0.0;
+            bv[q] = (pb && k < D) ? pb[k] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < 16; ++q)
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[q], bv[q], acc, 0, 0, 0);
+    }
+    return acc;
+}
+
+// Compiler-level ordering of LDS accesses between the steps of a one-wave
+// recurrence (a wavefront's LDS operations complete in issue order).
+__device__ inline void wave_order() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront"); }
+
+// Value of x in lane `src` (uniform) for every lane of the wave.
+__device__ inline double lane_bcast(double x, int src)
+{
+    const int s = __builtin_amdgcn_readfirstlane(src);
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), s);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), s);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ inline int lane_bcast_int(int x, int src) { return __builtin_amdgcn_readlane(x, __builtin_amdgcn_readfirstlane(src)); }
+
+// Row stride of the small Gram matrix in LDS: odd, so that a column read by
+// 64 lanes spreads over the banks, and at least 17 (the same array later holds
+// 16 rows of per-wave partial sums).
+__host__ __device__ constexpr int gram_ld(int nsv) { return nsv < 17 ? 17 : (nsv | 1); }
+
+// LDS (in doubles) of the block Cholesky-QR pass over nsv survivors with nw waves:
+// Gram / factor / inverse (nsv x gram_ld) | pivots | verified norms | two index
+// lists (ints) | per-wave norm partials (nw x nsv).
+__host__ __device__ constexpr int64_t bqr_lds(int nsv, int nw)
+{
+    return 2 * (int64_t)nsv * gram_ld(nsv) + 4 * (int64_t)nsv + (int64_t)nw * nsv;
+}
+
+struct BqrOut {
+    int resume;  // first survivor left to the exact sequential path (nsv: none)
+    int u;       // survivors before `resume` accepted by the pass (they are V[N0 .. N0+u))
+};
+
+// Block Cholesky-QR of a block's survivors (Algorithm 4's in-block decisions, in
+// candidate order).  Survivor rows R_0..R_{s-1} are already orthogonal to the
+// basis snapshot; what the sequential loop would measure for R_j is its norm after
+// removing the survivors accepted before it, i.e. the Cholesky pivot of the Gram
+// matrix G = R R^T restricted to those rows.
+//  * A pivot is a certified acceptance when it is at least 0.1 ||R_j|| (the
+//    accepted rows stay well conditioned, so the Gram rounding, ~eps ||R_j||^2,
+//    cannot matter) and at least 10 thr (rounding cannot flip the decision).
+//  * Every other row is provisionally rejected (its column is skipped).  The Gram
+//    pivot cannot certify a rejection -- it carries an absolute error of order
+//    sqrt(eps) ||R_j|| -- so each provisional rejection is checked with the
+//    explicit FP64 residual R_j - sum_c <R_j, Q_c> Q_c over the accepted Q_c that
+//    precede it.  The first one found above thr ends the pass there and the
+//    exact sequential path resumes at that row; the accepted rows before it stand.
+// The accepted rows become Q = L^{-1} R_acc.  Gram, Q and the verification use FP64
+// MFMA 16x16x4 (result register r of lane l holds D[4r + l/16][l%16]); the
+// factorisation and the triangular inverse are one-wave recurrences in LDS (lane
+// i owns row i, resp. column i) that need no workgroup barrier.
+__device__ __forceinline__ BqrOut block_qr(const AcceptArgs &a, int nsv, int64_t N0, double *lds, double *cache2, int64_t cslots,
+                           double *stat)
+{
+    const int64_t D = a.D;
+    const int ld = gram_ld(nsv);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    double *Gm = lds, *piv = Gm + (int64_t)nsv * ld, *vn = piv + nsv;
+    int *acc_idx = reinterpret_cast<int *>(vn + nsv), *rej_idx = acc_idx + nsv, *hrow = rej_idx + nsv;
+    double *part = vn + 3 * nsv;
+    double *Gc = part + (int64_t)nw * nsv;  // copy of G for the verification coefficients
+    __shared__ int s_u, s_nrej, s_stop, s_resume, s_uk;
+    for (int r = threadIdx.x; r < nsv; r += blockDim.x)
+        hrow[r] = a.rrow ? a.rrow[r] : r;
+    __syncthreads();
+    auto row = [&](int r) -> const double * { return a.H + (int64_t)hrow[r] * D; };
+    // 1. Gram matrix, lower 16 x 16 tiles (I >= J), one tile per wave.  The survivor rows are
+    // staged through LDS in chunks of 64 columns with coalesced loads (the next chunk is
+    // fetched into registers while the current one is multiplied); without room for the
+    // stage the tiles read global memory directly.
+    const int T16 = (nsv + 15) / 16;
+    const int ntile = T16 * (T16 + 1) / 2;  // <= 10 <= nw
+    int tI = 0, tJ = w;
+    while (tJ > tI) {
+        tJ -= tI + 1;
+        ++tI;
+    }
+    constexpr int KC = 64, KS = KC + 1;
+    if (cslots * D >= (int64_t)nsv * KS) {
+        double *stage = cache2;
+        const int per = (nsv * KC + blockDim.x - 1) / blockDim.x;  // <= 4
+        double nxt[4];
+        auto fetch = [&](int64_t k0) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int e = threadIdx.x + q * blockDim.x;
+                const int r = e / KC, c = e % KC;
+                nxt[q] = (q < per && r < nsv && k0 + c < D) ? row(r)[k0 + c] : 0.0;
+            }
+        };
+        fetch(0);
+        f64x4_t acc = {0.0, 0.0, 0.0, 0.0};
+        for (int64_t k0 = 0; k0 < D; k0 += KC) {
+            __syncthreads();  // the previous chunk has been consumed
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int e = threadIdx.x + q * blockDim.x;
+                if (q < per && e < nsv * KC)
+                    stage[(e / KC) * KS + e % KC] = nxt[q];
+            }
+            __syncthreads();
+            if (k0 + KC < D)
+                fetch(k0 + KC);
+            if (w < ntile) {
+                const int ia = tI * 16 + (lane & 15), ib = tJ * 16 + (lane & 15);
+#pragma unroll
+                for (int q = 0; q < KC / 4; ++q) {
+                    const int k = 4 * q + (lane >> 4);
+                    const double av = ia < nsv ? stage[ia * KS + k] : 0.0;
+                    const double bv = ib < nsv ? stage[ib * KS + k] : 0.0;
+                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+                }
+            }
+        }
+        if (w < ntile) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = tI * 16 + 4 * r + (lane >> 4), j = tJ * 16 + (lane & 15);
+                if (i < nsv && j <= i)
+                    Gm[i * ld + j] = Gc[i * ld + j] = acc[r];
+            }
+        }
+    } else if (w < ntile) {
+        const int ia = tI * 16 + (lane & 15), ib = tJ * 16 + (lane & 15);
+        const f64x4_t acc = dot_tile_f64(ia < nsv ? row(ia) : nullptr, ib < nsv ? row(ib) : nullptr, D, lane);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int i = tI * 16 + 4 * r + (lane >> 4), j = tJ * 16 + (lane & 15);
+            if (i < nsv && j <= i)
+                Gm[i * ld + j] = Gc[i * ld + j] = acc[r];
+        }
+    }
+    __syncthreads();
+    if (w == 0) {
+        // 2. Cholesky with skipping in candidate order, one wave, panels of 16 candidate
+        // columns.  Panel update (left-looking, MFMA): S = G[:, panel] - L[:, :u] L[panel, :u]^T
+        // for the rows not yet decided, written back over G.  Panel steps: lane i holds its 16
+        // panel values of S in registers; the pivot of row j is lane j's value, and an accepted
+        // column's entries are broadcast with readlane for the rank-1 update of the panel.
+        // Column c of the compact factor L is stored over column c <= j of G (already consumed).
+        const int i = lane;
+        const double nrm = i < nsv ? sqrt(Gm[i * ld + i]) : 0.0;
+        int u = 0, nrej = 0, stop = nsv;
+        bool halt = false;
+        int accreg = 0;        // lane r: row index of the r-th accepted survivor
+        double pinvreg = 1.0;  // lane r: reciprocal of its pivot
+        for (int jb = 0; jb < nsv && !halt; jb += 16) {
+            if (u > 0) {
+                for (int I = jb / 16; I < T16; ++I) {
+                    const int ia = I * 16 + (lane & 15), ib = jb + (lane & 15);
+                    f64x4_t acc = {0.0, 0.0, 0.0, 0.0};
+                    for (int k0 = 0; k0 < u; k0 += 16) {
+                        double av[4], bv[4];
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            const int k = k0 + 4 * q + (lane >> 4);
+                            av[q] = (ia < nsv && k < u) ? Gm[ia * ld + k] : 0.0;
+                            bv[q] = (ib < nsv && k < u) ? Gm[ib * ld + k] : 0.0;
+                        }
+#pragma unroll
+                        for (int q = 0; q < 4; ++q)
+                            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[q], bv[q], acc, 0, 0, 0);
+                    }
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int row = I * 16 + 4 * r + (lane >> 4), col = jb + (lane & 15);
+                        if (row < nsv && col <= row)
+                            Gm[row * ld + col] -= acc[r];
+                    }
+                }
+                wave_order();
+            }
+            double sv[16];
+#pragma unroll
+            for (int t = 0; t < 16; ++t)
+                sv[t] = (i < nsv && jb + t <= i) ? Gm[i * ld + jb + t] : 0.0;
+#pragma unroll
+            for (int t = 0; t < 16; ++t) {
+                const int j = jb + t;
+                if (!halt && j < nsv) {
+                    const double dj = lane_bcast(sv[t], j);
+                    const double nj = lane_bcast(nrm, j);
+                    // 1/sqrt(dj) from the hardware estimate and two Newton steps (quadratic
+                    // convergence from ~2^-22 to working precision); rr = dj / sqrt(dj)
+                    const bool pos = dj > 1e-200;
+                    double rinv = 0.0;
+                    if (pos) {
+                        double y = __builtin_amdgcn_rsq(dj);
+                        y = y * (1.5 - 0.5 * dj * y * y);
+                        y = y * (1.5 - 0.5 * dj * y * y);
+                        rinv = y;
+                    }
+                    const double rr = dj * rinv;
+                    const bool room = N0 + u < a.ambient && N0 + u < a.cap;
+                    if (!isfinite(dj) || !isfinite(nj)) {
+                        stop = j;  // the exact path reports the non-finite residual
+                        halt = true;
+                    } else if (room && pos && rr >= 0.1 * nj && rr >= 10.0 * a.tol) {
+                        const double li = i > j ? sv[t] * rinv : 0.0;
+                        if (i > j && i < nsv)
+                            Gm[i * ld + u] = li;
+                        if (i == u) {
+                            accreg = j;
+                            pinvreg = rinv;
+                        }
+                        if (i == 0) {
+                            piv[u] = rr;
+                            acc_idx[u] = j;
+                        }
+                        wave_order();
+#pragma unroll
+                        for (int t2 = t + 1; t2 < 16; ++t2)
+                            sv[t2] -= li * lane_bcast(li, jb + t2);
+                        ++u;
+                        if (a.early_exit && N0 + u >= a.ambient) {
+                            stop = j + 1;  // nothing after this row is decided
+                            halt = true;
+                        }
+                    } else {
+                        if (i == 0)
+                            rej_idx[nrej] = j;
+                        ++nrej;
+                    }
+                }
+            }
+            wave_order();
+        }
+        // 3. T = L^{-1} in place of L (row acc_idx[r] of the array holds row r of L, then of T),
+        // one wave, panels of 16 rows of T: P = L[panel, :pb] T[:pb, :] (MFMA, into part[]), then
+        // a 16-step recurrence with lane c holding column c of the panel rows of T in registers.
+        for (int pb = 0; pb < u; pb += 16) {
+            if (pb > 0) {
+                const int ra = pb + (lane & 15);
+                const double *arow = ra < u ? Gm + (int64_t)acc_idx[ra] * ld : nullptr;
+                for (int J = 0; J * 16 < pb; ++J) {
+                    const int cb = J * 16 + (lane & 15);
+                    f64x4_t acc = {0.0, 0.0, 0.0, 0.0};
+                    for (int k0 = 0; k0 < pb; k0 += 16) {
+                        double av[4], bv[4];
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            const int k = k0 + 4 * q + (lane >> 4);
+                            // row index of accepted k: lane k of accreg (k < pb <= 48)
+                            const int rk = __shfl(accreg, k < 64 ? k : 0, 64);
+                            av[q] = (arow && k < pb) ? arow[k] : 0.0;
+                            bv[q] = (k < pb && cb <= k) ? Gm[rk * ld + cb] : 0.0;
+                        }
+#pragma unroll
+                        for (int q = 0; q < 4; ++q)
+                            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[q], bv[q], acc, 0, 0, 0);
+                    }
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int m = 4 * r + (lane >> 4), c = J * 16 + (lane & 15);
+                        if (c < nsv)
+                            part[m * nsv + c] = acc[r];
+                    }
+                }
+                wave_order();
+            }
+            const int c = lane;
+            double tv[16];
+#pragma unroll
+            for (int m = 0; m < 16; ++m)
+                tv[m] = (pb > 0 && c < pb && pb + m < u) ? part[m * nsv + c] : 0.0;
+#pragma unroll
+            for (int m = 0; m < 16; ++m) {
+                if (pb + m < u) {
+                    // row pb + m of L's diagonal block: uniform LDS addresses (broadcast reads)
+                    const double *lrow = Gm + (int64_t)acc_idx[pb + m] * ld + pb;
+                    double acc = tv[m];
+#pragma unroll
+                    for (int m2 = 0; m2 < m; ++m2)
+                        acc += lrow[m2] * tv[m2];
+                    const double pinv = lane_bcast(pinvreg, pb + m);
+                    tv[m] = c == pb + m ? pinv : (c < pb + m ? -acc * pinv : 0.0);
+                }
+            }
+            wave_order();
+#pragma unroll
+            for (int m = 0; m < 16; ++m)
+                if (pb + m < u && c <= pb + m)
+                    Gm[(int64_t)acc_idx[pb + m] * ld + c] = tv[m];
+            wave_order();
+        }
+        if (lane == 0) {
+            s_u = u;
+            s_nrej = nrej;
+            s_stop = stop;
+        }
+    }
+    __syncthreads();
+    const int u = s_u, nrej = s_nrej, stop = s_stop;
+    // 4. Q = T R_acc, written as V[N0 + r] (FP64), its FP32 rounding, and the LDS cache.
+    // Wave w takes the 16-column tiles J = w, w + nw, ...: the R values of a column tile
+    // are loaded once (all at once) and serve every 16-row tile of Q.
+    const int64_t JT = (D + 15) / 16;
+    const int IT = (u + 15) / 16;
+    for (int64_t J = w; J < JT && u > 0; J += nw) {
+        const int64_t jc = J * 16 + (lane & 15);
+        double bv[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int k = 4 * q + (lane >> 4);
+            bv[q] = (k < u && jc < D) ? row(acc_idx[k])[jc] : 0.0;
+        }
+        for (int I = 0; I < IT; ++I) {
+            const int iq = I * 16 + (lane & 15);
+            const double *trow = iq < u ? Gm + (int64_t)acc_idx[iq] * ld : nullptr;
+            f64x4_t acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                if (4 * q < u) {
+                    const int k = 4 * q + (lane >> 4);
+                    const double av = (trow && k <= iq) ? trow[k] : 0.0;
+                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv[q], acc, 0, 0, 0);
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = I * 16 + 4 * r + (lane >> 4);
+                if (i < u && jc < D) {
+                    a.V[(N0 + i) * D + jc] = acc[r];
+                    if (a.Vs)
+                        a.Vs[(N0 + i) * D + jc] = (float)acc[r];
+                    if (i < cslots)
+                        cache2[(int64_t)i * D + jc] = acc[r];
+                }
+            }
+        }
+    }
+    __syncthreads();  // Q is complete (global and LDS); T is no longer needed
+    // 5. explicit residual norms of the provisional rejections: C = R_rej Q^T (masked to the
+    // accepted rows that precede each rejected row), then ||R_rej - C Q|| without storing it
+    const int ldc = u > 0 ? u : 1;
+    double *C = part;  // nrej x u <= (nsv/2)^2 <= 16 nsv
+    auto qrow = [&](int c) -> const double * { return c < cslots ? cache2 + (int64_t)c * D : a.V + (N0 + c) * D; };
+    if (nrej > 0 && u > 0) {
+        // <R_rej, Q_c> = sum_{k <= c} T[c][k] G[rej][acc_k], from the copy of G (T is row
+        // acc_idx[c] of Gm, columns k <= c); one 16 x 16 tile of C per wave
+        const int RT = (nrej + 15) / 16, CT = (u + 15) / 16;
+        auto gsym = [&](int p, int q) -> double { return p >= q ? Gc[p * ld + q] : Gc[q * ld + p]; };
+        for (int t = w; t < RT * CT; t += nw) {
+            const int I = t / CT, J = t % CT;
+            const int ir = I * 16 + (lane & 15), jq = J * 16 + (lane & 15);
+            const int rrow = ir < nrej ? rej_idx[ir] : 0;
+            const double *trow = jq < u ? Gm + (int64_t)acc_idx[jq] * ld : nullptr;
+            f64x4_t acc = {0.0, 0.0, 0.0, 0.0};
+            for (int k0 = 0; k0 < u; k0 += 4) {
+                const int k = k0 + (lane >> 4);
+                const double av = (ir < nrej && k < u) ? gsym(rrow, acc_idx[k]) : 0.0;
+                const double bv = (trow && k <= jq) ? trow[k] : 0.0;
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = I * 16 + 4 * r + (lane >> 4), c = J * 16 + (lane & 15);
+                if (i < nrej && c < u)
+                    C[i * ldc + c] = acc_idx[c] < rej_idx[i] ? acc[r] : 0.0;
+            }
+        }
+        __syncthreads();
+    }
+    if (nrej > 0) {
+        // wave w takes the column tiles J = w, w + nw, ... in a fixed order (the Q values of a
+        // column tile are loaded once for all rejected rows); the per-wave partial sums are
+        // added in wave order, so the result is deterministic
+        const int RT = (nrej + 15) / 16;  // <= 4
+        double sq[4][4] = {};
+        for (int64_t J = w; J < JT; J += nw) {
+            const int64_t jc = J * 16 + (lane & 15);
+            double bq[16];
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const int k = 4 * q + (lane >> 4);
+                bq[q] = (k < u && jc < D) ? qrow(k)[jc] : 0.0;
+            }
+#pragma unroll
+            for (int I = 0; I < 4; ++I) {
+                if (I < RT) {
+                    const int ir = I * 16 + (lane & 15);
+                    f64x4_t acc;
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int i = I * 16 + 4 * r + (lane >> 4);
+                        acc[r] = (i < nrej && jc < D) ? row(rej_idx[i])[jc] : 0.0;
+                    }
+#pragma unroll
+                    for (int q = 0; q < 16; ++q) {
+                        if (4 * q < u) {
+                            const int k = 4 * q + (lane >> 4);
+                            const double av = (ir < nrej && k < u) ? -C[ir * ldc + k] : 0.0;
+                            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bq[q], acc, 0, 0, 0);
+                        }
+                    }
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        sq[I][r] += acc[r] * acc[r];
+                }
+            }
+        }
+#pragma unroll
+        for (int I = 0; I < 4; ++I) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                double v = sq[I][r];
+                for (int off = 1; off < 16; off <<= 1)
+                    v += __shfl_xor(v, off, 64);
+                const int i = I * 16 + 4 * r + (lane >> 4);
+                if ((lane & 15) == 0 && i < nrej)
+                    Gc[w * nsv + i] = v;  // the Gram copy is no longer needed
+            }
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < nrej; i += blockDim.x) {
+            double t = 0.0;
+            for (int q = 0; q < nw; ++q)
+                t += Gc[q * nsv + i];
+            vn[i] = sqrt(t);
+        }
+        __syncthreads();
+    }
+    // 6. the first provisional rejection above the threshold (or non-finite) ends the pass
+    if (threadIdx.x == 0) {
+        int resume = stop, uk = u;
+        for (int q = 0; q < nrej; ++q) {
+            const double v = vn[q];
+            if (!(v <= a.tol)) {
+                resume = rej_idx[q];
+                break;
+            }
+        }
+        if (resume < stop) {
+            uk = 0;
+            while (uk < u && acc_idx[uk] < resume)
+                ++uk;
+        }
+        // statistics of the rows decided here: [0] max rejected residual, [1] min accepted
+        double mr = 0.0, ma = INFINITY;
+        for (int q = 0; q < nrej && rej_idx[q] < resume; ++q)
+            mr = fmax(mr, vn[q]);
+        for (int q = 0; q < uk; ++q)
+            ma = fmin(ma, piv[q]);
+        stat[0] = mr;
+        stat[1] = ma;
+        s_resume = resume;
+        s_uk = uk;
+    }
+    __syncthreads();
+    return BqrOut{s_resume, s_uk};
+}
+
 // Dynamic LDS layout of the acceptance kernel: coef[cnt] | R[D] | slots x D
 // cached copies of the vectors appended earlier in the block (the rest are
 // read from the basis in global memory).
-__device__ void accept_body(const AcceptArgs &a)
+__device__ __forceinline__ void accept_body(const AcceptArgs &a)
 {
     extern __shared__ double dyn[];
     __shared__ double red[16];
@@ -524,13 +999,51 @@ __device__ void accept_body(const AcceptArgs &a)
         l_sdep = 0.0;
         l_sind = INFINITY;
     }
+    // block Cholesky-QR pass over the survivors (brackets only, at most 64 survivors)
+    const int64_t gram_need = bqr_lds(nsv, nw);
+    const bool gram_ok = a.mode == 1 && nsv >= 2 && nsv <= 64 && nw >= 16 && meta_in_lds &&
+                         slots * D - 3 * (int64_t)nsv >= gram_need;
+    double *gram_base = cache2;
+    if (gram_ok)
+        cache2 = gram_base + gram_need;
+    const int64_t slots3 =
+        gram_ok ? std::max<int64_t>(0, (slots * D - 3 * (int64_t)nsv - gram_need) / D) : slots2;
     double *cbase = meta_in_lds ? cache2 : cache;
-    const int64_t cslots = meta_in_lds ? slots2 : slots;
+    const int64_t cslots = meta_in_lds ? slots3 : slots;
+    int r_first = 0;
+    if (gram_ok) {
+        __shared__ double bstat[2];
+        const BqrOut b = block_qr(a, nsv, N0, gram_base, cache2, cslots, bstat);
+        if (threadIdx.x == 0) {
+            // rows 0 .. resume-1 are decided: b.u accepted, the rest rejected
+            const double thr = a.tol;
+            for (int r = 0; r < b.resume; ++r) {
+                if (sn_a[r] >= 0.0) {
+                    if (sn_a[r] > thr)
+                        l_sind = fmin(l_sind, rs_a[r]);
+                    else
+                        l_sdep = fmax(l_sdep, rs_a[r]);
+                }
+            }
+            l_fp64 += b.resume;
+            l_acc += b.u;
+            l_maxrej = fmax(l_maxrej, bstat[0]);
+            l_minacc = fmin(l_minacc, bstat[1]);
+            st->n_bqr += b.u;
+            sN = N0 + b.u;
+            if (a.early_exit && sN >= a.ambient)
+                st->done = 1;
+        }
+        __syncthreads();
+        r_first = b.resume;
+        if (a.early_exit && sN >= a.ambient)
+            r_first = nsv;  // nothing more to decide
+    }
     constexpr int PF = 16;  // residual elements prefetched per thread (D <= 16 * blockDim)
     double pf[PF];
     auto row_of = [&](int r) -> const double * { return a.H + (int64_t)(a.rrow ? a.rrow[r] : r) * D; };
-    if (nsv > 0) {
-        const double *Rg = row_of(0);
+    if (r_first < nsv) {
+        const double *Rg = row_of(r_first);
 #pragma unroll
         for (int k = 0; k < PF; ++k) {
             const int64_t j = threadIdx.x + (int64_t)k * blockDim.x;
@@ -543,7 +1056,7 @@ __device__ void accept_body(const AcceptArgs &a)
     const int G = D <= 256 ? (int)std::min<int64_t>(16, blockDim.x / D) : 1;
     const int gid = G > 1 ? (int)(threadIdx.x / D) : 0;
     const int64_t gt = G > 1 ? (int64_t)(threadIdx.x % D) : 0;
-    for (int r = 0; r < nsv; ++r) {
+    for (int r = r_first; r < nsv; ++r) {
         lds_barrier();  // everyone has read the previous survivor's verdict and R
 #pragma unroll
         for (int k = 0; k < PF; ++k) {

@@ -37,6 +37,7 @@ struct DevState {
     int32_t full;            // 1: an append was refused because the capacity is reached
     int32_t done;            // 1: early-exit bound reached
     int32_t pad;
+    int64_t n_bqr;           // appended by the block Cholesky-QR prefix of the acceptance kernel
 };
 
 // Pair index p <-> (l, m) with 0 <= m < l: p = l(l-1)/2 + m.  Row l holds the

@@ -240,3 +240,45 @@ def test_adaptive_default_su16(precision):
     assert dim == ref.dim == 255 and st["candidates"] == ref.candidates
     assert pins.span_distance(v, ref.basis) <= SPAN_TOL_MIXED
     assert st["block"] < 0  # adaptive
+
+
+# Block Cholesky-QR of a block's survivors: certified acceptances from the Gram
+# pivots, provisional rejections checked with explicit residuals, and a hand-over
+# to the sequential path at the first provisional rejection that is independent.
+BQR_CASES = {
+    "su16": (lambda: W.rand_pair(16, seed=2), 1e-10, 255),   # Jacobi-identity dependencies inside blocks
+    "ising4": (lambda: W.ising(4), 1e-10, 28),               # exact zero and duplicate brackets
+    "pauli4x6": (lambda: W.pauli_set(4, 6, 11), 1e-10, None),  # many duplicate Pauli strings per block
+    "pair12": (lambda: W.rand_pair(12, seed=4), 1e-10, 143),
+}
+
+
+@pytest.mark.parametrize("case", list(BQR_CASES))
+@pytest.mark.parametrize("block", [0, 16, 64])
+def test_block_qr_matches_sequential(case, block):
+    """The block Cholesky-QR decisions and vectors against the one-survivor-at-a-time path."""
+    make, tol, expected = BQR_CASES[case]
+    gens = make()
+    ref = reference(gens, tol, False)
+    dim, v, st, orth = gpu_closure(gens, tol, block=block)
+    dim1, v1, st1, _ = gpu_closure(gens, tol, block=1)
+    assert dim == dim1 == ref.dim
+    if expected is not None:
+        assert dim == expected
+    assert st1["block_qr_accepted"] == 0  # one candidate per block: nothing to factor
+    assert st["block_qr_accepted"] > 0
+    assert st["candidates"] == ref.candidates
+    assert np.max(np.abs(v - v1)) <= ELEM_TOL_FP64
+    assert np.max(np.abs(v - ref.basis)) <= ELEM_TOL_FP64
+    assert orth <= ORTH_TOL_FP64
+
+
+def test_block_qr_early_exit_at_ambient():
+    """Early exit reached inside a factored block: stops at d^2 - 1 exactly."""
+    gens = W.rand_pair(8, seed=7)
+    ref = reference(gens, 1e-10, True)
+    dim, v, st, orth = gpu_closure(gens, 1e-10, early_exit=True, block=64)
+    assert dim == ref.dim == 63 and st["done"] == 1
+    assert st["block_qr_accepted"] > 0
+    assert pins.span_distance(v, ref.basis) <= SPAN_TOL_FP64
+    assert orth <= ORTH_TOL_FP64
