@@ -168,6 +168,7 @@ struct lie_closure {
     int *surv_rows = nullptr;    // block: survivor -> candidate
     int64_t *surv_pairs = nullptr;  // block: survivor -> pair index
     int *slot = nullptr;         // block: candidate -> survivor or -1
+    int *keep = nullptr;         // block: survivors left to the in-block decisions (acceptance kernel)
     int *nsurv = nullptr;        // 1: survivor count
     lie::DevState *st = nullptr;
     double *scalar = nullptr;    // one double of device scratch
@@ -207,8 +208,8 @@ struct lie_closure {
         for (void *p : {(void *)d_cursor, (void *)V64, (void *)Vs, (void *)H64, (void *)Hs, (void *)C, (void *)Cs,
                         (void *)part,
                         (void *)normpart_s, (void *)cand_a2, (void *)cand_n2, (void *)rho2, (void *)h2, (void *)h2b,
-                        (void *)surv_rows, (void *)surv_pairs, (void *)slot, (void *)nsurv, (void *)st,
-                        (void *)scalar})
+                        (void *)surv_rows, (void *)surv_pairs, (void *)slot, (void *)keep, (void *)nsurv,
+                        (void *)st, (void *)scalar})
             if (p)
                 (void)hipFree(p);
         if (own_stream && stream)
@@ -305,6 +306,7 @@ struct lie_closure {
         a.slot = slot;
         a.nsurv = nsurv;
         a.surv_cand = surv_rows;
+        a.keep = keep;
         a.h2 = h2_surv;
         a.rho2 = rho2;
         a.cnt = cnt;
@@ -768,6 +770,7 @@ lie_status lie_closure_init(lie_closure **out, const double *generators, int32_t
         (s = alloc(&h->rho2, bmax)) != LIE_OK || (s = alloc(&h->h2, bmax)) != LIE_OK ||
         (s = alloc(&h->h2b, bmax)) != LIE_OK || (s = alloc(&h->surv_rows, bmax)) != LIE_OK ||
         (s = alloc(&h->surv_pairs, bmax)) != LIE_OK || (s = alloc(&h->slot, bmax)) != LIE_OK ||
+        (s = alloc(&h->keep, bmax)) != LIE_OK ||
         (s = alloc(&h->nsurv, 1)) != LIE_OK || (s = alloc(&h->scalar, 1)) != LIE_OK ||
         (s = alloc(&h->d_cursor, 1)) != LIE_OK ||
         (s = alloc(&h->st, 1)) != LIE_OK)
@@ -1304,6 +1307,7 @@ struct lie_closure_batch {
             a.slot = h->slot;
             a.nsurv = h->nsurv;
             a.surv_cand = h->surv_rows;
+            a.keep = h->keep;
             a.h2 = screen ? h->h2 : nullptr;
             a.rho2 = h->rho2;
             a.cnt = it.cnt;

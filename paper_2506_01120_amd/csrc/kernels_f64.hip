@@ -500,8 +500,10 @@ __device__ __forceinline__ BqrOut block_qr(const AcceptArgs &a, int nsv, int64_t
     double *part = vn + 3 * nsv;
     double *Gc = part + (int64_t)nw * nsv;  // copy of G for the verification coefficients
     __shared__ int s_u, s_nrej, s_stop, s_resume, s_uk;
-    for (int r = threadIdx.x; r < nsv; r += blockDim.x)
-        hrow[r] = a.rrow ? a.rrow[r] : r;
+    for (int r = threadIdx.x; r < nsv; r += blockDim.x) {
+        const int sr = a.rho2 && a.keep ? a.keep[r] : r;  // the caller's survivor order (see sv_of)
+        hrow[r] = a.rrow ? a.rrow[sr] : sr;
+    }
     __syncthreads();
     auto row = [&](int r) -> const double * { return a.H + (int64_t)hrow[r] * D; };
     // 1. Gram matrix, lower 16 x 16 tiles (I >= J), one tile per wave.  The survivor rows are
@@ -976,20 +978,7 @@ __device__ __forceinline__ void accept_body(const AcceptArgs &a)
     if (stop)
         return;
     // ---- phase B
-    // per-survivor scalars go to LDS first, counters stay in LDS until the end,
-    // and the next survivor's residual is prefetched into registers
     const int64_t N0 = sN;
-    const int nsv = ns;
-    double *hn_a = cache, *rs_a = hn_a + nsv, *sn_a = rs_a + nsv;
-    double *cache2 = sn_a + nsv;
-    const int64_t slots2 = slots > 0 ? std::max<int64_t>(0, (slots * D - 3 * (int64_t)nsv) / D) : 0;
-    const bool meta_in_lds = slots * D >= 3 * (int64_t)nsv;
-    for (int r = threadIdx.x; r < nsv && meta_in_lds; r += blockDim.x) {
-        const int c = a.surv_cand[r];
-        hn_a[r] = sqrt(a.h2 ? a.h2[r] : a.cand_n2[c]);
-        rs_a[r] = sqrt(a.cand_a2[c]);
-        sn_a[r] = a.rho2 ? sqrt(a.rho2[r]) : -1.0;
-    }
     __shared__ int64_t l_fp64, l_zero, l_acc, l_gen;
     __shared__ double l_maxrej, l_minacc, l_sdep, l_sind;
     if (threadIdx.x == 0) {
@@ -999,6 +988,83 @@ __device__ __forceinline__ void accept_body(const AcceptArgs &a)
         l_sdep = 0.0;
         l_sind = INFINITY;
     }
+    // Snapshot rejections, in parallel: a survivor whose FP64 residual against the block's
+    // basis snapshot is already at or below the threshold stays dependent on every superset
+    // of that basis, so it is rejected here; the others (their survivor indices in order)
+    // go to a.keep and on to the in-block decisions.
+    int nsv = ns;
+    const bool use_keep = a.rho2 && a.keep && ns > 0;
+    if (use_keep) {
+        __shared__ int s_wcnt[16];
+        __shared__ int s_base;
+        if (threadIdx.x == 0)
+            s_base = 0;
+        unsigned long long krej = 0;
+        double kmax = 0.0, kdep = 0.0;
+        for (int r0 = 0; r0 < ns; r0 += blockDim.x) {
+            const int r = r0 + threadIdx.x;
+            bool kp = false;
+            if (r < ns) {
+                const int c = a.surv_cand[r];
+                const double hn = sqrt(a.h2 ? a.h2[r] : a.cand_n2[c]);
+                const double snap = sqrt(a.rho2[r]);
+                const double thr = a.mode == 0 ? a.tol * hn : a.tol;
+                const bool rej = snap <= thr && hn > 0.0 && isfinite(hn);  // NaN: left to the exact path
+                kp = !rej;
+                if (rej && a.mode == 1) {
+                    ++krej;
+                    kmax = fmax(kmax, snap);
+                    kdep = fmax(kdep, sqrt(a.cand_a2[c]));
+                }
+            }
+            const unsigned long long bal = __ballot(kp);
+            const int wpre = __popcll(bal & ((1ull << lane) - 1ull));
+            __syncthreads();  // s_base and s_wcnt of the previous chunk are settled
+            if (lane == 0)
+                s_wcnt[w] = __popcll(bal);
+            __syncthreads();
+            int off = s_base;
+            for (int q = 0; q < w; ++q)
+                off += s_wcnt[q];
+            if (kp)
+                a.keep[off + wpre] = r;
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                int t = 0;
+                for (int q = 0; q < nw; ++q)
+                    t += s_wcnt[q];
+                s_base += t;
+            }
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            krej += __shfl_down(krej, off, 64);
+            kmax = fmax(kmax, __shfl_down(kmax, off, 64));
+            kdep = fmax(kdep, __shfl_down(kdep, off, 64));
+        }
+        if (lane == 0 && krej) {
+            atomicAdd((unsigned long long *)&l_fp64, krej);
+            atomic_max_pos(&l_maxrej, kmax);
+            atomic_max_pos(&l_sdep, kdep);
+        }
+        __syncthreads();
+        nsv = s_base;
+    }
+    // survivor index of the k-th survivor left to decide
+    auto sv_of = [&](int k) -> int { return use_keep ? a.keep[k] : k; };
+    // per-survivor scalars go to LDS first, counters stay in LDS until the end,
+    // and the next survivor's residual is prefetched into registers
+    double *hn_a = cache, *rs_a = hn_a + nsv, *sn_a = rs_a + nsv;
+    double *cache2 = sn_a + nsv;
+    const int64_t slots2 = slots > 0 ? std::max<int64_t>(0, (slots * D - 3 * (int64_t)nsv) / D) : 0;
+    const bool meta_in_lds = slots * D >= 3 * (int64_t)nsv;
+    for (int k = threadIdx.x; k < nsv && meta_in_lds; k += blockDim.x) {
+        const int r = sv_of(k);
+        const int c = a.surv_cand[r];
+        hn_a[k] = sqrt(a.h2 ? a.h2[r] : a.cand_n2[c]);
+        rs_a[k] = sqrt(a.cand_a2[c]);
+        sn_a[k] = a.rho2 ? sqrt(a.rho2[r]) : -1.0;
+    }
+    __syncthreads();
     // block Cholesky-QR pass over the survivors (brackets only, at most 64 survivors)
     const int64_t gram_need = bqr_lds(nsv, nw);
     const bool gram_ok = a.mode == 1 && nsv >= 2 && nsv <= 64 && nw >= 16 && meta_in_lds &&
@@ -1041,7 +1107,10 @@ __device__ __forceinline__ void accept_body(const AcceptArgs &a)
     }
     constexpr int PF = 16;  // residual elements prefetched per thread (D <= 16 * blockDim)
     double pf[PF];
-    auto row_of = [&](int r) -> const double * { return a.H + (int64_t)(a.rrow ? a.rrow[r] : r) * D; };
+    auto row_of = [&](int k) -> const double * {
+        const int r = sv_of(k);
+        return a.H + (int64_t)(a.rrow ? a.rrow[r] : r) * D;
+    };
     if (r_first < nsv) {
         const double *Rg = row_of(r_first);
 #pragma unroll
@@ -1078,10 +1147,11 @@ __device__ __forceinline__ void accept_body(const AcceptArgs &a)
             rs = rs_a[r];
             snap = sn_a[r];
         } else {
-            const int c = a.surv_cand[r];
-            hn = sqrt(a.h2 ? a.h2[r] : a.cand_n2[c]);
+            const int sr = sv_of(r);
+            const int c = a.surv_cand[sr];
+            hn = sqrt(a.h2 ? a.h2[sr] : a.cand_n2[c]);
             rs = sqrt(a.cand_a2[c]);
-            snap = a.rho2 ? sqrt(a.rho2[r]) : -1.0;
+            snap = a.rho2 ? sqrt(a.rho2[sr]) : -1.0;
         }
         const double thr = a.mode == 0 ? a.tol * hn : a.tol;
         if (threadIdx.x == 0 && a.mode == 1 && snap >= 0.0) {

@@ -195,6 +195,7 @@ struct AcceptArgs {
     const int *surv_cand;    // survivor r -> candidate c
     const double *h2;        // per survivor: squared FP64 candidate norm (null: cand_n2 of its candidate)
     const double *rho2;      // per survivor: squared FP64 residual against the block's basis snapshot
+    int *keep;               // scratch (cnt ints): survivors left after the snapshot rejections
     int cnt;
     int64_t D, cap, ambient;
     double tol;
