@@ -132,6 +132,9 @@ def main():
     ap.add_argument("--decide", default="screen", choices=["fp64", "strict", "screen"])
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--early-exit", action="store_true")
+    ap.add_argument("--autotune", action="store_true",
+                    help="pick the saturated block size and GEMM tiles by timing them at init (before timing)")
+    ap.add_argument("--tune-cache", default=None, help="text cache of autotuner choices")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="skip the one-candidate-at-a-time FP64 comparison run")
     args = ap.parse_args()
@@ -147,7 +150,8 @@ def main():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
     gens, tol, desc = workload(args.workload)
-    cfg = dict(precision=args.precision, decide=args.decide, block=args.block, early_exit=args.early_exit)
+    cfg = dict(precision=args.precision, decide=args.decide, block=args.block, early_exit=args.early_exit,
+               autotune=args.autotune, tune_cache=args.tune_cache)
 
     print(f"[bench] warmup {args.warmup} x {args.workload} {cfg}", file=sys.stderr, flush=True)
     if args.warmup:
@@ -193,7 +197,10 @@ def main():
                    "dim": (dims[0] if not isinstance(gens, list) else sum(dims[0])),
                    "checks_per_step": checks // args.steps, "precision": args.precision,
                    "decide": args.decide if args.precision != "fp64" else "fp64",
-                   "block": stats0[0]["block"], "early_exit": bool(args.early_exit), "parallelism": "single GPU"},
+                   "block": stats0[0]["block"], "block_growth": stats0[0]["block_growth"],
+                   "tile_dot": stats0[0]["tile_dot"], "tile_sub": stats0[0]["tile_sub"],
+                   "autotuned": stats0[0]["autotuned"], "early_exit": bool(args.early_exit),
+                   "parallelism": "single GPU"},
         "roofline": roof,
         "cpu_baseline": cpu,
         "plain_fp64": plain,

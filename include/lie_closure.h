@@ -80,7 +80,13 @@ typedef struct lie_closure_config {
     void *stream;          /* hipStream_t the handle runs on; NULL = a stream the library creates */
     int32_t use_graphs;    /* 1: replay block steps from captured hipGraphs (default 1) */
     int32_t profile;       /* 1: time every kernel launch with HIP events on the handle's stream */
-    int32_t reserved[6];   /* must be zero */
+    int32_t autotune;      /* 1 (adaptive blocks only): pick the saturated block size and the screening GEMM
+                              tiles by timing them on the device at init (about 0.1-1 s once per device,
+                              precision, d and ambient bound; remembered for the process); 0: heuristics */
+    int32_t reserved0;     /* must be zero */
+    const char *tune_cache;/* autotune: text file of earlier choices, read at init and appended to after a
+                              timing run (NULL: no file); the library does not keep the pointer */
+    int32_t reserved[2];   /* must be zero */
 } lie_closure_config;
 
 /* Kernel classes reported by the per-kernel counters of lie_closure_stats. */
@@ -119,6 +125,9 @@ typedef struct lie_closure_stats {
     int32_t precision, decide;
     int32_t block;                /* fixed block size, or -(saturated size) when adaptive */
     int32_t early_exit;
+    int32_t tile_dot, tile_sub;   /* screening GEMM tiles of full saturated blocks (0: shape heuristic) */
+    int32_t autotuned;            /* 1: sizes from a timing run at init, 2: from the tune cache, 0: heuristics */
+    int32_t block_growth;         /* adaptive: block size of the growth phase */
     /* Per kernel class (lie_kernel_id), accumulated over the run: launches, and
      * the algorithmic floating-point operations and bytes those launches must
      * perform (formulas in the engine source).  kernel_ms is the summed

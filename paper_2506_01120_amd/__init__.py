@@ -12,6 +12,7 @@ used, only supplies device memory (``basis_device``) and a HIP stream.
 from __future__ import annotations
 
 import ctypes
+import os
 
 import numpy as np
 
@@ -23,7 +24,8 @@ __all__ = ["LieClosure", "BatchClosure", "closure", "LieError", "make_config"]
 
 def make_config(*, precision: str = "fp64", decide: str = "screen", block: int = 0, early_exit: bool = False,
                 tau_rej: float = 0.0, max_dim: int = 0, stream=None, device: int | None = None,
-                use_graphs: bool = True, profile: bool = False) -> _lib.Config:
+                use_graphs: bool = True, profile: bool = False, autotune: bool = False,
+                tune_cache: str | None = None) -> _lib.Config:
     cfg = _lib.Config()
     _lib.check(_lib.load().lie_closure_config_default(ctypes.byref(cfg)))
     cfg.precision = _lib.PRECISIONS[precision]
@@ -35,6 +37,10 @@ def make_config(*, precision: str = "fp64", decide: str = "screen", block: int =
     cfg.device = -1 if device is None else int(device)
     cfg.use_graphs = 1 if use_graphs else 0
     cfg.profile = 1 if profile else 0
+    cfg.autotune = 1 if autotune else 0
+    # the bytes object must outlive the init call that reads it; the Config keeps it
+    cfg._tune_cache_bytes = None if tune_cache is None else os.fsencode(tune_cache)
+    cfg.tune_cache = cfg._tune_cache_bytes
     if stream is not None:
         cfg.stream = int(getattr(stream, "cuda_stream", stream))
     return cfg

@@ -47,7 +47,10 @@ class Config(ctypes.Structure):
         ("stream", ctypes.c_void_p),
         ("use_graphs", ctypes.c_int32),
         ("profile", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 6),
+        ("autotune", ctypes.c_int32),
+        ("reserved0", ctypes.c_int32),
+        ("tune_cache", ctypes.c_char_p),
+        ("reserved", ctypes.c_int32 * 2),
     ]
 
 
@@ -76,6 +79,10 @@ class Stats(ctypes.Structure):
         ("decide", ctypes.c_int32),
         ("block", ctypes.c_int32),
         ("early_exit", ctypes.c_int32),
+        ("tile_dot", ctypes.c_int32),
+        ("tile_sub", ctypes.c_int32),
+        ("autotuned", ctypes.c_int32),
+        ("block_growth", ctypes.c_int32),
         ("kernel_launches", ctypes.c_int64 * K_COUNT),
         ("kernel_ms", ctypes.c_double * K_COUNT),
         ("kernel_flops", ctypes.c_double * K_COUNT),

@@ -144,6 +144,8 @@ struct lie_closure {
     int block = 1;           // fixed block size, or 0: adaptive (growth / saturated sizes below)
     int block_growth = 32;   // adaptive: block size while most candidates are accepted
     int block_sat = 1024;    // adaptive: block size once acceptances are rare
+    int tile_dot = 0, tile_sub = 0;  // screening GEMM tiles of full saturated blocks (0: heuristic)
+    int autotuned = 0;       // 1: timed at init, 2: from the tune cache
     int bmax = 1;            // allocation bound of any block
     bool screened = false;   // FP32 screening pass in front of the FP64 decisions
     int policy = lie::POL_ALL;
@@ -388,20 +390,22 @@ struct lie_closure {
         timer.begin(stream);
         HIP_TRY(lie::launch_comm_f32(Vs, d, cursor, cnt, st, Hs, cand_n2, stream, dp0));
         timer.end(LIE_K_COMM, stream, 8.0 * dd * dd * dd * c, 3.0 * c * Dd * w);
-        const int tile_dot = lie::gemm_tile_f32(cnt, nh), tile_sub = lie::gemm_tile_f32(cnt, D);
+        const bool tuned = cnt == block_sat && tile_dot > 0;
+        const int tile_d = tuned ? tile_dot : lie::gemm_tile_f32(cnt, nh);
+        const int tile_s = tuned ? tile_sub : lie::gemm_tile_f32(cnt, D);
         const bool bf = cfg.precision == LIE_PREC_BF16X3;
         const int64_t ldc = lie::coef_ld(cap);
         timer.begin(stream);
-        HIP_TRY(bf ? lie::launch_gemm_dot_bf16x3(Vs, st, Hs, cnt, D, nh, ldc, Cs, tile_dot, stream)
-                   : lie::launch_gemm_dot_f32(Vs, st, Hs, cnt, D, nh, ldc, Cs, tile_dot, stream));
+        HIP_TRY(bf ? lie::launch_gemm_dot_bf16x3(Vs, st, Hs, cnt, D, nh, ldc, Cs, tile_d, stream)
+                   : lie::launch_gemm_dot_f32(Vs, st, Hs, cnt, D, nh, ldc, Cs, tile_d, stream));
         timer.end(LIE_K_DOT, stream, 2.0 * N * Dd * c, (N * Dd + c * Dd + c * N) * w);
         timer.begin(stream);
-        HIP_TRY(bf ? lie::launch_gemm_sub_bf16x3(Vs, st, Hs, Cs, nh, ldc, cnt, D, normpart_s, tile_sub, stream)
-                   : lie::launch_gemm_sub_f32(Vs, st, Hs, Cs, nh, ldc, cnt, D, normpart_s, tile_sub, stream));
+        HIP_TRY(bf ? lie::launch_gemm_sub_bf16x3(Vs, st, Hs, Cs, nh, ldc, cnt, D, normpart_s, tile_s, stream)
+                   : lie::launch_gemm_sub_f32(Vs, st, Hs, Cs, nh, ldc, cnt, D, normpart_s, tile_s, stream));
         timer.end(LIE_K_SUB, stream, 2.0 * N * Dd * c, (N * Dd + c * N + c * Dd) * w);
         timer.begin(stream);
         HIP_TRY(lie::launch_norm_final(normpart_s, nullptr, cnt,
-                                       bf ? lie::gemm_sub_tiles_bf16(D, tile_sub) : lie::gemm_sub_tiles_f32(D, tile_sub),
+                                       bf ? lie::gemm_sub_tiles_bf16(D, tile_s) : lie::gemm_sub_tiles_f32(D, tile_s),
                                        st, cand_a2, nullptr, stream));
         timer.end(LIE_K_REDUCE, stream, 0, 0);
         lie_status s;
@@ -635,6 +639,11 @@ lie_status resolve_config(const lie_closure_config *in, lie_closure_config *out)
     for (int r : out->reserved)
         if (r != 0)
             return fail(LIE_ERR_ARG, "config.reserved must be zero");
+    if (out->reserved0 != 0)
+        return fail(LIE_ERR_ARG, "config.reserved0 must be zero");
+    if (out->autotune != 0 && out->autotune != 1)
+        return fail(LIE_ERR_ARG, "config.autotune must be 0 or 1");
+    out->tune_cache = nullptr;  // read at init only (see lie_closure_init), never kept
     return LIE_OK;
 }
 
@@ -748,6 +757,20 @@ lie_status lie_closure_init(lie_closure **out, const double *generators, int32_t
         if (h->block == 0) {
             h->block_sat = std::min(h->block_sat, maxb);
             h->block_growth = std::min(h->block_growth, h->block_sat);
+        }
+        if (h->block == 0 && cfg.autotune) {
+            lie::TuneChoice tc{};
+            bool cached = false;
+            const hipError_t e = lie::autotune_block_step(dev, cfg.precision, d, ambient, maxb,
+                                                          cfg_in ? cfg_in->tune_cache : nullptr, h->stream, &tc,
+                                                          &cached);
+            if (e != hipSuccess)
+                return bail(fail(LIE_ERR_DEVICE, "autotuning failed: %s", hipGetErrorString(e)));
+            h->block_sat = tc.block_sat;
+            h->tile_dot = tc.tile_dot;
+            h->tile_sub = tc.tile_sub;
+            h->block_growth = std::min(h->block_growth, h->block_sat);
+            h->autotuned = cached ? 2 : 1;
         }
     }
     const int b = h->block > 0 ? h->block : std::max(h->block_growth, h->block_sat);
@@ -908,6 +931,10 @@ lie_status lie_closure_stats_get(const lie_closure *h, lie_closure_stats *out)
     out->decide = h->cfg.decide;
     out->block = h->block > 0 ? h->block : -h->block_sat;
     out->early_exit = h->cfg.early_exit;
+    out->tile_dot = h->tile_dot;
+    out->tile_sub = h->tile_sub;
+    out->autotuned = h->autotuned;
+    out->block_growth = h->block > 0 ? h->block : h->block_growth;
     for (int k = 0; k < LIE_K_COUNT; ++k) {
         out->kernel_launches[k] = h->timer.n[k];
         out->kernel_ms[k] = h->timer.ms[k];
@@ -1510,6 +1537,7 @@ lie_status lie_closure_batch_init(lie_closure_batch **out, int32_t n_problems, c
     lie_closure_config pc = cfg;
     pc.stream = b->stream;  // every problem runs on the batch's stream
     pc.device = dev;
+    pc.tune_cache = cfg_in ? cfg_in->tune_cache : nullptr;  // resolve_config drops the pointer
     for (int32_t i = 0; i < n_problems; ++i) {
         lie_closure *h = nullptr;
         s = lie_closure_init(&h, generators[i], n_gen[i], d[i], tol[i], &pc);
@@ -1589,6 +1617,10 @@ lie_status lie_closure_batch_stats_get(const lie_closure_batch *b, int32_t i, li
         agg.decide = one.decide;
         agg.block = one.block;
         agg.early_exit = one.early_exit;
+        agg.block_growth = one.block_growth;  // per-problem values: those of the last problem
+        agg.tile_dot = one.tile_dot;
+        agg.tile_sub = one.tile_sub;
+        agg.autotuned = std::max(agg.autotuned, one.autotuned);
     }
     agg.blocks = b->rounds;
     agg.host_syncs = b->host_syncs;

@@ -276,4 +276,17 @@ hipError_t launch_classify(const double *a2, const double *n2, int cnt, int64_t 
                            const DevState *st, int *rows, int64_t *pairs, int *slot, int *nsurv, hipStream_t s,
                            const int64_t *dp0 = nullptr);
 
+// ------------------------------------------------------------- autotuner (autotune.hip)
+struct TuneChoice {
+    int block_sat;            // saturated-phase block size
+    int tile_dot, tile_sub;   // FP32 / split-BF16 GEMM tiles (gemm_tile_f32 codes; 0 for FP64)
+    double us_per_candidate;  // timed cost of the two projection GEMMs per candidate
+};
+// Times the coefficient and residual GEMMs of one saturated block step (basis at the
+// ambient bound) for every admissible block size (<= max_block) and tile pair on
+// `device`, and returns the fastest.  Looks up (and appends to) the text cache at
+// cache_path when it is non-null; *from_cache tells whether any timing was run.
+hipError_t autotune_block_step(int device, int precision, int d, int64_t ambient, int max_block, const char *cache_path,
+                               hipStream_t s, TuneChoice *out, bool *from_cache);
+
 }  // namespace lie

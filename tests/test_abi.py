@@ -118,7 +118,13 @@ def test_config_validation(lib):
         setattr(cfg, field, bad)
         assert _init(lib, g, 3, 4, 1e-10, cfg)[0] == -1, field
     cfg = make_config()
-    cfg.reserved[2] = 1
+    cfg.reserved[1] = 1
+    assert _init(lib, g, 3, 4, 1e-10, cfg)[0] == -1
+    cfg = make_config()
+    cfg.reserved0 = 1
+    assert _init(lib, g, 3, 4, 1e-10, cfg)[0] == -1
+    cfg = make_config()
+    cfg.autotune = 2
     assert _init(lib, g, 3, 4, 1e-10, cfg)[0] == -1
 
 
