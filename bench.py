@@ -105,6 +105,58 @@ def roofline(stats, precision: str):
             "avg_launch_us": 1e6 * t / n[dom], "breakdown": breakdown}
 
 
+# kernel class -> source file of its kernels (the traffic record is void once that file changes)
+KERNEL_SOURCE = {
+    "accept": "kernels_f64.hip",
+    "verify": "kernels_gemm.hip",
+    "dot": {"fp64": "kernels_gemm.hip", "fp32": "kernels_gemm.hip", "bf16x3": "kernels_bf16.hip"},
+    "sub": {"fp64": "kernels_gemm.hip", "fp32": "kernels_gemm.hip", "bf16x3": "kernels_bf16.hip"},
+    "comm": {"fp64": "kernels_f64.hip", "fp32": "kernels_screen.hip", "bf16x3": "kernels_screen.hip"},
+}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.txt")
+
+
+def source_sha256(kernel: str, precision: str):
+    import hashlib
+
+    src = KERNEL_SOURCE.get(kernel)
+    if isinstance(src, dict):
+        src = src.get(precision)
+    if not src:
+        return None
+    path = os.path.join(ROOT, "paper_2506_01120_amd", "csrc", src)
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def measured_traffic(kernel: str, workload: str, precision: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter record, if
+    it was taken on this workload and the kernel's source is unchanged since; else None."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    sha = source_sha256(kernel, precision)
+    for line in open(TRAFFIC_FILE):
+        f = dict(kv.split("=", 1) for kv in line.split() if "=" in kv)
+        if (f.get("kernel") == kernel and f.get("workload") == workload and f.get("precision") == precision
+                and f.get("source_sha256") == sha):
+            return float(f["fetch_bytes_per_launch"]) + float(f["write_bytes_per_launch"])
+    return None
+
+
+def calibrate_copy(mib: int, copies: int = 5):
+    """A plain device-to-device copy of known size, for scaling the FETCH_SIZE and
+    WRITE_SIZE counters (run under rocprofv3 --pmc)."""
+    import torch
+
+    n = mib << 20
+    src = torch.ones(n, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(copies):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibration": "device-to-device copy", "bytes_per_copy": n, "copies": copies}))
+
+
 def cpu_baseline(gens, tol, early_exit: bool, target_s: float = 10.0):
     """The CPU reference as it stands, single-threaded, on this host: whole closures until ~target_s."""
     from oracle import oracle as ref
@@ -137,7 +189,12 @@ def main():
     ap.add_argument("--tune-cache", default=None, help="text cache of autotuner choices")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="skip the one-candidate-at-a-time FP64 comparison run")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a device copy of MIB MiB (counter calibration) and exit")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        calibrate_copy(args.calibrate_copy)
+        return
 
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: this build has no multi-GPU path (asked for --gpus {args.gpus}).",
@@ -166,6 +223,7 @@ def main():
     elapsed_p, stats, _ = run_steps(gens, tol, dict(cfg, profile=True), args.steps)
     roof = roofline(stats, args.precision)
     roof["profiled_ms_per_step"] = round(1e3 * elapsed_p / args.steps, 3)
+    roof["traffic"] = measured_traffic(roof["kernel"], args.workload, args.precision)
 
     plain = None
     if not args.no_plain:

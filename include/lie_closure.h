@@ -70,7 +70,8 @@ typedef struct lie_closure_config {
     uint32_t struct_size;  /* must be sizeof(lie_closure_config) */
     int32_t precision;     /* lie_precision, default LIE_PREC_FP64 */
     int32_t decide;        /* lie_decide, default LIE_DECIDE_SCREEN for screened precisions */
-    int32_t block;         /* candidates per block: 1 = plain one-at-a-time form, 2..4096 fixed, 0 = adaptive
+    int32_t block;         /* candidates per block: 1 = plain one-at-a-time form, 2..16384 fixed (bounded by
+                              the acceptance kernel's LDS: about 18000 - d^2), 0 = adaptive
                               (small FP64-decided blocks while most candidates are accepted, large
                               screened blocks after) */
     int32_t early_exit;    /* 1: stop once |V| equals the ambient bound (exact; d^2-1 for traceless inputs) */

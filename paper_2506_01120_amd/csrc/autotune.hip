@@ -189,7 +189,7 @@ hipError_t autotune_block_step(int device, int precision, int d, int64_t ambient
     const int64_t n = std::max<int64_t>(ambient, 1);
     const int64_t ldc = coef_ld(n);
     std::vector<int> blocks;
-    for (int b : {1024, 2048, 3072, 4096})
+    for (int b : {1024, 2048, 4096, 8192, 16384})
         if (b <= max_block)
             blocks.push_back(b);
     if (blocks.empty())

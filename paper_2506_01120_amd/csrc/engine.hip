@@ -50,7 +50,7 @@ constexpr int kGrowthQueued = 4;
 constexpr double kDefaultTauFp32 = 1e-4;
 // Default SCREEN reject threshold on the split-BF16-screened residual.
 constexpr double kDefaultTauBf16x3 = 1e-2;
-constexpr int kMaxBlock = 4096;
+constexpr int kMaxBlock = 16384;
 constexpr int kMaxD = 128;
 
 int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
@@ -941,6 +941,16 @@ lie_status lie_closure_stats_get(const lie_closure *h, lie_closure_stats *out)
         out->kernel_flops[k] = h->timer.flops[k];
         out->kernel_bytes[k] = h->timer.bytes[k];
     }
+    // The acceptance kernel's work depends on device-side survivor counts, so its
+    // algorithmic bytes are formed from the run's counters: per candidate its
+    // classification record (an int and two doubles), per survivor left to the
+    // in-block decisions its residual row, per appended element its FP64 row (and
+    // FP32 shadow when screened).
+    {
+        const double D = (double)h->D;
+        out->kernel_bytes[LIE_K_ACCEPT] = 20.0 * (double)h->hs.n_cand + 8.0 * D * (double)h->hs.n_rows +
+                                          (8.0 + (h->screened ? 4.0 : 0.0)) * D * (double)h->hs.n_acc;
+    }
     return LIE_OK;
 }
 
@@ -1595,6 +1605,7 @@ lie_status lie_closure_batch_stats_get(const lie_closure_batch *b, int32_t i, li
     agg.done = b->done ? 1 : 0;
     agg.min_accepted_residual = INFINITY;
     agg.screen_min_independent = INFINITY;
+    double acc_bytes = 0.0;  // acceptance bytes come from each problem's counters
     for (lie_closure *h : b->probs) {
         lie_closure_stats one;
         one.struct_size = sizeof one;
@@ -1621,6 +1632,7 @@ lie_status lie_closure_batch_stats_get(const lie_closure_batch *b, int32_t i, li
         agg.tile_dot = one.tile_dot;
         agg.tile_sub = one.tile_sub;
         agg.autotuned = std::max(agg.autotuned, one.autotuned);
+        acc_bytes += one.kernel_bytes[LIE_K_ACCEPT];
     }
     agg.blocks = b->rounds;
     agg.host_syncs = b->host_syncs;
@@ -1631,6 +1643,7 @@ lie_status lie_closure_batch_stats_get(const lie_closure_batch *b, int32_t i, li
         agg.kernel_flops[k] = b->timer.flops[k];
         agg.kernel_bytes[k] = b->timer.bytes[k];
     }
+    agg.kernel_bytes[LIE_K_ACCEPT] = acc_bytes;
     *out = agg;
     return LIE_OK;
 }

@@ -401,7 +401,7 @@ int split_k(int64_t D, int cnt, int64_t n_hi)
 // normalised and appended as V[N] (and its FP32 rounding as Vs[N]).
 
 constexpr int kAccThreads = 1024;
-constexpr int kMaxBlock = 4096;
+constexpr int kMaxBlock = 16384;
 
 
 
@@ -1316,6 +1316,7 @@ __device__ __forceinline__ void accept_body(const AcceptArgs &a)
     }
     __syncthreads();
     if (threadIdx.x == 0) {
+        st->n_rows += nsv;
         st->n_fp64 += l_fp64;
         st->n_zero += l_zero;
         st->n_acc += l_acc;

@@ -38,6 +38,7 @@ struct DevState {
     int32_t done;            // 1: early-exit bound reached
     int32_t pad;
     int64_t n_bqr;           // appended by the block Cholesky-QR prefix of the acceptance kernel
+    int64_t n_rows;          // survivor residual rows read by the acceptance kernel's in-block decisions
 };
 
 // Pair index p <-> (l, m) with 0 <= m < l: p = l(l-1)/2 + m.  Row l holds the

@@ -113,7 +113,7 @@ def test_config_validation(lib):
     cfg = make_config()
     cfg.struct_size = 3
     assert _init(lib, g, 3, 4, 1e-10, cfg)[0] == -1
-    for field, bad in (("precision", 7), ("decide", -1), ("block", 5000), ("max_dim", -2)):
+    for field, bad in (("precision", 7), ("decide", -1), ("block", 20000), ("max_dim", -2)):
         cfg = make_config()
         setattr(cfg, field, bad)
         assert _init(lib, g, 3, 4, 1e-10, cfg)[0] == -1, field
