@@ -227,9 +227,21 @@ def main():
 
     plain = None
     if not args.no_plain:
-        print("[bench] plain one-at-a-time FP64 comparison step", file=sys.stderr, flush=True)
-        pt, pstats, _ = run_steps(gens, tol, dict(cfg, precision="fp64", block=1), 1)
-        plain = {"checks_per_s": pstats[0]["candidates"] / pt, "ms_per_step": 1e3 * pt}
+        plain_cfg = dict(cfg, precision="fp64", block=1, autotune=False)
+        if isinstance(gens, list):
+            # the batched workload's denominator: every problem on its own, one candidate at a time
+            print("[bench] plain one-at-a-time FP64 comparison: each problem alone", file=sys.stderr, flush=True)
+            pt, pc = 0.0, 0
+            for p in gens:
+                t, ps, _ = run_steps(p.gens, p.tol, plain_cfg, 1)
+                pt += t
+                pc += ps[0]["candidates"]
+            plain = {"checks_per_s": pc / pt, "ms_per_step": 1e3 * pt, "form": "each problem alone, block 1, FP64"}
+        else:
+            print("[bench] plain one-at-a-time FP64 comparison step", file=sys.stderr, flush=True)
+            pt, pstats, _ = run_steps(gens, tol, plain_cfg, 1)
+            plain = {"checks_per_s": pstats[0]["candidates"] / pt, "ms_per_step": 1e3 * pt,
+                     "form": "block 1, FP64"}
 
     cpu = None
     if not args.no_cpu_baseline:
