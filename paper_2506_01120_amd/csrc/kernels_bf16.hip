@@ -86,35 +86,28 @@ struct SplitRowLoader {
 };
 
 // Row-major FP32 K x N operand (rows k, contiguous n): [k0, k0+KC) x [n0, n0+BN) -> split bf16 S[n][k].
+// A thread takes one column n and 8 consecutive rows k (eight 4-byte loads, each coalesced
+// across the wave along n), splits them, and stores each of hi and lo as one 16-byte
+// vector at S[n][8g .. 8g+8) -- the layout the MFMA operand reads back.
 template <int BN>
 struct SplitColLoader {
-    static constexpr int TOTAL = KC * BN / 4;
+    static constexpr int GROUPS = KC / 8;
+    static constexpr int TOTAL = BN * GROUPS;  // (column, 8-row group) items per tile
     static constexpr int PER_THREAD = (TOTAL + 255) / 256;
-    float v[PER_THREAD][4];
+    float v[PER_THREAD][8];
 
     __device__ void load(const float *__restrict__ base, int64_t ld, int64_t k0, int64_t K, int64_t n0, int64_t Ncols,
-                         bool vec_ok)
+                         bool)
     {
 #pragma unroll
         for (int i = 0; i < PER_THREAD; ++i) {
             const int q = threadIdx.x + 256 * i;
-            const int kk = q / (BN / 4), nv = (q % (BN / 4)) * 4;
-            const int64_t k = k0 + kk, n = n0 + nv;
-            v[i][0] = v[i][1] = v[i][2] = v[i][3] = 0.f;
-            if (q < TOTAL && k < K) {
-                const float *p = base + k * ld + n;
-                if (vec_ok && n + 4 <= Ncols) {
-                    const float4 t = *reinterpret_cast<const float4 *>(p);
-                    v[i][0] = t.x;
-                    v[i][1] = t.y;
-                    v[i][2] = t.z;
-                    v[i][3] = t.w;
-                } else {
+            const int n = q % BN, g = q / BN;
+            const int64_t col = n0 + n;
 #pragma unroll
-                    for (int u = 0; u < 4; ++u)
-                        if (n + u < Ncols)
-                            v[i][u] = p[u];
-                }
+            for (int u = 0; u < 8; ++u) {
+                const int64_t k = k0 + 8 * g + u;
+                v[i][u] = (q < TOTAL && col < Ncols && k < K) ? base[k * ld + col] : 0.f;
             }
         }
     }
@@ -124,10 +117,17 @@ struct SplitColLoader {
         for (int i = 0; i < PER_THREAD; ++i) {
             const int q = threadIdx.x + 256 * i;
             if (q < TOTAL) {
-                const int kk = q / (BN / 4), nv = (q % (BN / 4)) * 4;
+                const int n = q % BN, g = q / BN;
+                bf16x8 h, l;
 #pragma unroll
-                for (int u = 0; u < 4; ++u)
-                    split(v[i][u], Sh[nv + u][kk], Sl[nv + u][kk]);
+                for (int u = 0; u < 8; ++u) {
+                    __bf16 hu, lu;
+                    split(v[i][u], hu, lu);
+                    h[u] = hu;
+                    l[u] = lu;
+                }
+                *reinterpret_cast<bf16x8 *>(&Sh[n][8 * g]) = h;
+                *reinterpret_cast<bf16x8 *>(&Sl[n][8 * g]) = l;
             }
         }
     }
