@@ -37,6 +37,14 @@
  *     generator is traceless, d^2 otherwise): no further candidate can be
  *     independent there.  Off by default (the literal algorithm).
  *
+ * Algorithm 3 (lo_enable_raw): the same loop, but the brackets are taken
+ * between the raw elements B -- the accepted generators and the accepted
+ * brackets themselves, not their orthonormalised versions -- while the
+ * independence test still runs against the span of the accepted candidates.
+ * Raw nested brackets have no fixed scale, so a raw bracket h is accepted iff
+ * its residual exceeds tol * ||h|| (the generator phase's relative rule).
+ * B is returned alongside V.
+ *
  * Storage: operators are d x d complex, row-major, vectorised as length d*d.
  * Reflector j is H_j = I - 2 u_j u_j^H with ||u_j||_2 = 1 and u_j[k] = 0 for
  * k < j; Q = H_0 H_1 ... H_{N-1} has the accepted candidates' span in its
@@ -60,6 +68,7 @@ typedef struct lo_state {
     double tol;
     cplx *U;          /* cap reflectors, each of length n */
     cplx *V;          /* cap basis elements, each of length n, paper-normalised */
+    cplx *B;          /* Algorithm 3 only: cap raw elements (generators and brackets), else NULL */
     cplx *x;          /* candidate scratch, length n */
     cplx *y;          /* transformed candidate, length n */
     cplx *t1, *t2;    /* d x d product scratch */
@@ -165,6 +174,8 @@ static int append_residual(lo_state *s)
     const int64_t N = s->N, n = s->n;
     if (N >= s->cap || N >= n)
         return -1;
+    if (s->B)  /* Algorithm 3: keep the raw candidate itself */
+        memcpy(s->B + N * n, s->x, (size_t)n * sizeof(cplx));
     const double ynorm = vec_norm2(s->y + N, n - N);
     /* h_perp in the candidate's coordinates */
     cplx *h = s->V + N * n;
@@ -234,9 +245,22 @@ void lo_free(lo_state *s)
 {
     if (!s)
         return;
-    free(s->U); free(s->V); free(s->x); free(s->y); free(s->t1); free(s->t2);
+    free(s->U); free(s->V); free(s->B); free(s->x); free(s->y); free(s->t1); free(s->t2);
     free(s->log_l); free(s->log_m); free(s->log_r); free(s->log_acc);
     free(s);
+}
+
+/*
+ * Switch to Algorithm 3: keep the raw elements B and bracket them instead of V.
+ * Must be called before the first generator.  Returns 0, or -1 (too late, or
+ * out of memory).
+ */
+int lo_enable_raw(lo_state *s)
+{
+    if (s->N != 0 || s->n_gen_checks != 0 || s->B)
+        return -1;
+    s->B = malloc((size_t)(s->cap * s->n) * sizeof(cplx));
+    return s->B ? 0 : -1;
 }
 
 /*
@@ -283,8 +307,9 @@ int64_t lo_brackets(lo_state *s, int early_exit, int64_t ambient, int64_t budget
         if (budget >= 0 && done_here >= budget)
             break;
         const int64_t l = s->l, m = s->m;
-        const cplx *a = s->V + l * s->n;
-        const cplx *b = s->V + m * s->n;
+        const cplx *src = s->B ? s->B : s->V;  /* Algorithm 3 brackets raw elements */
+        const cplx *a = src + l * s->n;
+        const cplx *b = src + m * s->n;
         matmul(d, a, b, s->t1);
         matmul(d, b, a, s->t2);
         int zero = 1;
@@ -299,7 +324,8 @@ int64_t lo_brackets(lo_state *s, int early_exit, int64_t ambient, int64_t budget
             s->n_zero++;
         } else {
             r = ls_residual(s);
-            if (r > s->tol) {
+            const double thr = s->B ? s->tol * vec_norm2(s->x, s->n) / sqrt((double)d) : s->tol;
+            if (r > thr) {
                 if (append_residual(s) != 0)
                     return -1;
                 acc = 1;
@@ -333,6 +359,17 @@ int64_t lo_cursor_row(const lo_state *s) { return s->l; }
 int64_t lo_cursor_col(const lo_state *s) { return s->m; }
 
 /* Copy V (N x d x d complex, interleaved) into out. */
+/* Raw basis B of Algorithm 3 (interleaved re,im; N x d x d); no-op without it. */
+void lo_raw_basis(const lo_state *s, double *out)
+{
+    if (!s->B)
+        return;
+    for (int64_t k = 0; k < s->N * s->n; ++k) {
+        out[2 * k] = creal(s->B[k]);
+        out[2 * k + 1] = cimag(s->B[k]);
+    }
+}
+
 void lo_basis(const lo_state *s, double *out)
 {
     for (int64_t k = 0; k < s->N * s->n; ++k) {

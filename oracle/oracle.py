@@ -54,6 +54,10 @@ def _declare(lib: ctypes.CDLL) -> ctypes.CDLL:
         getattr(lib, name).argtypes = [vp]
     lib.lo_basis.restype = None
     lib.lo_basis.argtypes = [vp, dptr]
+    lib.lo_raw_basis.restype = None
+    lib.lo_raw_basis.argtypes = [vp, dptr]
+    lib.lo_enable_raw.restype = i32
+    lib.lo_enable_raw.argtypes = [vp]
     lib.lo_log_copy.restype = None
     lib.lo_log_copy.argtypes = [vp, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
     lib.lo_residual_of.restype = dbl
@@ -98,13 +102,14 @@ class OracleResult:
     min_accepted: float
     max_rejected: float
     log: dict = field(default_factory=dict)
+    raw_basis: np.ndarray | None = None  # Algorithm 3: (dim, d, d) raw elements (generators, brackets)
 
 
 class Oracle:
     """Stateful reference closure; supports budgeted runs that resume exactly."""
 
     def __init__(self, gens: np.ndarray, tol: float, *, max_dim: int | None = None, log: bool = False,
-                 lib: ctypes.CDLL | None = None):
+                 raw: bool = False, lib: ctypes.CDLL | None = None):
         gens = np.ascontiguousarray(np.asarray(gens, dtype=np.complex128))
         if gens.ndim != 3 or gens.shape[1] != gens.shape[2]:
             raise ValueError("generators must have shape (n_gen, d, d)")
@@ -116,6 +121,9 @@ class Oracle:
         self._s = self.lib.lo_new(self.d, cap, self.tol, 1 if log else 0)
         if not self._s:
             raise MemoryError("oracle allocation failed")
+        self.raw = bool(raw)
+        if self.raw and self.lib.lo_enable_raw(self._s) != 0:
+            raise MemoryError("oracle allocation failed (raw basis)")
         self.accepted_generators = []
         for i, g in enumerate(gens):
             buf = np.ascontiguousarray(g).view(np.float64).reshape(-1)
@@ -153,6 +161,16 @@ class Oracle:
             self.lib.lo_basis(self._s, _dptr(out.view(np.float64).reshape(-1)))
         return out
 
+    def raw_basis(self) -> np.ndarray | None:
+        """Algorithm 3's raw elements B (accepted generators and brackets, unnormalised)."""
+        if not self.raw:
+            return None
+        n = self.dim
+        out = np.empty((n, self.d, self.d), dtype=np.complex128)
+        if n:
+            self.lib.lo_raw_basis(self._s, _dptr(out.view(np.float64).reshape(-1)))
+        return out
+
     def residual_of(self, x: np.ndarray) -> float:
         buf = np.ascontiguousarray(np.asarray(x, dtype=np.complex128)).view(np.float64).reshape(-1)
         return float(self.lib.lo_residual_of(self._s, _dptr(buf)))
@@ -185,12 +203,13 @@ class Oracle:
             min_accepted=float(self.lib.lo_min_accepted(self._s)),
             max_rejected=float(self.lib.lo_max_rejected(self._s)),
             log=self.log(),
+            raw_basis=self.raw_basis(),
         )
 
 
 def closure(gens: np.ndarray, tol: float, *, early_exit: bool = False, max_dim: int | None = None,
-            log: bool = False, lib: ctypes.CDLL | None = None) -> OracleResult:
-    """Run the reference closure to completion and return its result."""
-    o = Oracle(gens, tol, max_dim=max_dim, log=log, lib=lib)
+            log: bool = False, raw: bool = False, lib: ctypes.CDLL | None = None) -> OracleResult:
+    """Run the reference closure to completion and return its result (raw=True: Algorithm 3)."""
+    o = Oracle(gens, tol, max_dim=max_dim, log=log, raw=raw, lib=lib)
     o.run(early_exit=early_exit)
     return o.result()
