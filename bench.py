@@ -187,6 +187,8 @@ def main():
     ap.add_argument("--autotune", action="store_true",
                     help="pick the saturated block size and GEMM tiles by timing them at init (before timing)")
     ap.add_argument("--tune-cache", default=None, help="text cache of autotuner choices")
+    ap.add_argument("--raw-basis", action="store_true",
+                    help="Algorithm 3: also keep the raw basis B and bracket raw elements (single problems)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="skip the one-candidate-at-a-time FP64 comparison run")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -208,7 +210,9 @@ def main():
         sys.exit(1)
     gens, tol, desc = workload(args.workload)
     cfg = dict(precision=args.precision, decide=args.decide, block=args.block, early_exit=args.early_exit,
-               autotune=args.autotune, tune_cache=args.tune_cache)
+               autotune=args.autotune, tune_cache=args.tune_cache, raw_basis=args.raw_basis)
+    if args.raw_basis and args.workload == "batch64":
+        raise SystemExit("--raw-basis is for single problems")
 
     print(f"[bench] warmup {args.warmup} x {args.workload} {cfg}", file=sys.stderr, flush=True)
     if args.warmup:
@@ -270,6 +274,7 @@ def main():
                    "block": stats0[0]["block"], "block_growth": stats0[0]["block_growth"],
                    "tile_dot": stats0[0]["tile_dot"], "tile_sub": stats0[0]["tile_sub"],
                    "autotuned": stats0[0]["autotuned"], "early_exit": bool(args.early_exit),
+                   "algorithm": "Algorithm 3 (raw basis kept)" if args.raw_basis else "Algorithm 4 (dimension only)",
                    "parallelism": "single GPU"},
         "roofline": roof,
         "cpu_baseline": cpu,

@@ -87,7 +87,11 @@ typedef struct lie_closure_config {
     int32_t reserved0;     /* must be zero */
     const char *tune_cache;/* autotune: text file of earlier choices, read at init and appended to after a
                               timing run (NULL: no file); the library does not keep the pointer */
-    int32_t reserved[2];   /* must be zero */
+    int32_t raw_basis;     /* 1: Algorithm 3 -- also keep the raw basis B (accepted generators and nested
+                              brackets, unnormalised) and bracket raw elements [B_l, B_m] instead of
+                              [V_l, V_m]; raw brackets are accepted iff their residual exceeds tol * ||h||
+                              (single problems only; doubles the basis memory) */
+    int32_t reserved[1];   /* must be zero */
 } lie_closure_config;
 
 /* Kernel classes reported by the per-kernel counters of lie_closure_stats. */
@@ -173,6 +177,13 @@ lie_status lie_closure_basis(const lie_closure *h, double *out, int64_t capacity
 
 /* Same into device memory of the handle's device (ordered on the handle's stream). */
 lie_status lie_closure_basis_device(const lie_closure *h, void *dst, int64_t capacity, int64_t *written);
+
+/* Algorithm 3 (Section 3.2): copy the raw basis B -- the accepted generators as given and the
+ * accepted nested brackets [B_l, B_m], unnormalised, in append order -- into a host buffer
+ * laid out like lie_closure_basis's (capacity * d * d complex128, interleaved re,im).
+ * span(B) = span(V).  *written = |B| = |V|.  Returns LIE_ERR_STATE if the handle was not
+ * created with config.raw_basis = 1, LIE_ERR_CAPACITY if capacity < |B| (nothing copied). */
+lie_status lie_closure_raw_basis(const lie_closure *h, double *out, int64_t capacity, int64_t *written);
 
 /* ||G - I||_F with G_ij = <V_i, V_j>, computed in FP64 on the device. */
 lie_status lie_closure_orthogonality(lie_closure *h, double *loss);

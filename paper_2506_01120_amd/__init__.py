@@ -25,7 +25,7 @@ __all__ = ["LieClosure", "BatchClosure", "closure", "LieError", "make_config"]
 def make_config(*, precision: str = "fp64", decide: str = "screen", block: int = 0, early_exit: bool = False,
                 tau_rej: float = 0.0, max_dim: int = 0, stream=None, device: int | None = None,
                 use_graphs: bool = True, profile: bool = False, autotune: bool = False,
-                tune_cache: str | None = None) -> _lib.Config:
+                tune_cache: str | None = None, raw_basis: bool = False) -> _lib.Config:
     cfg = _lib.Config()
     _lib.check(_lib.load().lie_closure_config_default(ctypes.byref(cfg)))
     cfg.precision = _lib.PRECISIONS[precision]
@@ -38,6 +38,7 @@ def make_config(*, precision: str = "fp64", decide: str = "screen", block: int =
     cfg.use_graphs = 1 if use_graphs else 0
     cfg.profile = 1 if profile else 0
     cfg.autotune = 1 if autotune else 0
+    cfg.raw_basis = 1 if raw_basis else 0
     # the bytes object must outlive the init call that reads it; the Config keeps it
     cfg._tune_cache_bytes = None if tune_cache is None else os.fsencode(tune_cache)
     cfg.tune_cache = cfg._tune_cache_bytes
@@ -112,6 +113,15 @@ class LieClosure:
         out = np.empty((max(n, 1), self.d, self.d), dtype=np.complex128)
         w = ctypes.c_int64()
         _lib.check(self._libh.lie_closure_basis(self._h, out.ctypes.data, n, ctypes.byref(w)))
+        return out[: w.value]
+
+    def raw_basis(self) -> np.ndarray:
+        """Algorithm 3's raw basis B (dim, d, d): accepted generators and nested brackets,
+        unnormalised, in append order (handle created with raw_basis=True)."""
+        n = self.dim
+        out = np.empty((max(n, 1), self.d, self.d), dtype=np.complex128)
+        w = ctypes.c_int64()
+        _lib.check(self._libh.lie_closure_raw_basis(self._h, out.ctypes.data, n, ctypes.byref(w)))
         return out[: w.value]
 
     def basis_device(self):

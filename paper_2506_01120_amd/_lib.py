@@ -27,7 +27,8 @@ DECIDES = {"fp64": 0, "strict": 1, "screen": 2}
 # Every symbol include/lie_closure.h declares.
 EXPORTS = (
     "lie_closure_config_default", "lie_closure_init", "lie_closure_run", "lie_closure_run_budget",
-    "lie_closure_dim", "lie_closure_basis", "lie_closure_basis_device", "lie_closure_orthogonality",
+    "lie_closure_dim", "lie_closure_basis", "lie_closure_basis_device", "lie_closure_raw_basis",
+    "lie_closure_orthogonality",
     "lie_closure_stats_get", "lie_closure_free", "lie_status_string", "lie_last_error",
     "lie_closure_batch_init", "lie_closure_batch_run", "lie_closure_batch_dim", "lie_closure_batch_basis",
     "lie_closure_batch_stats_get", "lie_closure_batch_free",
@@ -50,7 +51,8 @@ class Config(ctypes.Structure):
         ("autotune", ctypes.c_int32),
         ("reserved0", ctypes.c_int32),
         ("tune_cache", ctypes.c_char_p),
-        ("reserved", ctypes.c_int32 * 2),
+        ("raw_basis", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 1),
     ]
 
 
@@ -118,6 +120,7 @@ def _declare(lib: ctypes.CDLL) -> ctypes.CDLL:
         "lie_closure_dim": (st, [vp, i64p]),
         "lie_closure_basis": (st, [vp, vp, i64, i64p]),
         "lie_closure_basis_device": (st, [vp, vp, i64, i64p]),
+        "lie_closure_raw_basis": (st, [vp, vp, i64, i64p]),
         "lie_closure_orthogonality": (st, [vp, dblp]),
         "lie_closure_stats_get": (st, [vp, ctypes.POINTER(Stats)]),
         "lie_closure_free": (None, [vp]),

@@ -171,6 +171,12 @@ struct lie_closure {
     int64_t *surv_pairs = nullptr;  // block: survivor -> pair index
     int *slot = nullptr;         // block: candidate -> survivor or -1
     int *keep = nullptr;         // block: survivors left to the in-block decisions (acceptance kernel)
+    // Algorithm 3 (config.raw_basis): raw elements and where each came from
+    bool raw = false;
+    double *B64 = nullptr;       // cap x D, raw elements (packed), FP64
+    float *Bs = nullptr;         // cap x D, their FP32 rounding (screened modes)
+    double *Graw = nullptr;      // n_gen x D, packed generators as given
+    int64_t *elem_src = nullptr; // cap: pair index of each element, or -(generator + 1)
     int *nsurv = nullptr;        // 1: survivor count
     lie::DevState *st = nullptr;
     double *scalar = nullptr;    // one double of device scratch
@@ -211,7 +217,7 @@ struct lie_closure {
                         (void *)part,
                         (void *)normpart_s, (void *)cand_a2, (void *)cand_n2, (void *)rho2, (void *)h2, (void *)h2b,
                         (void *)surv_rows, (void *)surv_pairs, (void *)slot, (void *)keep, (void *)nsurv,
-                        (void *)st, (void *)scalar})
+                        (void *)st, (void *)scalar, (void *)B64, (void *)Bs, (void *)Graw, (void *)elem_src})
             if (p)
                 (void)hipFree(p);
         if (own_stream && stream)
@@ -295,7 +301,8 @@ struct lie_closure {
         return LIE_OK;
     }
 
-    lie_status accept(int cnt, int mode, bool screen_first, const int *rrow, const double *h2_surv, int kid)
+    lie_status accept(int cnt, int mode, bool screen_first, const int *rrow, const double *h2_surv, int kid,
+                      int64_t src0 = 0)
     {
         lie::AcceptArgs a{};
         a.V = V64;
@@ -309,6 +316,10 @@ struct lie_closure {
         a.nsurv = nsurv;
         a.surv_cand = surv_rows;
         a.keep = keep;
+        a.surv_pairs = surv_pairs;
+        a.elem_src = raw ? elem_src : nullptr;
+        a.src0 = src0;
+        a.rel = raw && mode == 1 ? 1 : 0;
         a.h2 = h2_surv;
         a.rho2 = rho2;
         a.cnt = cnt;
@@ -323,6 +334,12 @@ struct lie_closure {
         timer.begin(stream);
         HIP_TRY(lie::launch_accept_f64(a, stream));
         timer.end(kid, stream, 0, 0);
+        if (raw) {
+            // Algorithm 3: the raw rows of this launch's appends (brackets of raw rows)
+            timer.begin(stream);
+            HIP_TRY(lie::launch_raw_append(Graw, B64, Bs, d, elem_src, st, cnt, stream));
+            timer.end(LIE_K_OTHER, stream, 0, 0);
+        }
         return LIE_OK;
     }
 
@@ -336,9 +353,10 @@ struct lie_closure {
             double *p;
             ~Guard() { (void)hipFree(p); }
         } guard{staging};
-        double *packed = nullptr;
-        HIP_TRY(hipMalloc(&packed, (size_t)n_gen * D * sizeof(double)));
-        Guard guard2{packed};
+        double *packed = raw ? Graw : nullptr;  // Algorithm 3 keeps the packed generators
+        if (!raw)
+            HIP_TRY(hipMalloc(&packed, (size_t)n_gen * D * sizeof(double)));
+        Guard guard2{raw ? nullptr : packed};
         HIP_TRY(hipMemcpyAsync(staging, gens_host, bytes, hipMemcpyHostToDevice, stream));
         HIP_TRY(lie::launch_pack_c128(staging, packed, n_gen, d, stream));
         lie_status s;
@@ -351,7 +369,7 @@ struct lie_closure {
                 return s;
             if ((s = project(surv_rows, nsurv, rho2, h2b, 1, g, g, LIE_K_OTHER, LIE_K_OTHER, LIE_K_OTHER)) != LIE_OK)
                 return s;
-            if ((s = accept(1, 0, false, surv_rows, nullptr, LIE_K_OTHER)) != LIE_OK)
+            if ((s = accept(1, 0, false, surv_rows, nullptr, LIE_K_OTHER, -(int64_t)g - 1)) != LIE_OK)
                 return s;
         }
         if ((s = sync_state()) != LIE_OK)
@@ -366,13 +384,13 @@ struct lie_closure {
     {
         const double c = cnt, Dd = (double)D, dd = d;
         timer.begin(stream);
-        HIP_TRY(lie::launch_comm_f64(V64, d, cursor, nullptr, nullptr, cnt, st, H64, stream, dp0));
+        HIP_TRY(lie::launch_comm_f64(raw ? B64 : V64, d, cursor, nullptr, nullptr, cnt, st, H64, stream, dp0));
         timer.end(LIE_K_COMM, stream, 8.0 * dd * dd * dd * c, 3.0 * c * Dd * sizeof(double));
         lie_status s;
         if ((s = project(nullptr, nullptr, cand_a2, cand_n2, cnt, n_lo, n_hi, LIE_K_DOT, LIE_K_SUB, LIE_K_REDUCE)) !=
             LIE_OK)
             return s;
-        if ((s = classify(cnt, cursor, lie::POL_ABS, tol, dp0)) != LIE_OK)
+        if ((s = classify(cnt, cursor, raw ? lie::POL_REL : lie::POL_ABS, tol, dp0)) != LIE_OK)
             return s;
         // re-orthogonalisation pass for the survivors only (twice is enough)
         if ((s = project(surv_rows, nsurv, rho2, h2b, cnt, 0, n_hi, LIE_K_VERIFY, LIE_K_VERIFY, LIE_K_VERIFY)) !=
@@ -388,7 +406,7 @@ struct lie_closure {
         const double c = cnt, Dd = (double)D, dd = d, N = (double)n_lo, w = sizeof(float);
         const int64_t nh = std::min(std::max<int64_t>(n_hi, 1), cap);
         timer.begin(stream);
-        HIP_TRY(lie::launch_comm_f32(Vs, d, cursor, cnt, st, Hs, cand_n2, stream, dp0));
+        HIP_TRY(lie::launch_comm_f32(raw ? Bs : Vs, d, cursor, cnt, st, Hs, cand_n2, stream, dp0));
         timer.end(LIE_K_COMM, stream, 8.0 * dd * dd * dd * c, 3.0 * c * Dd * w);
         const bool tuned = cnt == block_sat && tile_dot > 0;
         const int tile_d = tuned ? tile_dot : lie::gemm_tile_f32(cnt, nh);
@@ -412,7 +430,7 @@ struct lie_closure {
         if ((s = classify(cnt, cursor, policy, policy_thr, dp0)) != LIE_OK)
             return s;
         timer.begin(stream);
-        HIP_TRY(lie::launch_comm_f64(V64, d, 0, surv_pairs, nsurv, cnt, st, H64, stream));
+        HIP_TRY(lie::launch_comm_f64(raw ? B64 : V64, d, 0, surv_pairs, nsurv, cnt, st, H64, stream));
         timer.end(LIE_K_VERIFY, stream, 0, 0);
         if ((s = project(nullptr, nsurv, rho2, h2, cnt, 0, n_hi, LIE_K_VERIFY, LIE_K_VERIFY, LIE_K_VERIFY)) != LIE_OK)
             return s;
@@ -641,6 +659,8 @@ lie_status resolve_config(const lie_closure_config *in, lie_closure_config *out)
             return fail(LIE_ERR_ARG, "config.reserved must be zero");
     if (out->reserved0 != 0)
         return fail(LIE_ERR_ARG, "config.reserved0 must be zero");
+    if (out->raw_basis != 0 && out->raw_basis != 1)
+        return fail(LIE_ERR_ARG, "config.raw_basis must be 0 or 1");
     if (out->autotune != 0 && out->autotune != 1)
         return fail(LIE_ERR_ARG, "config.autotune must be 0 or 1");
     out->tune_cache = nullptr;  // read at init only (see lie_closure_init), never kept
@@ -722,6 +742,14 @@ lie_status lie_closure_init(lie_closure **out, const double *generators, int32_t
             break;
         }
     }
+    h->raw = cfg.raw_basis != 0;
+    if (h->raw) {
+        // Algorithm 3: raw brackets have no fixed scale, so every threshold is relative to ||h||
+        if (h->policy == lie::POL_ABS)
+            h->policy = lie::POL_REL;
+        else if (h->policy == lie::POL_GE)
+            h->policy = lie::POL_GE_REL;
+    }
     h->cap = cfg.max_dim > 0 ? std::min<int64_t>(cfg.max_dim, h->D) : std::max<int64_t>(ambient, 1);
     h->device = -1;
 
@@ -798,6 +826,12 @@ lie_status lie_closure_init(lie_closure **out, const double *generators, int32_t
         (s = alloc(&h->d_cursor, 1)) != LIE_OK ||
         (s = alloc(&h->st, 1)) != LIE_OK)
         return bail(s);
+    if (h->raw) {
+        if ((s = alloc(&h->B64, (size_t)h->cap * D)) != LIE_OK || (s = alloc(&h->Graw, (size_t)n_gen * D)) != LIE_OK ||
+            (s = alloc(&h->elem_src, (size_t)h->cap)) != LIE_OK ||
+            (h->screened && (s = alloc(&h->Bs, (size_t)h->cap * D)) != LIE_OK))
+            return bail(s);
+    }
     if (h->screened) {
         if ((s = alloc(&h->Vs, (size_t)h->cap * D)) != LIE_OK || (s = alloc(&h->Hs, (size_t)bmax * D)) != LIE_OK ||
             (s = alloc(&h->Cs, (size_t)bmax * capr)) != LIE_OK ||
@@ -880,6 +914,33 @@ lie_status lie_closure_basis(const lie_closure *h, double *out, int64_t capacity
 lie_status lie_closure_basis_device(const lie_closure *h, void *dst, int64_t capacity, int64_t *written)
 {
     return basis_common(h, dst, capacity, written, true);
+}
+
+lie_status lie_closure_raw_basis(const lie_closure *h, double *out, int64_t capacity, int64_t *written)
+{
+    if (!h || !written || (!out && capacity > 0))
+        return fail(LIE_ERR_ARG, "NULL argument");
+    if (!h->raw)
+        return fail(LIE_ERR_STATE, "the handle was not created with config.raw_basis = 1");
+    const int64_t n = h->hs.N;
+    *written = n;
+    if (capacity < n)
+        return fail(LIE_ERR_CAPACITY, "output holds %lld elements, raw basis has %lld", (long long)capacity,
+                    (long long)n);
+    if (n == 0)
+        return LIE_OK;
+    HIP_TRY(hipSetDevice(h->device));
+    double *tmp = nullptr;
+    HIP_TRY(hipMalloc(&tmp, (size_t)n * h->D * 2 * sizeof(double)));
+    hipError_t e = lie::launch_unpack_c128(h->B64, tmp, n, h->d, h->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(out, tmp, (size_t)n * h->D * 2 * sizeof(double), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(h->stream);
+    (void)hipFree(tmp);
+    if (e != hipSuccess)
+        return fail(LIE_ERR_DEVICE, "raw basis copy failed: %s", hipGetErrorString(e));
+    return LIE_OK;
 }
 
 lie_status lie_closure_orthogonality(lie_closure *h, double *loss)
@@ -1514,6 +1575,8 @@ lie_status lie_closure_batch_init(lie_closure_batch **out, int32_t n_problems, c
     lie_status s = resolve_config(cfg_in, &cfg);
     if (s != LIE_OK)
         return s;
+    if (cfg.raw_basis)
+        return fail(LIE_ERR_ARG, "config.raw_basis (Algorithm 3) is supported for single problems only");
     // validate every problem before any device work
     for (int32_t i = 0; i < n_problems; ++i) {
         int64_t amb = 0;

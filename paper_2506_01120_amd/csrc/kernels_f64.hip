@@ -227,6 +227,37 @@ __global__ void __launch_bounds__(kThreads) k_comm_f64_lds_b(Batch b)
     const CommArgs a = static_cast<const CommArgs *>(b.args)[p];
     comm_f64_lds_body(a, blockIdx.x - b.start[p]);
 }
+// Algorithm 3: raw rows of the elements appended by the last acceptance launch.
+// Element e in [st->raw_lo, st->N) came from generator -(src+1) (its packed copy is
+// G's row) or from the bracket of raw rows l, m < raw_lo of its source pair.
+__global__ void __launch_bounds__(kThreads) k_raw_append(const double *G, double *B, float *Bs, int d,
+                                                         const int64_t *elem_src, const DevState *st, int use_lds)
+{
+    const int64_t lo = st->raw_lo, hi = st->N;
+    const int64_t D = (int64_t)d * d;
+    for (int64_t e = lo + blockIdx.x; e < hi; e += gridDim.x) {
+        const int64_t src = elem_src[e];
+        double *out = B + e * D;
+        if (src < 0) {
+            const double *g = G + (-src - 1) * D;
+            for (int64_t j = threadIdx.x; j < D; j += blockDim.x)
+                out[j] = g[j];
+        } else {
+            const CommArgs A{B, d, 0, elem_src + e, nullptr, nullptr, 1, nullptr, out, nullptr};
+            if (use_lds)
+                comm_f64_lds_body(A, 0);
+            else
+                for (int bx = 0; (int64_t)bx * blockDim.x < D; ++bx)
+                    comm_f64_global_body(A, bx, 0);
+        }
+        __syncthreads();  // row e is complete
+        if (Bs)
+            for (int64_t j = threadIdx.x; j < D; j += blockDim.x)
+                Bs[e * D + j] = (float)out[j];
+        __syncthreads();  // the operand LDS is reused by the next element
+    }
+}
+
 __global__ void __launch_bounds__(kThreads) k_comm_f64_global_b(Batch b)
 {
     const int p = batch_find(b.start, b.nprob, blockIdx.x);
@@ -490,7 +521,7 @@ struct BqrOut {
 // factorisation and the triangular inverse are one-wave recurrences in LDS (lane
 // i owns row i, resp. column i) that need no workgroup barrier.
 __device__ __forceinline__ BqrOut block_qr(const AcceptArgs &a, int nsv, int64_t N0, double *lds, double *cache2, int64_t cslots,
-                           double *stat)
+                           double *stat, const double *hn_rows)
 {
     const int64_t D = a.D;
     const int ld = gram_ld(nsv);
@@ -634,10 +665,11 @@ __device__ __forceinline__ BqrOut block_qr(const AcceptArgs &a, int nsv, int64_t
                     }
                     const double rr = dj * rinv;
                     const bool room = N0 + u < a.ambient && N0 + u < a.cap;
+                    const double thr_j = a.rel ? a.tol * hn_rows[j] : a.tol;  // decision threshold of row j
                     if (!isfinite(dj) || !isfinite(nj)) {
                         stop = j;  // the exact path reports the non-finite residual
                         halt = true;
-                    } else if (room && pos && rr >= 0.1 * nj && rr >= 10.0 * a.tol) {
+                    } else if (room && pos && rr >= 0.1 * nj && rr >= 10.0 * thr_j) {
                         const double li = i > j ? sv[t] * rinv : 0.0;
                         if (i > j && i < nsv)
                             Gm[i * ld + u] = li;
@@ -867,7 +899,7 @@ __device__ __forceinline__ BqrOut block_qr(const AcceptArgs &a, int nsv, int64_t
         int resume = stop, uk = u;
         for (int q = 0; q < nrej; ++q) {
             const double v = vn[q];
-            if (!(v <= a.tol)) {
+            if (!(v <= (a.rel ? a.tol * hn_rows[rej_idx[q]] : a.tol))) {
                 resume = rej_idx[q];
                 break;
             }
@@ -887,6 +919,11 @@ __device__ __forceinline__ BqrOut block_qr(const AcceptArgs &a, int nsv, int64_t
         stat[1] = ma;
         s_resume = resume;
         s_uk = uk;
+        if (a.elem_src)  // Algorithm 3: the source pair of each element appended here
+            for (int c = 0; c < uk; ++c) {
+                const int sr = a.rho2 && a.keep ? a.keep[acc_idx[c]] : acc_idx[c];
+                a.elem_src[N0 + c] = a.surv_pairs ? a.surv_pairs[sr] : -1;
+            }
     }
     __syncthreads();
     return BqrOut{s_resume, s_uk};
@@ -914,6 +951,8 @@ __device__ __forceinline__ void accept_body(const AcceptArgs &a)
     const int64_t slots = a.lds_doubles > a.cnt + D ? (a.lds_doubles - a.cnt - D) / D : 0;
     if (threadIdx.x == 0) {
         sN = st->N;
+        if (a.elem_src)
+            st->raw_lo = sN;  // the raw rows of this launch's appends start here
         stop = aborted(st);
         ns = a.nsurv ? *a.nsurv : 0;
         for (int i = 0; i < 4; ++i)
@@ -1008,7 +1047,7 @@ __device__ __forceinline__ void accept_body(const AcceptArgs &a)
                 const int c = a.surv_cand[r];
                 const double hn = sqrt(a.h2 ? a.h2[r] : a.cand_n2[c]);
                 const double snap = sqrt(a.rho2[r]);
-                const double thr = a.mode == 0 ? a.tol * hn : a.tol;
+                const double thr = (a.mode == 0 || a.rel) ? a.tol * hn : a.tol;
                 const bool rej = snap <= thr && hn > 0.0 && isfinite(hn);  // NaN: left to the exact path
                 kp = !rej;
                 if (rej && a.mode == 1) {
@@ -1079,11 +1118,11 @@ __device__ __forceinline__ void accept_body(const AcceptArgs &a)
     int r_first = 0;
     if (gram_ok) {
         __shared__ double bstat[2];
-        const BqrOut b = block_qr(a, nsv, N0, gram_base, cache2, cslots, bstat);
+        const BqrOut b = block_qr(a, nsv, N0, gram_base, cache2, cslots, bstat, hn_a);
         if (threadIdx.x == 0) {
             // rows 0 .. resume-1 are decided: b.u accepted, the rest rejected
-            const double thr = a.tol;
             for (int r = 0; r < b.resume; ++r) {
+                const double thr = a.rel ? a.tol * hn_a[r] : a.tol;
                 if (sn_a[r] >= 0.0) {
                     if (sn_a[r] > thr)
                         l_sind = fmin(l_sind, rs_a[r]);
@@ -1153,7 +1192,7 @@ __device__ __forceinline__ void accept_body(const AcceptArgs &a)
             rs = sqrt(a.cand_a2[c]);
             snap = a.rho2 ? sqrt(a.rho2[sr]) : -1.0;
         }
-        const double thr = a.mode == 0 ? a.tol * hn : a.tol;
+        const double thr = (a.mode == 0 || a.rel) ? a.tol * hn : a.tol;
         if (threadIdx.x == 0 && a.mode == 1 && snap >= 0.0) {
             // audit against the same basis snapshot the screen used
             if (snap > thr)
@@ -1300,6 +1339,8 @@ __device__ __forceinline__ void accept_body(const AcceptArgs &a)
         else
             __syncthreads();
         if (threadIdx.x == 0) {
+            if (a.elem_src)
+                a.elem_src[sN] = a.mode == 0 ? a.src0 : (a.surv_pairs ? a.surv_pairs[sv_of(r)] : -1);
             sN++;
             if (a.mode == 1) {
                 l_acc++;
@@ -1413,6 +1454,28 @@ hipError_t launch_unpack_c128(const double *src, double *dst, int64_t count, int
     if (blocks == 0)
         return hipSuccess;
     hipLaunchKernelGGL(k_unpack_c128, dim3((unsigned)blocks), dim3(kThreads), 0, s, src, dst, count, d);
+    return hipGetLastError();
+}
+
+hipError_t launch_raw_append(const double *G, double *B, float *Bs, int d, const int64_t *elem_src, const DevState *st,
+                             int max_new, hipStream_t s)
+{
+    if (max_new <= 0)
+        return hipSuccess;
+    const size_t lds = (size_t)4 * d * (d + 1) * sizeof(double);
+    static size_t granted = 65536;
+    bool use_lds = d <= 64;
+    if (use_lds && lds > granted) {
+        if (hipFuncSetAttribute((const void *)k_raw_append, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) ==
+            hipSuccess)
+            granted = lds;
+        else
+            (void)hipGetLastError();
+    }
+    use_lds = use_lds && lds <= granted;
+    const int grid = std::min(max_new, 1024);
+    hipLaunchKernelGGL(k_raw_append, dim3(grid), dim3(kThreads), use_lds ? lds : 0, s, G, B, Bs, d, elem_src, st,
+                       use_lds ? 1 : 0);
     return hipGetLastError();
 }
 

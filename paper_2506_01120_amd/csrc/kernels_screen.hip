@@ -263,6 +263,7 @@ __device__ void classify_body(const ClassifyArgs &A)
                 case POL_ABS: keep = h > 0.0 && r > thr; break;
                 case POL_REL: keep = h > 0.0 && r > thr * h; break;
                 case POL_GE: keep = h > 0.0 && r >= thr; break;
+                case POL_GE_REL: keep = h > 0.0 && r >= thr * h; break;
                 }
             }
         }

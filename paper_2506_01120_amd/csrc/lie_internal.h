@@ -39,6 +39,7 @@ struct DevState {
     int32_t pad;
     int64_t n_bqr;           // appended by the block Cholesky-QR prefix of the acceptance kernel
     int64_t n_rows;          // survivor residual rows read by the acceptance kernel's in-block decisions
+    int64_t raw_lo;          // Algorithm 3: |V| when the last acceptance launch started (raw rows from here on)
 };
 
 // Pair index p <-> (l, m) with 0 <= m < l: p = l(l-1)/2 + m.  Row l holds the
@@ -140,7 +141,8 @@ enum Policy {
     POL_ALL = 0,  // every candidate survives
     POL_ABS = 1,  // survive iff n2 > 0 and sqrt(a2) > thr
     POL_REL = 2,  // survive iff n2 > 0 and sqrt(a2) > thr * sqrt(n2)
-    POL_GE = 3    // survive iff n2 > 0 and sqrt(a2) >= thr
+    POL_GE = 3,   // survive iff n2 > 0 and sqrt(a2) >= thr
+    POL_GE_REL = 4  // survive iff n2 > 0 and sqrt(a2) >= thr * sqrt(n2)
 };
 
 // ------------------------------------------------------------- FP64 kernels
@@ -197,6 +199,10 @@ struct AcceptArgs {
     const double *h2;        // per survivor: squared FP64 candidate norm (null: cand_n2 of its candidate)
     const double *rho2;      // per survivor: squared FP64 residual against the block's basis snapshot
     int *keep;               // scratch (cnt ints): survivors left after the snapshot rejections
+    const int64_t *surv_pairs;  // Algorithm 3: survivor r -> pair index (null: not recorded)
+    int64_t *elem_src;       // Algorithm 3: element N -> its pair index, or -(generator + 1) (null: off)
+    int64_t src0;            // Algorithm 3, generator phase: the source code of the (single) candidate
+    int rel;                 // 1: brackets use the relative threshold tol * ||h|| (Algorithm 3)
     int cnt;
     int64_t D, cap, ambient;
     double tol;
@@ -210,6 +216,12 @@ hipError_t launch_accept_f64(const AcceptArgs &args, hipStream_t s);
 int64_t accept_lds_doubles(int cnt, int64_t D);
 // Largest block whose acceptance launch fits in LDS (coefficients + one residual).
 int accept_max_block(int64_t D);
+
+// Algorithm 3: raw rows B[e] for the elements appended by the last acceptance launch
+// (e in [st->raw_lo, st->N)): the packed generator G[g] for a source -(g+1), else the
+// packed bracket [B_l, B_m] of the source pair; Bs (if non-null) gets the FP32 rounding.
+hipError_t launch_raw_append(const double *G, double *B, float *Bs, int d, const int64_t *elem_src, const DevState *st,
+                             int max_new, hipStream_t s);
 
 // G = V V^T (n x n) then ||G - I||_F into *out (device), using `work` of n*n + 256 doubles.
 hipError_t launch_orth_loss(const double *V, int64_t n, int64_t D, double *work, double *out, hipStream_t s);

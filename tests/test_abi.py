@@ -118,7 +118,10 @@ def test_config_validation(lib):
         setattr(cfg, field, bad)
         assert _init(lib, g, 3, 4, 1e-10, cfg)[0] == -1, field
     cfg = make_config()
-    cfg.reserved[1] = 1
+    cfg.reserved[0] = 1
+    assert _init(lib, g, 3, 4, 1e-10, cfg)[0] == -1
+    cfg = make_config()
+    cfg.raw_basis = 3
     assert _init(lib, g, 3, 4, 1e-10, cfg)[0] == -1
     cfg = make_config()
     cfg.reserved0 = 1
