@@ -90,6 +90,9 @@ def roofline(stats, precision: str):
     n = {k: sum(s["kernel_launches"][k] for s in stats) for k in names}
     dom = max(names, key=lambda k: ms[k])
     t = ms[dom] / 1e3
+    if t <= 0 or n[dom] == 0:
+        return {"kernel": dom, "bound": "hbm", "achieved": 0.0, "peak": PEAK["hbm_GBps"], "unit": "GB/s",
+                "frac": 0.0, "traffic": None, "note": "no timed kernel launches", "breakdown": {}}
     peak_tf = PEAK["fp64_TF"] if precision == "fp64" else PEAK["fp32_TF"] if precision == "fp32" else PEAK["bf16_TF"]
     intensity = fl[dom] / by[dom] if by[dom] else float("inf")
     ridge = peak_tf * 1e12 / (PEAK["hbm_GBps"] * 1e9)
@@ -187,6 +190,8 @@ def main():
     ap.add_argument("--autotune", action="store_true",
                     help="pick the saturated block size and GEMM tiles by timing them at init (before timing)")
     ap.add_argument("--tune-cache", default=None, help="text cache of autotuner choices")
+    ap.add_argument("--method", default="orthonormalization", choices=["orthonormalization", "rank_svd"],
+                    help="rank_svd: the standard algorithm with an SVD rank test (comparison baseline)")
     ap.add_argument("--raw-basis", action="store_true",
                     help="Algorithm 3: also keep the raw basis B and bracket raw elements (single problems)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -210,7 +215,7 @@ def main():
         sys.exit(1)
     gens, tol, desc = workload(args.workload)
     cfg = dict(precision=args.precision, decide=args.decide, block=args.block, early_exit=args.early_exit,
-               autotune=args.autotune, tune_cache=args.tune_cache, raw_basis=args.raw_basis)
+               autotune=args.autotune, tune_cache=args.tune_cache, raw_basis=args.raw_basis, method=args.method)
     if args.raw_basis and args.workload == "batch64":
         raise SystemExit("--raw-basis is for single problems")
 
@@ -274,7 +279,8 @@ def main():
                    "block": stats0[0]["block"], "block_growth": stats0[0]["block_growth"],
                    "tile_dot": stats0[0]["tile_dot"], "tile_sub": stats0[0]["tile_sub"],
                    "autotuned": stats0[0]["autotuned"], "early_exit": bool(args.early_exit),
-                   "algorithm": "Algorithm 3 (raw basis kept)" if args.raw_basis else "Algorithm 4 (dimension only)",
+                   "algorithm": ("Algorithm 1, SVD rank test (baseline)" if args.method == "rank_svd" else
+                                 "Algorithm 3 (raw basis kept)" if args.raw_basis else "Algorithm 4 (dimension only)"),
                    "parallelism": "single GPU"},
         "roofline": roof,
         "cpu_baseline": cpu,

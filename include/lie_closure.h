@@ -59,6 +59,17 @@ typedef enum lie_precision {
     LIE_PREC_BF16X3 = 2   /* screen in split BF16 (hi*hi + hi*lo + lo*hi on MFMA, FP32 accumulate); FP64 verification */
 } lie_precision;
 
+/* Independence test.  ORTHONORMALIZATION is the paper's method (Algorithms 3 and 4: residual
+ * against an orthonormal basis).  RANK_SVD is the standard algorithm it is compared with
+ * (Algorithm 1 with the rank computed by an SVD, Section 3): a bracket of raw basis elements
+ * is kept iff the rank of [B; h] exceeds that of B, the rank being the number of singular
+ * values above max(d^2, |B|+1) * eps * sigma_max.  RANK_SVD keeps only the raw basis B
+ * (lie_closure_raw_basis); it runs in FP64, one problem at a time, for d <= 16. */
+typedef enum lie_method {
+    LIE_METHOD_ORTHONORMALIZATION = 0,
+    LIE_METHOD_RANK_SVD = 1
+} lie_method;
+
 /* How a screened candidate is decided (ignored for LIE_PREC_FP64). */
 typedef enum lie_decide {
     LIE_DECIDE_FP64 = 0,   /* every candidate is decided from its FP64 residual (screen used for nothing) */
@@ -91,7 +102,8 @@ typedef struct lie_closure_config {
                               brackets, unnormalised) and bracket raw elements [B_l, B_m] instead of
                               [V_l, V_m]; raw brackets are accepted iff their residual exceeds tol * ||h||
                               (single problems only; doubles the basis memory) */
-    int32_t reserved[1];   /* must be zero */
+    int32_t method;        /* lie_method: LIE_METHOD_ORTHONORMALIZATION (default) or the comparison
+                              baseline LIE_METHOD_RANK_SVD */
 } lie_closure_config;
 
 /* Kernel classes reported by the per-kernel counters of lie_closure_stats. */

@@ -25,7 +25,8 @@ __all__ = ["LieClosure", "BatchClosure", "closure", "LieError", "make_config"]
 def make_config(*, precision: str = "fp64", decide: str = "screen", block: int = 0, early_exit: bool = False,
                 tau_rej: float = 0.0, max_dim: int = 0, stream=None, device: int | None = None,
                 use_graphs: bool = True, profile: bool = False, autotune: bool = False,
-                tune_cache: str | None = None, raw_basis: bool = False) -> _lib.Config:
+                tune_cache: str | None = None, raw_basis: bool = False,
+                method: str = "orthonormalization") -> _lib.Config:
     cfg = _lib.Config()
     _lib.check(_lib.load().lie_closure_config_default(ctypes.byref(cfg)))
     cfg.precision = _lib.PRECISIONS[precision]
@@ -39,6 +40,7 @@ def make_config(*, precision: str = "fp64", decide: str = "screen", block: int =
     cfg.profile = 1 if profile else 0
     cfg.autotune = 1 if autotune else 0
     cfg.raw_basis = 1 if raw_basis else 0
+    cfg.method = {"orthonormalization": 0, "rank_svd": 1}[method]
     # the bytes object must outlive the init call that reads it; the Config keeps it
     cfg._tune_cache_bytes = None if tune_cache is None else os.fsencode(tune_cache)
     cfg.tune_cache = cfg._tune_cache_bytes

@@ -52,7 +52,7 @@ class Config(ctypes.Structure):
         ("reserved0", ctypes.c_int32),
         ("tune_cache", ctypes.c_char_p),
         ("raw_basis", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 1),
+        ("method", ctypes.c_int32),
     ]
 
 

@@ -177,6 +177,9 @@ struct lie_closure {
     float *Bs = nullptr;         // cap x D, their FP32 rounding (screened modes)
     double *Graw = nullptr;      // n_gen x D, packed generators as given
     int64_t *elem_src = nullptr; // cap: pair index of each element, or -(generator + 1)
+    // comparison baseline (config.method = LIE_METHOD_RANK_SVD): standard algorithm, SVD rank test
+    int method = LIE_METHOD_ORTHONORMALIZATION;
+    lie::RankTester *rank = nullptr;
     int *nsurv = nullptr;        // 1: survivor count
     lie::DevState *st = nullptr;
     double *scalar = nullptr;    // one double of device scratch
@@ -213,6 +216,7 @@ struct lie_closure {
             (void)hipStreamSynchronize(stream);
         if (graph.exec)
             (void)hipGraphExecDestroy(graph.exec);
+        lie::rank_tester_destroy(rank);
         for (void *p : {(void *)d_cursor, (void *)V64, (void *)Vs, (void *)H64, (void *)Hs, (void *)C, (void *)Cs,
                         (void *)part,
                         (void *)normpart_s, (void *)cand_a2, (void *)cand_n2, (void *)rho2, (void *)h2, (void *)h2b,
@@ -344,6 +348,27 @@ struct lie_closure {
     }
 
     // Generator phase: every generator in input order, FP64, relative threshold.
+    // Generator phase of the standard algorithm: each generator is kept iff it raises the
+    // rank of the raw basis.
+    lie_status generators_rank(const double *packed)
+    {
+        unsigned char flag = 0;
+        for (int g = 0; g < n_gen; ++g) {
+            const int64_t N = hs.N;
+            if (N >= D || N >= cap)
+                break;
+            HIP_TRY(lie::rank_tester_run(rank, B64, N, packed + (size_t)g * D, 1, &flag));
+            if (flag) {
+                HIP_TRY(hipMemcpyAsync(B64 + N * D, packed + (size_t)g * D, D * sizeof(double),
+                                       hipMemcpyDeviceToDevice, stream));
+                hs.N = N + 1;
+                hs.n_gen_acc++;
+            }
+        }
+        HIP_TRY(hipStreamSynchronize(stream));
+        return LIE_OK;
+    }
+
     lie_status generators(const double *gens_host)
     {
         double *staging = nullptr;
@@ -359,6 +384,8 @@ struct lie_closure {
         Guard guard2{raw ? nullptr : packed};
         HIP_TRY(hipMemcpyAsync(staging, gens_host, bytes, hipMemcpyHostToDevice, stream));
         HIP_TRY(lie::launch_pack_c128(staging, packed, n_gen, d, stream));
+        if (method == LIE_METHOD_RANK_SVD)
+            return generators_rank(packed);
         lie_status s;
         for (int g = 0; g < n_gen; ++g) {
             HIP_TRY(hipMemcpyAsync(H64, packed + (size_t)g * D, D * sizeof(double), hipMemcpyDeviceToDevice, stream));
@@ -510,8 +537,93 @@ struct lie_closure {
         return LIE_OK;
     }
 
+    // Standard algorithm (Algorithm 1) with the SVD rank test, host-driven: each batch of
+    // brackets [B_l, B_m] (pair order of the paper) is tested against the raw basis B; the
+    // first candidate that raises the rank is appended and the candidates before it are
+    // final (dependent on B, hence on every superset).  Batches grow while nothing is
+    // accepted and restart at one candidate after an acceptance.
+    lie_status run_rank(int64_t budget)
+    {
+        const auto t0 = std::chrono::steady_clock::now();
+        constexpr int kRankBatch = 64;
+        int64_t spent = 0;
+        int cnt = 1;
+        unsigned char flags[kRankBatch];
+        lie_status s = LIE_OK;
+        for (;;) {
+            const int64_t N = hs.N;
+            const int64_t avail = lie::pairs_below(N);
+            if ((cfg.early_exit && N >= ambient) || cursor >= avail) {
+                done = true;
+                break;
+            }
+            if (budget >= 0 && spent >= budget) {
+                s = LIE_INCOMPLETE;
+                break;
+            }
+            const int c = (int)std::min<int64_t>(cnt, avail - cursor);
+            int j = -1;
+            if (N < D) {
+                const double dd = d, cc = c, n1 = (double)N + 1.0, Dd = (double)D;
+                timer.begin(stream);
+                hipError_t e = lie::launch_comm_f64(B64, d, cursor, nullptr, nullptr, c, st, H64, stream);
+                timer.end(LIE_K_COMM, stream, 8.0 * dd * dd * dd * cc, 3.0 * cc * Dd * sizeof(double));
+                // singular values of c matrices D x (N+1): bidiagonalisation 4 m n^2 - 4 n^3 / 3 flops each
+                timer.begin(stream);
+                if (e == hipSuccess)
+                    e = lie::rank_tester_run(rank, B64, N, H64, c, flags);
+                timer.end(LIE_K_OTHER, stream, cc * (4.0 * Dd * n1 * n1 - 4.0 * n1 * n1 * n1 / 3.0),
+                          cc * n1 * Dd * sizeof(double) * 2.0);
+                if (e != hipSuccess) {
+                    s = fail(LIE_ERR_DEVICE, "rank test failed: %s", hipGetErrorString(e));
+                    failed = true;
+                    break;
+                }
+                for (int q = 0; q < c && j < 0; ++q)
+                    if (flags[q])
+                        j = q;
+            }
+            const int processed = j >= 0 ? j + 1 : c;
+            if (j >= 0) {
+                if (N >= cap) {
+                    hs.full = 1;
+                    s = fail(LIE_ERR_CAPACITY, "basis capacity %lld reached", (long long)cap);
+                    failed = true;
+                    break;
+                }
+                const hipError_t e = hipMemcpyAsync(B64 + N * D, H64 + (int64_t)j * D, D * sizeof(double),
+                                                    hipMemcpyDeviceToDevice, stream);
+                if (e != hipSuccess) {
+                    s = fail(LIE_ERR_DEVICE, "append failed: %s", hipGetErrorString(e));
+                    failed = true;
+                    break;
+                }
+                hs.N = N + 1;
+                hs.n_acc++;
+                cnt = 1;
+            } else {
+                cnt = std::min(2 * cnt, kRankBatch);
+            }
+            hs.n_cand += processed;
+            hs.n_fp64 += processed;
+            cursor += processed;
+            spent += processed;
+            ++blocks;
+        }
+        run_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        return s;
+    }
+
     lie_status run(int64_t budget)
     {
+        if (method == LIE_METHOD_RANK_SVD) {
+            if (failed)
+                return fail(LIE_ERR_STATE, "a previous run of this handle failed");
+            if (done)
+                return LIE_OK;
+            HIP_TRY(hipSetDevice(device));
+            return run_rank(budget);
+        }
         if (failed)
             return fail(LIE_ERR_STATE, "a previous run of this handle failed");
         if (done)
@@ -654,13 +766,14 @@ lie_status resolve_config(const lie_closure_config *in, lie_closure_config *out)
         return fail(LIE_ERR_ARG, "max_dim must be >= 0");
     if (out->tau_rej < 0 || !std::isfinite(out->tau_rej))
         return fail(LIE_ERR_ARG, "tau_rej must be finite and >= 0");
-    for (int r : out->reserved)
-        if (r != 0)
-            return fail(LIE_ERR_ARG, "config.reserved must be zero");
     if (out->reserved0 != 0)
         return fail(LIE_ERR_ARG, "config.reserved0 must be zero");
     if (out->raw_basis != 0 && out->raw_basis != 1)
         return fail(LIE_ERR_ARG, "config.raw_basis must be 0 or 1");
+    if (out->method != LIE_METHOD_ORTHONORMALIZATION && out->method != LIE_METHOD_RANK_SVD)
+        return fail(LIE_ERR_ARG, "unknown method %d", out->method);
+    if (out->method == LIE_METHOD_RANK_SVD && out->precision != LIE_PREC_FP64)
+        return fail(LIE_ERR_ARG, "the rank-test method runs in FP64 only");
     if (out->autotune != 0 && out->autotune != 1)
         return fail(LIE_ERR_ARG, "config.autotune must be 0 or 1");
     out->tune_cache = nullptr;  // read at init only (see lie_closure_init), never kept
@@ -702,6 +815,11 @@ lie_status lie_closure_init(lie_closure **out, const double *generators, int32_t
     lie_closure_config cfg;
     if ((s = resolve_config(cfg_in, &cfg)) != LIE_OK)
         return s;
+    if (cfg.method == LIE_METHOD_RANK_SVD) {
+        if (d > 16)
+            return fail(LIE_ERR_ARG, "the rank-test method is limited to d <= 16 (got %d)", d);
+        cfg.block = 0;  // its batches are sized by the host loop
+    }
 
     lie_closure *h = new (std::nothrow) lie_closure();
     if (!h)
@@ -742,7 +860,8 @@ lie_status lie_closure_init(lie_closure **out, const double *generators, int32_t
             break;
         }
     }
-    h->raw = cfg.raw_basis != 0;
+    h->method = cfg.method;
+    h->raw = cfg.raw_basis != 0 || cfg.method == LIE_METHOD_RANK_SVD;  // the rank method keeps B only
     if (h->raw) {
         // Algorithm 3: raw brackets have no fixed scale, so every threshold is relative to ||h||
         if (h->policy == lie::POL_ABS)
@@ -838,6 +957,11 @@ lie_status lie_closure_init(lie_closure **out, const double *generators, int32_t
             (s = alloc(&h->normpart_s, (size_t)bmax * lie::gemm_sub_tiles_f32(D, 1) * 2)) != LIE_OK)
             return bail(s);
     }
+    if (h->method == LIE_METHOD_RANK_SVD) {
+        const hipError_t e = lie::rank_tester_create(&h->rank, D, 64, h->stream);
+        if (e != hipSuccess)
+            return bail(fail(LIE_ERR_DEVICE, "rank tester setup failed: %s", hipGetErrorString(e)));
+    }
     h->hs = lie::DevState{};
     h->hs.min_acc = INFINITY;
     h->hs.scr_min_indep = INFINITY;
@@ -880,6 +1004,8 @@ static lie_status basis_common(const lie_closure *h, void *dst, int64_t capacity
 {
     if (!h || !written || (!dst && capacity > 0))
         return fail(LIE_ERR_ARG, "NULL argument");
+    if (h->method == LIE_METHOD_RANK_SVD)
+        return fail(LIE_ERR_STATE, "the rank-test method keeps only the raw basis (lie_closure_raw_basis)");
     const int64_t n = h->hs.N;
     *written = n;
     if (capacity < n)
@@ -947,6 +1073,8 @@ lie_status lie_closure_orthogonality(lie_closure *h, double *loss)
 {
     if (!h || !loss)
         return fail(LIE_ERR_ARG, "NULL argument");
+    if (h->method == LIE_METHOD_RANK_SVD)
+        return fail(LIE_ERR_STATE, "the rank-test method keeps no orthonormal basis");
     const int64_t n = h->hs.N;
     HIP_TRY(hipSetDevice(h->device));
     double *work = nullptr;

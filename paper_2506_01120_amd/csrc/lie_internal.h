@@ -289,6 +289,17 @@ hipError_t launch_classify(const double *a2, const double *n2, int cnt, int64_t 
                            const DevState *st, int *rows, int64_t *pairs, int *slot, int *nsurv, hipStream_t s,
                            const int64_t *dp0 = nullptr);
 
+// ------------------------------------------------------------- rank-test baseline (rank_svd.hip)
+// Standard algorithm (Algorithm 1): a candidate raises the rank of the raw basis iff the
+// smallest singular value of [B_0 .. B_{N-1}, h] (packed rows) exceeds
+// max(D, N+1) * eps * sigma_max.  Batched SVD of up to max_batch such matrices (N + 1 <= D).
+struct RankTester;
+hipError_t rank_tester_create(RankTester **out, int64_t D, int max_batch, hipStream_t s);
+void rank_tester_destroy(RankTester *t);
+// flags[c] (host) = 1 iff candidate row c of H (device, cnt x D) is independent of B (device, N x D).
+// Synchronises the tester's stream.
+hipError_t rank_tester_run(RankTester *t, const double *B, int64_t N, const double *H, int cnt, unsigned char *flags);
+
 // ------------------------------------------------------------- autotuner (autotune.hip)
 struct TuneChoice {
     int block_sat;            // saturated-phase block size

@@ -118,7 +118,10 @@ def test_config_validation(lib):
         setattr(cfg, field, bad)
         assert _init(lib, g, 3, 4, 1e-10, cfg)[0] == -1, field
     cfg = make_config()
-    cfg.reserved[0] = 1
+    cfg.method = 5
+    assert _init(lib, g, 3, 4, 1e-10, cfg)[0] == -1
+    cfg = make_config(precision="fp32")
+    cfg.method = 1  # the rank-test baseline runs in FP64 only
     assert _init(lib, g, 3, 4, 1e-10, cfg)[0] == -1
     cfg = make_config()
     cfg.raw_basis = 3
