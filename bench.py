@@ -190,8 +190,10 @@ def main():
     ap.add_argument("--autotune", action="store_true",
                     help="pick the saturated block size and GEMM tiles by timing them at init (before timing)")
     ap.add_argument("--tune-cache", default=None, help="text cache of autotuner choices")
-    ap.add_argument("--method", default="orthonormalization", choices=["orthonormalization", "rank_svd"],
-                    help="rank_svd: the standard algorithm with an SVD rank test (comparison baseline)")
+    ap.add_argument("--method", default="orthonormalization",
+                    choices=["orthonormalization", "rank_svd", "matrix_inversion"],
+                    help="rank_svd: the standard algorithm with an SVD rank test (comparison baseline); "
+                         "matrix_inversion: the paper's Algorithm 2")
     ap.add_argument("--raw-basis", action="store_true",
                     help="Algorithm 3: also keep the raw basis B and bracket raw elements (single problems)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -280,6 +282,7 @@ def main():
                    "tile_dot": stats0[0]["tile_dot"], "tile_sub": stats0[0]["tile_sub"],
                    "autotuned": stats0[0]["autotuned"], "early_exit": bool(args.early_exit),
                    "algorithm": ("Algorithm 1, SVD rank test (baseline)" if args.method == "rank_svd" else
+                                 "Algorithm 2, matrix inversion" if args.method == "matrix_inversion" else
                                  "Algorithm 3 (raw basis kept)" if args.raw_basis else "Algorithm 4 (dimension only)"),
                    "parallelism": "single GPU"},
         "roofline": roof,

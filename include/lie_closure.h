@@ -64,10 +64,15 @@ typedef enum lie_precision {
  * (Algorithm 1 with the rank computed by an SVD, Section 3): a bracket of raw basis elements
  * is kept iff the rank of [B; h] exceeds that of B, the rank being the number of singular
  * values above max(d^2, |B|+1) * eps * sigma_max.  RANK_SVD keeps only the raw basis B
- * (lie_closure_raw_basis); it runs in FP64, one problem at a time, for d <= 16. */
+ * (lie_closure_raw_basis); it runs in FP64, one problem at a time, for d <= 16.
+ * MATRIX_INVERSION is the paper's other method (Algorithm 2, Section 3.1): unit-norm raw elements
+ * B, the inverse of their Gram matrix A, and the explicit residual h - B A^{-1} beta of a unit-norm
+ * candidate (beta_k = <B_k, h>), kept iff its norm exceeds tol; A^{-1} is recomputed after each
+ * block that appended elements.  FP64, single problems, raw basis only (unit-norm elements). */
 typedef enum lie_method {
     LIE_METHOD_ORTHONORMALIZATION = 0,
-    LIE_METHOD_RANK_SVD = 1
+    LIE_METHOD_RANK_SVD = 1,
+    LIE_METHOD_MATRIX_INVERSION = 2
 } lie_method;
 
 /* How a screened candidate is decided (ignored for LIE_PREC_FP64). */

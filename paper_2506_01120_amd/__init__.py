@@ -40,7 +40,7 @@ def make_config(*, precision: str = "fp64", decide: str = "screen", block: int =
     cfg.profile = 1 if profile else 0
     cfg.autotune = 1 if autotune else 0
     cfg.raw_basis = 1 if raw_basis else 0
-    cfg.method = {"orthonormalization": 0, "rank_svd": 1}[method]
+    cfg.method = {"orthonormalization": 0, "rank_svd": 1, "matrix_inversion": 2}[method]
     # the bytes object must outlive the init call that reads it; the Config keeps it
     cfg._tune_cache_bytes = None if tune_cache is None else os.fsencode(tune_cache)
     cfg.tune_cache = cfg._tune_cache_bytes

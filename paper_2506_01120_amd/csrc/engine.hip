@@ -180,6 +180,10 @@ struct lie_closure {
     // comparison baseline (config.method = LIE_METHOD_RANK_SVD): standard algorithm, SVD rank test
     int method = LIE_METHOD_ORTHONORMALIZATION;
     lie::RankTester *rank = nullptr;
+    // matrix-inversion method (config.method = LIE_METHOD_MATRIX_INVERSION)
+    bool inv = false;
+    lie::GramInverse *ginv = nullptr;
+    double *Xc = nullptr;        // block x cap: x = A^{-1} beta of every candidate
     int *nsurv = nullptr;        // 1: survivor count
     lie::DevState *st = nullptr;
     double *scalar = nullptr;    // one double of device scratch
@@ -217,6 +221,9 @@ struct lie_closure {
         if (graph.exec)
             (void)hipGraphExecDestroy(graph.exec);
         lie::rank_tester_destroy(rank);
+        lie::gram_inverse_destroy(ginv);
+        if (Xc)
+            (void)hipFree(Xc);
         for (void *p : {(void *)d_cursor, (void *)V64, (void *)Vs, (void *)H64, (void *)Hs, (void *)C, (void *)Cs,
                         (void *)part,
                         (void *)normpart_s, (void *)cand_a2, (void *)cand_n2, (void *)rho2, (void *)h2, (void *)h2b,
@@ -325,7 +332,7 @@ struct lie_closure {
         a.src0 = src0;
         a.rel = raw && mode == 1 ? 1 : 0;
         a.h2 = h2_surv;
-        a.rho2 = rho2;
+        a.rho2 = inv ? nullptr : rho2;  // the matrix-inversion step has no second projection pass
         a.cnt = cnt;
         a.D = D;
         a.cap = cap;
@@ -341,7 +348,7 @@ struct lie_closure {
         if (raw) {
             // Algorithm 3: the raw rows of this launch's appends (brackets of raw rows)
             timer.begin(stream);
-            HIP_TRY(lie::launch_raw_append(Graw, B64, Bs, d, elem_src, st, cnt, stream));
+            HIP_TRY(lie::launch_raw_append(Graw, B64, Bs, d, elem_src, st, cnt, stream, inv));
             timer.end(LIE_K_OTHER, stream, 0, 0);
         }
         return LIE_OK;
@@ -387,6 +394,20 @@ struct lie_closure {
         if (method == LIE_METHOD_RANK_SVD)
             return generators_rank(packed);
         lie_status s;
+        if (inv) {
+            // Algorithm 2's generator phase: each generator against B through A^{-1}, unit-normalised
+            for (int g = 0; g < n_gen; ++g) {
+                HIP_TRY(hipMemcpyAsync(H64, packed + (size_t)g * D, D * sizeof(double), hipMemcpyDeviceToDevice,
+                                       stream));
+                const int64_t N = hs.N;
+                if ((s = step_inv(1, true, -(int64_t)g - 1)) != LIE_OK || (s = sync_state()) != LIE_OK ||
+                    (s = check_state()) != LIE_OK)
+                    return s;
+                if (hs.N > N && (s = refresh_inverse()) != LIE_OK)
+                    return s;
+            }
+            return LIE_OK;
+        }
         for (int g = 0; g < n_gen; ++g) {
             HIP_TRY(hipMemcpyAsync(H64, packed + (size_t)g * D, D * sizeof(double), hipMemcpyDeviceToDevice, stream));
             if ((s = project(nullptr, nullptr, cand_a2, cand_n2, 1, g, g, LIE_K_OTHER, LIE_K_OTHER, LIE_K_OTHER)) !=
@@ -614,8 +635,101 @@ struct lie_closure {
         return s;
     }
 
+    // Matrix-inversion method (Algorithm 2): one block of candidates (brackets of unit-norm raw
+    // rows, or one generator) tested against the raw basis B through x = A^{-1} beta and the
+    // explicit residual h - B x (relative to ||h||, i.e. absolute for the unit-norm candidate);
+    // survivors are then decided in candidate order against the elements appended earlier in
+    // the block, and the new raw rows are appended unit-normalised.  N = hs.N is current.
+    lie_status step_inv(int cnt, bool generator, int64_t src0)
+    {
+        const int64_t N = hs.N;
+        const int64_t ldc = lie::coef_ld(cap);
+        const double c = cnt, Dd = (double)D, Nd = (double)N, dd = d, w = sizeof(double);
+        if (!generator) {
+            timer.begin(stream);
+            HIP_TRY(lie::launch_comm_f64(B64, d, cursor, nullptr, nullptr, cnt, st, H64, stream));
+            timer.end(LIE_K_COMM, stream, 8.0 * dd * dd * dd * c, 3.0 * c * Dd * w);
+        }
+        timer.begin(stream);
+        HIP_TRY(lie::launch_gemm_dot_f64(B64, st, H64, nullptr, nullptr, cnt, D, std::max<int64_t>(N, 1), ldc, C,
+                                         stream));
+        HIP_TRY(lie::gram_inverse_apply(ginv, C, ldc, N, cnt, Xc, ldc));
+        timer.end(LIE_K_DOT, stream, 2.0 * Nd * Dd * c + 2.0 * Nd * Nd * c, (Nd * Dd + c * Dd + Nd * Nd + 2 * c * Nd) * w);
+        timer.begin(stream);
+        HIP_TRY(lie::launch_gemm_sub_f64(B64, st, H64, nullptr, nullptr, Xc, std::max<int64_t>(N, 1), ldc, cnt, D, part,
+                                         stream));
+        timer.end(LIE_K_SUB, stream, 2.0 * Nd * Dd * c, (Nd * Dd + c * Nd + 2.0 * c * Dd) * w);
+        timer.begin(stream);
+        HIP_TRY(lie::launch_norm_final(part, nullptr, cnt, lie::gemm_sub_tiles_f64(D), st, cand_a2, cand_n2, stream));
+        timer.end(LIE_K_REDUCE, stream, 0, 0);
+        lie_status s;
+        if ((s = classify(cnt, generator ? 0 : cursor, lie::POL_REL, tol)) != LIE_OK)
+            return s;
+        return accept(cnt, generator ? 0 : 1, false, surv_rows, nullptr, LIE_K_ACCEPT, src0);
+    }
+
+    // A^{-1} after appends; a failed Cholesky factorisation of A is the method's numerical failure.
+    lie_status refresh_inverse()
+    {
+        int info = 0;
+        const hipError_t e = lie::gram_inverse_update(ginv, B64, hs.N, &info);
+        if (e != hipSuccess)
+            return fail(LIE_ERR_DEVICE, "inverse Gram update failed: %s", hipGetErrorString(e));
+        if (info != 0)
+            return fail(LIE_ERR_NUMERIC, "Gram matrix of %lld elements is not numerically positive definite "
+                                         "(minor %d); the matrix-inversion method lost accuracy",
+                        (long long)hs.N, info);
+        return LIE_OK;
+    }
+
+    lie_status run_inv(int64_t budget)
+    {
+        const auto t0 = std::chrono::steady_clock::now();
+        int64_t spent = 0;
+        int cur = block_growth;
+        lie_status s = LIE_OK;
+        for (;;) {
+            const int64_t N = hs.N;
+            const int64_t avail = lie::pairs_below(N);
+            if ((cfg.early_exit && N >= ambient) || cursor >= avail) {
+                done = true;
+                break;
+            }
+            if (budget >= 0 && spent >= budget) {
+                s = LIE_INCOMPLETE;
+                break;
+            }
+            const int cnt = (int)std::min<int64_t>(cur, avail - cursor);
+            if ((s = step_inv(cnt, false, 0)) != LIE_OK || (s = sync_state()) != LIE_OK ||
+                (s = check_state()) != LIE_OK)
+                break;
+            if (hs.N > N) {
+                if ((s = refresh_inverse()) != LIE_OK)
+                    break;
+                cur = block_growth;
+            } else {
+                cur = block_sat;
+            }
+            cursor += cnt;
+            spent += cnt;
+            ++blocks;
+        }
+        if (s < 0)
+            failed = true;
+        run_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        return s;
+    }
+
     lie_status run(int64_t budget)
     {
+        if (method == LIE_METHOD_MATRIX_INVERSION) {
+            if (failed)
+                return fail(LIE_ERR_STATE, "a previous run of this handle failed");
+            if (done)
+                return LIE_OK;
+            HIP_TRY(hipSetDevice(device));
+            return run_inv(budget);
+        }
         if (method == LIE_METHOD_RANK_SVD) {
             if (failed)
                 return fail(LIE_ERR_STATE, "a previous run of this handle failed");
@@ -770,10 +884,11 @@ lie_status resolve_config(const lie_closure_config *in, lie_closure_config *out)
         return fail(LIE_ERR_ARG, "config.reserved0 must be zero");
     if (out->raw_basis != 0 && out->raw_basis != 1)
         return fail(LIE_ERR_ARG, "config.raw_basis must be 0 or 1");
-    if (out->method != LIE_METHOD_ORTHONORMALIZATION && out->method != LIE_METHOD_RANK_SVD)
+    if (out->method != LIE_METHOD_ORTHONORMALIZATION && out->method != LIE_METHOD_RANK_SVD &&
+        out->method != LIE_METHOD_MATRIX_INVERSION)
         return fail(LIE_ERR_ARG, "unknown method %d", out->method);
-    if (out->method == LIE_METHOD_RANK_SVD && out->precision != LIE_PREC_FP64)
-        return fail(LIE_ERR_ARG, "the rank-test method runs in FP64 only");
+    if (out->method != LIE_METHOD_ORTHONORMALIZATION && out->precision != LIE_PREC_FP64)
+        return fail(LIE_ERR_ARG, "the rank-test and matrix-inversion methods run in FP64 only");
     if (out->autotune != 0 && out->autotune != 1)
         return fail(LIE_ERR_ARG, "config.autotune must be 0 or 1");
     out->tune_cache = nullptr;  // read at init only (see lie_closure_init), never kept
@@ -861,7 +976,8 @@ lie_status lie_closure_init(lie_closure **out, const double *generators, int32_t
         }
     }
     h->method = cfg.method;
-    h->raw = cfg.raw_basis != 0 || cfg.method == LIE_METHOD_RANK_SVD;  // the rank method keeps B only
+    h->inv = cfg.method == LIE_METHOD_MATRIX_INVERSION;
+    h->raw = cfg.raw_basis != 0 || cfg.method != LIE_METHOD_ORTHONORMALIZATION;  // the other methods keep B
     if (h->raw) {
         // Algorithm 3: raw brackets have no fixed scale, so every threshold is relative to ||h||
         if (h->policy == lie::POL_ABS)
@@ -962,6 +1078,13 @@ lie_status lie_closure_init(lie_closure **out, const double *generators, int32_t
         if (e != hipSuccess)
             return bail(fail(LIE_ERR_DEVICE, "rank tester setup failed: %s", hipGetErrorString(e)));
     }
+    if (h->inv) {
+        if ((s = alloc(&h->Xc, (size_t)bmax * capr)) != LIE_OK)
+            return bail(s);
+        const hipError_t e = lie::gram_inverse_create(&h->ginv, h->cap, D, h->stream);
+        if (e != hipSuccess)
+            return bail(fail(LIE_ERR_DEVICE, "inverse Gram setup failed: %s", hipGetErrorString(e)));
+    }
     h->hs = lie::DevState{};
     h->hs.min_acc = INFINITY;
     h->hs.scr_min_indep = INFINITY;
@@ -1004,8 +1127,8 @@ static lie_status basis_common(const lie_closure *h, void *dst, int64_t capacity
 {
     if (!h || !written || (!dst && capacity > 0))
         return fail(LIE_ERR_ARG, "NULL argument");
-    if (h->method == LIE_METHOD_RANK_SVD)
-        return fail(LIE_ERR_STATE, "the rank-test method keeps only the raw basis (lie_closure_raw_basis)");
+    if (h->method != LIE_METHOD_ORTHONORMALIZATION)
+        return fail(LIE_ERR_STATE, "this method keeps only the raw basis (lie_closure_raw_basis)");
     const int64_t n = h->hs.N;
     *written = n;
     if (capacity < n)
@@ -1073,8 +1196,8 @@ lie_status lie_closure_orthogonality(lie_closure *h, double *loss)
 {
     if (!h || !loss)
         return fail(LIE_ERR_ARG, "NULL argument");
-    if (h->method == LIE_METHOD_RANK_SVD)
-        return fail(LIE_ERR_STATE, "the rank-test method keeps no orthonormal basis");
+    if (h->method != LIE_METHOD_ORTHONORMALIZATION)
+        return fail(LIE_ERR_STATE, "this method keeps no orthonormal basis");
     const int64_t n = h->hs.N;
     HIP_TRY(hipSetDevice(h->device));
     double *work = nullptr;
@@ -1703,8 +1826,8 @@ lie_status lie_closure_batch_init(lie_closure_batch **out, int32_t n_problems, c
     lie_status s = resolve_config(cfg_in, &cfg);
     if (s != LIE_OK)
         return s;
-    if (cfg.raw_basis)
-        return fail(LIE_ERR_ARG, "config.raw_basis (Algorithm 3) is supported for single problems only");
+    if (cfg.raw_basis || cfg.method != LIE_METHOD_ORTHONORMALIZATION)
+        return fail(LIE_ERR_ARG, "config.raw_basis and the comparison methods are supported for single problems only");
     // validate every problem before any device work
     for (int32_t i = 0; i < n_problems; ++i) {
         int64_t amb = 0;

@@ -231,8 +231,10 @@ __global__ void __launch_bounds__(kThreads) k_comm_f64_lds_b(Batch b)
 // Element e in [st->raw_lo, st->N) came from generator -(src+1) (its packed copy is
 // G's row) or from the bracket of raw rows l, m < raw_lo of its source pair.
 __global__ void __launch_bounds__(kThreads) k_raw_append(const double *G, double *B, float *Bs, int d,
-                                                         const int64_t *elem_src, const DevState *st, int use_lds)
+                                                         const int64_t *elem_src, const DevState *st, int use_lds,
+                                                         int normalize)
 {
+    __shared__ double red[kThreads / 64];
     const int64_t lo = st->raw_lo, hi = st->N;
     const int64_t D = (int64_t)d * d;
     for (int64_t e = lo + blockIdx.x; e < hi; e += gridDim.x) {
@@ -251,6 +253,25 @@ __global__ void __launch_bounds__(kThreads) k_raw_append(const double *G, double
                     comm_f64_global_body(A, bx, 0);
         }
         __syncthreads();  // row e is complete
+        if (normalize) {
+            // unit norm (the matrix-inversion method keeps unit-norm raw elements)
+            double loc = 0.0;
+            for (int64_t j = threadIdx.x; j < D; j += blockDim.x)
+                loc += out[j] * out[j];
+            for (int off = 32; off > 0; off >>= 1)
+                loc += __shfl_down(loc, off, 64);
+            if ((threadIdx.x & 63) == 0)
+                red[threadIdx.x >> 6] = loc;
+            __syncthreads();
+            double t = 0.0;
+            for (int q = 0; q < (int)(blockDim.x >> 6); ++q)
+                t += red[q];
+            const double inv = t > 0.0 ? 1.0 / sqrt(t) : 0.0;
+            __syncthreads();  // red is reused by the next element
+            for (int64_t j = threadIdx.x; j < D; j += blockDim.x)
+                out[j] *= inv;
+            __syncthreads();
+        }
         if (Bs)
             for (int64_t j = threadIdx.x; j < D; j += blockDim.x)
                 Bs[e * D + j] = (float)out[j];
@@ -1458,7 +1479,7 @@ hipError_t launch_unpack_c128(const double *src, double *dst, int64_t count, int
 }
 
 hipError_t launch_raw_append(const double *G, double *B, float *Bs, int d, const int64_t *elem_src, const DevState *st,
-                             int max_new, hipStream_t s)
+                             int max_new, hipStream_t s, bool normalize)
 {
     if (max_new <= 0)
         return hipSuccess;
@@ -1475,7 +1496,7 @@ hipError_t launch_raw_append(const double *G, double *B, float *Bs, int d, const
     use_lds = use_lds && lds <= granted;
     const int grid = std::min(max_new, 1024);
     hipLaunchKernelGGL(k_raw_append, dim3(grid), dim3(kThreads), use_lds ? lds : 0, s, G, B, Bs, d, elem_src, st,
-                       use_lds ? 1 : 0);
+                       use_lds ? 1 : 0, normalize ? 1 : 0);
     return hipGetLastError();
 }
 

@@ -221,7 +221,7 @@ int accept_max_block(int64_t D);
 // (e in [st->raw_lo, st->N)): the packed generator G[g] for a source -(g+1), else the
 // packed bracket [B_l, B_m] of the source pair; Bs (if non-null) gets the FP32 rounding.
 hipError_t launch_raw_append(const double *G, double *B, float *Bs, int d, const int64_t *elem_src, const DevState *st,
-                             int max_new, hipStream_t s);
+                             int max_new, hipStream_t s, bool normalize = false);
 
 // G = V V^T (n x n) then ||G - I||_F into *out (device), using `work` of n*n + 256 doubles.
 hipError_t launch_orth_loss(const double *V, int64_t n, int64_t D, double *work, double *out, hipStream_t s);
@@ -299,6 +299,18 @@ void rank_tester_destroy(RankTester *t);
 // flags[c] (host) = 1 iff candidate row c of H (device, cnt x D) is independent of B (device, N x D).
 // Synchronises the tester's stream.
 hipError_t rank_tester_run(RankTester *t, const double *B, int64_t N, const double *H, int cnt, unsigned char *flags);
+
+// ------------------------------------------------------------- matrix-inversion method (inverse_gram.hip)
+// A^{-1} for the Gram matrix A = B B^T of the first N unit-norm raw rows (Algorithm 2).
+struct GramInverse;
+hipError_t gram_inverse_create(GramInverse **out, int64_t cap, int64_t D, hipStream_t s);
+void gram_inverse_destroy(GramInverse *g);
+// Recompute A^{-1} (N x N) from B (device, row stride D); *info_host != 0 when the Cholesky
+// factorisation of A failed (A not numerically positive definite).  Synchronises the stream.
+hipError_t gram_inverse_update(GramInverse *g, const double *B, int64_t N, int *info_host);
+// X (cnt x N, row stride ldx) = beta (cnt x N, row stride ldb) A^{-1}.
+hipError_t gram_inverse_apply(GramInverse *g, const double *beta, int64_t ldb, int64_t N, int cnt, double *X,
+                              int64_t ldx);
 
 // ------------------------------------------------------------- autotuner (autotune.hip)
 struct TuneChoice {
