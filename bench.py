@@ -198,6 +198,7 @@ def main():
                     help="Algorithm 3: also keep the raw basis B and bracket raw elements (single problems)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="skip the one-candidate-at-a-time FP64 comparison run")
+    ap.add_argument("--tol", type=float, default=0.0, help="override the workload's tolerance")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a device copy of MIB MiB (counter calibration) and exit")
     args = ap.parse_args()
@@ -216,6 +217,11 @@ def main():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
     gens, tol, desc = workload(args.workload)
+    if args.tol > 0:
+        tol = args.tol
+        if isinstance(gens, list):
+            for p in gens:
+                p.tol = tol
     cfg = dict(precision=args.precision, decide=args.decide, block=args.block, early_exit=args.early_exit,
                autotune=args.autotune, tune_cache=args.tune_cache, raw_basis=args.raw_basis, method=args.method)
     if args.raw_basis and args.workload == "batch64":
