@@ -44,6 +44,10 @@ def workload(name: str):
         return W.ising(3), 1e-10, "open transverse-field Ising chain n=3 d=8 -> so(6)"
     if name == "su32":
         return W.rand_pair(32, seed=3), 1e-8, "random traceless anti-Hermitian pair d=32 seed 3 -> su(32)"
+    if name == "ising7":
+        return W.ising(7), 1e-10, "open transverse-field Ising chain n=7 d=128 -> so(14)"
+    if name == "sums5":
+        return W.pauli_sums(5, 2, 3, 5), 1e-10, "two random 3-term Pauli sums on 5 qubits (seed 5), d=32"
     if name == "su64":
         return W.rand_pair(64, seed=5), 1e-8, "random traceless anti-Hermitian pair d=64 seed 5 -> su(64)"
     raise SystemExit(f"unknown workload {name}")
@@ -194,6 +198,8 @@ def main():
                     choices=["orthonormalization", "rank_svd", "matrix_inversion"],
                     help="rank_svd: the standard algorithm with an SVD rank test (comparison baseline); "
                          "matrix_inversion: the paper's Algorithm 2")
+    ap.add_argument("--representation", default="dense", choices=["dense", "pauli"],
+                    help="pauli: the sparse Pauli-sum representation (d = 2^n, FP64)")
     ap.add_argument("--raw-basis", action="store_true",
                     help="Algorithm 3: also keep the raw basis B and bracket raw elements (single problems)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -223,7 +229,8 @@ def main():
             for p in gens:
                 p.tol = tol
     cfg = dict(precision=args.precision, decide=args.decide, block=args.block, early_exit=args.early_exit,
-               autotune=args.autotune, tune_cache=args.tune_cache, raw_basis=args.raw_basis, method=args.method)
+               autotune=args.autotune, tune_cache=args.tune_cache, raw_basis=args.raw_basis, method=args.method,
+               representation=args.representation)
     if args.raw_basis and args.workload == "batch64":
         raise SystemExit("--raw-basis is for single problems")
 
@@ -244,7 +251,7 @@ def main():
 
     plain = None
     if not args.no_plain:
-        plain_cfg = dict(cfg, precision="fp64", block=1, autotune=False)
+        plain_cfg = dict(cfg, precision="fp64", block=1, autotune=False, representation="dense")
         if isinstance(gens, list):
             # the batched workload's denominator: every problem on its own, one candidate at a time
             print("[bench] plain one-at-a-time FP64 comparison: each problem alone", file=sys.stderr, flush=True)
@@ -287,6 +294,7 @@ def main():
                    "block": stats0[0]["block"], "block_growth": stats0[0]["block_growth"],
                    "tile_dot": stats0[0]["tile_dot"], "tile_sub": stats0[0]["tile_sub"],
                    "autotuned": stats0[0]["autotuned"], "early_exit": bool(args.early_exit),
+                   "representation": args.representation,
                    "algorithm": ("Algorithm 1, SVD rank test (baseline)" if args.method == "rank_svd" else
                                  "Algorithm 2, matrix inversion" if args.method == "matrix_inversion" else
                                  "Algorithm 3 (raw basis kept)" if args.raw_basis else "Algorithm 4 (dimension only)"),

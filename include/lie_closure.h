@@ -75,6 +75,18 @@ typedef enum lie_method {
     LIE_METHOD_MATRIX_INVERSION = 2
 } lie_method;
 
+/* Operator representation on the device.  DENSE: packed d x d matrices, brackets by one complex
+ * matrix product (8 d^3 flops).  PAULI (the sparse Pauli-sum representation, Sections 3 and 4.2;
+ * d = 2^n, n <= 7): real coordinates over the 4^n strings iP_s, which are orthonormal in the paper's
+ * inner product, brackets by the symplectic product rule over the support of the sparser operand
+ * (cost nnz * 4^n; far below 8 d^3 for sparse elements such as nested brackets of Pauli strings).
+ * Inputs and outputs stay dense d x d matrices.  PAULI: FP64, single problems, method
+ * ORTHONORMALIZATION without raw_basis. */
+typedef enum lie_representation {
+    LIE_REP_DENSE = 0,
+    LIE_REP_PAULI = 1
+} lie_representation;
+
 /* How a screened candidate is decided (ignored for LIE_PREC_FP64). */
 typedef enum lie_decide {
     LIE_DECIDE_FP64 = 0,   /* every candidate is decided from its FP64 residual (screen used for nothing) */
@@ -109,6 +121,8 @@ typedef struct lie_closure_config {
                               (single problems only; doubles the basis memory) */
     int32_t method;        /* lie_method: LIE_METHOD_ORTHONORMALIZATION (default) or the comparison
                               baseline LIE_METHOD_RANK_SVD */
+    int32_t representation;/* lie_representation: LIE_REP_DENSE (default) or LIE_REP_PAULI */
+    int32_t reserved[3];   /* must be zero */
 } lie_closure_config;
 
 /* Kernel classes reported by the per-kernel counters of lie_closure_stats. */
@@ -194,6 +208,16 @@ lie_status lie_closure_basis(const lie_closure *h, double *out, int64_t capacity
 
 /* Same into device memory of the handle's device (ordered on the handle's stream). */
 lie_status lie_closure_basis_device(const lie_closure *h, void *dst, int64_t capacity, int64_t *written);
+
+/* Host utilities of the Pauli-sum representation (no device work).  For d = 2^n (1 <= n <= 7):
+ * coords[x * 2^n + z] = <iP_s, M> = -i tr(P_s M) / d, real for an
+ * anti-Hermitian M, where P_s = i^{|x & z|} X^x Z^z, X^x flips the basis-index bits in x and Z^z
+ * multiplies |j> by (-1)^{popcount(z & j)} (so P_s is the Kronecker product of I, X, Y, Z with one
+ * Y per bit set in both masks).  matrix: d x d complex128 row-major, interleaved (re, im); coords:
+ * 4^n doubles.  lie_pauli_matrix is the inverse (M = sum_s coords[s] iP_s).  LIE_ERR_ARG on NULL
+ * or a d that is not such a power of two. */
+lie_status lie_pauli_coordinates(int32_t d, const double *matrix, double *coords);
+lie_status lie_pauli_matrix(int32_t d, const double *coords, double *matrix);
 
 /* Algorithm 3 (Section 3.2): copy the raw basis B -- the accepted generators as given and the
  * accepted nested brackets [B_l, B_m], unnormalised, in append order -- into a host buffer

@@ -28,6 +28,7 @@ DECIDES = {"fp64": 0, "strict": 1, "screen": 2}
 EXPORTS = (
     "lie_closure_config_default", "lie_closure_init", "lie_closure_run", "lie_closure_run_budget",
     "lie_closure_dim", "lie_closure_basis", "lie_closure_basis_device", "lie_closure_raw_basis",
+    "lie_pauli_coordinates", "lie_pauli_matrix",
     "lie_closure_orthogonality",
     "lie_closure_stats_get", "lie_closure_free", "lie_status_string", "lie_last_error",
     "lie_closure_batch_init", "lie_closure_batch_run", "lie_closure_batch_dim", "lie_closure_batch_basis",
@@ -53,6 +54,8 @@ class Config(ctypes.Structure):
         ("tune_cache", ctypes.c_char_p),
         ("raw_basis", ctypes.c_int32),
         ("method", ctypes.c_int32),
+        ("representation", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 3),
     ]
 
 
@@ -121,6 +124,8 @@ def _declare(lib: ctypes.CDLL) -> ctypes.CDLL:
         "lie_closure_basis": (st, [vp, vp, i64, i64p]),
         "lie_closure_basis_device": (st, [vp, vp, i64, i64p]),
         "lie_closure_raw_basis": (st, [vp, vp, i64, i64p]),
+        "lie_pauli_coordinates": (st, [ctypes.c_int32, vp, vp]),
+        "lie_pauli_matrix": (st, [ctypes.c_int32, vp, vp]),
         "lie_closure_orthogonality": (st, [vp, dblp]),
         "lie_closure_stats_get": (st, [vp, ctypes.POINTER(Stats)]),
         "lie_closure_free": (None, [vp]),

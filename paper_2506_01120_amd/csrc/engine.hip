@@ -180,6 +180,12 @@ struct lie_closure {
     // comparison baseline (config.method = LIE_METHOD_RANK_SVD): standard algorithm, SVD rank test
     int method = LIE_METHOD_ORTHONORMALIZATION;
     lie::RankTester *rank = nullptr;
+    // Pauli-sum representation (config.representation = LIE_REP_PAULI): rows are coordinates over
+    // the 4^nq strings; each element's support is recorded for the sparse bracket
+    bool pauli = false;
+    int nq = 0;
+    int *sup_cnt = nullptr;      // cap
+    int *sup_idx = nullptr;      // cap x D
     // matrix-inversion method (config.method = LIE_METHOD_MATRIX_INVERSION)
     bool inv = false;
     lie::GramInverse *ginv = nullptr;
@@ -222,8 +228,9 @@ struct lie_closure {
             (void)hipGraphExecDestroy(graph.exec);
         lie::rank_tester_destroy(rank);
         lie::gram_inverse_destroy(ginv);
-        if (Xc)
-            (void)hipFree(Xc);
+        for (void *p : {(void *)Xc, (void *)sup_cnt, (void *)sup_idx})
+            if (p)
+                (void)hipFree(p);
         for (void *p : {(void *)d_cursor, (void *)V64, (void *)Vs, (void *)H64, (void *)Hs, (void *)C, (void *)Cs,
                         (void *)part,
                         (void *)normpart_s, (void *)cand_a2, (void *)cand_n2, (void *)rho2, (void *)h2, (void *)h2b,
@@ -331,6 +338,7 @@ struct lie_closure {
         a.elem_src = raw ? elem_src : nullptr;
         a.src0 = src0;
         a.rel = raw && mode == 1 ? 1 : 0;
+        a.track_new = pauli ? 1 : 0;
         a.h2 = h2_surv;
         a.rho2 = inv ? nullptr : rho2;  // the matrix-inversion step has no second projection pass
         a.cnt = cnt;
@@ -345,6 +353,11 @@ struct lie_closure {
         timer.begin(stream);
         HIP_TRY(lie::launch_accept_f64(a, stream));
         timer.end(kid, stream, 0, 0);
+        if (pauli) {
+            timer.begin(stream);
+            HIP_TRY(lie::launch_pauli_support(V64, D, st, cnt, sup_cnt, sup_idx, stream));
+            timer.end(LIE_K_OTHER, stream, 0, 0);
+        }
         if (raw) {
             // Algorithm 3: the raw rows of this launch's appends (brackets of raw rows)
             timer.begin(stream);
@@ -389,8 +402,18 @@ struct lie_closure {
         if (!raw)
             HIP_TRY(hipMalloc(&packed, (size_t)n_gen * D * sizeof(double)));
         Guard guard2{raw ? nullptr : packed};
-        HIP_TRY(hipMemcpyAsync(staging, gens_host, bytes, hipMemcpyHostToDevice, stream));
-        HIP_TRY(lie::launch_pack_c128(staging, packed, n_gen, d, stream));
+        if (pauli) {
+            // Pauli coordinates of each generator (fast Walsh-Hadamard transforms on the host)
+            std::vector<double> coords((size_t)n_gen * D);
+            for (int g = 0; g < n_gen; ++g)
+                lie::pauli_from_dense(gens_host + (size_t)g * D * 2, nq, coords.data() + (size_t)g * D);
+            HIP_TRY(hipMemcpyAsync(packed, coords.data(), (size_t)n_gen * D * sizeof(double), hipMemcpyHostToDevice,
+                                   stream));
+            HIP_TRY(hipStreamSynchronize(stream));
+        } else {
+            HIP_TRY(hipMemcpyAsync(staging, gens_host, bytes, hipMemcpyHostToDevice, stream));
+            HIP_TRY(lie::launch_pack_c128(staging, packed, n_gen, d, stream));
+        }
         if (method == LIE_METHOD_RANK_SVD)
             return generators_rank(packed);
         lie_status s;
@@ -432,8 +455,11 @@ struct lie_closure {
     {
         const double c = cnt, Dd = (double)D, dd = d;
         timer.begin(stream);
-        HIP_TRY(lie::launch_comm_f64(raw ? B64 : V64, d, cursor, nullptr, nullptr, cnt, st, H64, stream, dp0));
-        timer.end(LIE_K_COMM, stream, 8.0 * dd * dd * dd * c, 3.0 * c * Dd * sizeof(double));
+        if (pauli)
+            HIP_TRY(lie::launch_comm_pauli(V64, sup_cnt, sup_idx, nq, cursor, cnt, st, H64, stream, dp0));
+        else
+            HIP_TRY(lie::launch_comm_f64(raw ? B64 : V64, d, cursor, nullptr, nullptr, cnt, st, H64, stream, dp0));
+        timer.end(LIE_K_COMM, stream, pauli ? 0.0 : 8.0 * dd * dd * dd * c, 3.0 * c * Dd * sizeof(double));
         lie_status s;
         if ((s = project(nullptr, nullptr, cand_a2, cand_n2, cnt, n_lo, n_hi, LIE_K_DOT, LIE_K_SUB, LIE_K_REDUCE)) !=
             LIE_OK)
@@ -889,6 +915,14 @@ lie_status resolve_config(const lie_closure_config *in, lie_closure_config *out)
         return fail(LIE_ERR_ARG, "unknown method %d", out->method);
     if (out->method != LIE_METHOD_ORTHONORMALIZATION && out->precision != LIE_PREC_FP64)
         return fail(LIE_ERR_ARG, "the rank-test and matrix-inversion methods run in FP64 only");
+    if (out->representation != LIE_REP_DENSE && out->representation != LIE_REP_PAULI)
+        return fail(LIE_ERR_ARG, "unknown representation %d", out->representation);
+    if (out->representation == LIE_REP_PAULI &&
+        (out->precision != LIE_PREC_FP64 || out->method != LIE_METHOD_ORTHONORMALIZATION || out->raw_basis))
+        return fail(LIE_ERR_ARG, "the Pauli representation runs the orthonormalization method in FP64 without raw_basis");
+    for (int r : out->reserved)
+        if (r != 0)
+            return fail(LIE_ERR_ARG, "config.reserved must be zero");
     if (out->autotune != 0 && out->autotune != 1)
         return fail(LIE_ERR_ARG, "config.autotune must be 0 or 1");
     out->tune_cache = nullptr;  // read at init only (see lie_closure_init), never kept
@@ -930,6 +964,8 @@ lie_status lie_closure_init(lie_closure **out, const double *generators, int32_t
     lie_closure_config cfg;
     if ((s = resolve_config(cfg_in, &cfg)) != LIE_OK)
         return s;
+    if (cfg.representation == LIE_REP_PAULI && (d < 2 || (d & (d - 1)) != 0 || d > 128))
+        return fail(LIE_ERR_ARG, "the Pauli representation needs d = 2^n with 1 <= n <= 7 (got %d)", d);
     if (cfg.method == LIE_METHOD_RANK_SVD) {
         if (d > 16)
             return fail(LIE_ERR_ARG, "the rank-test method is limited to d <= 16 (got %d)", d);
@@ -976,6 +1012,10 @@ lie_status lie_closure_init(lie_closure **out, const double *generators, int32_t
         }
     }
     h->method = cfg.method;
+    h->pauli = cfg.representation == LIE_REP_PAULI;
+    if (h->pauli)
+        while ((1 << h->nq) < d)
+            ++h->nq;
     h->inv = cfg.method == LIE_METHOD_MATRIX_INVERSION;
     h->raw = cfg.raw_basis != 0 || cfg.method != LIE_METHOD_ORTHONORMALIZATION;  // the other methods keep B
     if (h->raw) {
@@ -1078,6 +1118,10 @@ lie_status lie_closure_init(lie_closure **out, const double *generators, int32_t
         if (e != hipSuccess)
             return bail(fail(LIE_ERR_DEVICE, "rank tester setup failed: %s", hipGetErrorString(e)));
     }
+    if (h->pauli) {
+        if ((s = alloc(&h->sup_cnt, (size_t)h->cap)) != LIE_OK || (s = alloc(&h->sup_idx, (size_t)h->cap * D)) != LIE_OK)
+            return bail(s);
+    }
     if (h->inv) {
         if ((s = alloc(&h->Xc, (size_t)bmax * capr)) != LIE_OK)
             return bail(s);
@@ -1137,6 +1181,21 @@ static lie_status basis_common(const lie_closure *h, void *dst, int64_t capacity
     if (n == 0)
         return LIE_OK;
     HIP_TRY(hipSetDevice(h->device));
+    if (h->pauli) {
+        // coordinates to dense matrices on the host
+        std::vector<double> coords((size_t)n * h->D), dense((size_t)n * h->D * 2);
+        HIP_TRY(hipMemcpyAsync(coords.data(), h->V64, coords.size() * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+        HIP_TRY(hipStreamSynchronize(h->stream));
+        for (int64_t k = 0; k < n; ++k)
+            lie::pauli_to_dense(coords.data() + k * h->D, h->nq, dense.data() + k * h->D * 2);
+        if (device_dst) {
+            HIP_TRY(hipMemcpyAsync(dst, dense.data(), dense.size() * sizeof(double), hipMemcpyHostToDevice, h->stream));
+            HIP_TRY(hipStreamSynchronize(h->stream));
+        } else {
+            std::memcpy(dst, dense.data(), dense.size() * sizeof(double));
+        }
+        return LIE_OK;
+    }
     if (device_dst) {
         HIP_TRY(lie::launch_unpack_c128(h->V64, (double *)dst, n, h->d, h->stream));
         HIP_TRY(hipStreamSynchronize(h->stream));
@@ -1163,6 +1222,34 @@ lie_status lie_closure_basis(const lie_closure *h, double *out, int64_t capacity
 lie_status lie_closure_basis_device(const lie_closure *h, void *dst, int64_t capacity, int64_t *written)
 {
     return basis_common(h, dst, capacity, written, true);
+}
+
+static int pauli_qubits(int32_t d)
+{
+    if (d < 2 || d > 128 || (d & (d - 1)) != 0)
+        return -1;
+    int n = 0;
+    while ((1 << n) < d)
+        ++n;
+    return n;
+}
+
+lie_status lie_pauli_coordinates(int32_t d, const double *matrix, double *coords)
+{
+    const int n = pauli_qubits(d);
+    if (n < 0 || !matrix || !coords)
+        return fail(LIE_ERR_ARG, "need d = 2^n (1 <= n <= 7) and non-NULL buffers");
+    lie::pauli_from_dense(matrix, n, coords);
+    return LIE_OK;
+}
+
+lie_status lie_pauli_matrix(int32_t d, const double *coords, double *matrix)
+{
+    const int n = pauli_qubits(d);
+    if (n < 0 || !matrix || !coords)
+        return fail(LIE_ERR_ARG, "need d = 2^n (1 <= n <= 7) and non-NULL buffers");
+    lie::pauli_to_dense(coords, n, matrix);
+    return LIE_OK;
 }
 
 lie_status lie_closure_raw_basis(const lie_closure *h, double *out, int64_t capacity, int64_t *written)
@@ -1826,8 +1913,9 @@ lie_status lie_closure_batch_init(lie_closure_batch **out, int32_t n_problems, c
     lie_status s = resolve_config(cfg_in, &cfg);
     if (s != LIE_OK)
         return s;
-    if (cfg.raw_basis || cfg.method != LIE_METHOD_ORTHONORMALIZATION)
-        return fail(LIE_ERR_ARG, "config.raw_basis and the comparison methods are supported for single problems only");
+    if (cfg.raw_basis || cfg.method != LIE_METHOD_ORTHONORMALIZATION || cfg.representation != LIE_REP_DENSE)
+        return fail(LIE_ERR_ARG, "config.raw_basis, the comparison methods and the Pauli representation are "
+                                 "supported for single problems only");
     // validate every problem before any device work
     for (int32_t i = 0; i < n_problems; ++i) {
         int64_t amb = 0;

@@ -972,8 +972,8 @@ __device__ __forceinline__ void accept_body(const AcceptArgs &a)
     const int64_t slots = a.lds_doubles > a.cnt + D ? (a.lds_doubles - a.cnt - D) / D : 0;
     if (threadIdx.x == 0) {
         sN = st->N;
-        if (a.elem_src)
-            st->raw_lo = sN;  // the raw rows of this launch's appends start here
+        if (a.elem_src || a.track_new)
+            st->raw_lo = sN;  // the rows appended by this launch start here
         stop = aborted(st);
         ns = a.nsurv ? *a.nsurv : 0;
         for (int i = 0; i < 4; ++i)

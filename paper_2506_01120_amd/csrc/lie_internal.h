@@ -203,6 +203,7 @@ struct AcceptArgs {
     int64_t *elem_src;       // Algorithm 3: element N -> its pair index, or -(generator + 1) (null: off)
     int64_t src0;            // Algorithm 3, generator phase: the source code of the (single) candidate
     int rel;                 // 1: brackets use the relative threshold tol * ||h|| (Algorithm 3)
+    int track_new;           // 1: record st->raw_lo (first row appended by this launch) without elem_src
     int cnt;
     int64_t D, cap, ambient;
     double tol;
@@ -311,6 +312,19 @@ hipError_t gram_inverse_update(GramInverse *g, const double *B, int64_t N, int *
 // X (cnt x N, row stride ldx) = beta (cnt x N, row stride ldb) A^{-1}.
 hipError_t gram_inverse_apply(GramInverse *g, const double *beta, int64_t ldb, int64_t N, int cnt, double *X,
                               int64_t ldx);
+
+// ------------------------------------------------------------- Pauli-sum representation (pauli.hip)
+// Rows are coefficient vectors over the 4^n strings iP_s (index x * 2^n + z), D = 4^n.
+// H[c] = [V_l, V_m] for pairs p0 + c (or *dp0 + c) through the sparse symplectic product.
+hipError_t launch_comm_pauli(const double *V, const int *sup_cnt, const int *sup_idx, int n, int64_t p0, int cnt,
+                             const DevState *st, double *H, hipStream_t s, const int64_t *dp0 = nullptr);
+// Supports of the rows [st->raw_lo, st->N) (indices of coefficients above 1e-14 of the row norm).
+hipError_t launch_pauli_support(const double *V, int64_t D, const DevState *st, int max_new, int *sup_cnt,
+                                int *sup_idx, hipStream_t s);
+// Host transforms between a dense anti-Hermitian d x d matrix (interleaved complex, row-major)
+// and its 4^n real Pauli coordinates.
+void pauli_from_dense(const double *g, int n, double *out);
+void pauli_to_dense(const double *a, int n, double *g);
 
 // ------------------------------------------------------------- autotuner (autotune.hip)
 struct TuneChoice {

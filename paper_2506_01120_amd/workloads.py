@@ -98,6 +98,26 @@ def pauli_set(n: int, k: int, seed: int) -> np.ndarray:
     return np.ascontiguousarray(np.stack([c * pauli_string(s) for s, c in zip(strings, coeffs)]))
 
 
+def pauli_sums(n: int, k: int, terms: int, seed: int) -> np.ndarray:
+    """k generators, each i * sum of `terms` distinct random non-identity Pauli strings on n
+    qubits with standard-normal real weights (numpy PCG64 ``default_rng(seed)``),
+    Frobenius-normalised: sparse sums of Pauli strings, the operators of the sparse
+    representation."""
+    rng = np.random.default_rng(seed)
+    letters = "IXYZ"
+    out = []
+    for _ in range(k):
+        picked = set()
+        while len(picked) < terms:
+            s = "".join(letters[i] for i in rng.integers(0, 4, size=n))
+            if s != "I" * n:
+                picked.add(s)
+        m = sum(w * pauli_string(s) for s, w in zip(sorted(picked), rng.standard_normal(terms)))
+        m = 1j * m
+        out.append(m / np.linalg.norm(m))
+    return np.ascontiguousarray(np.stack(out))
+
+
 def rand_pair(d: int, seed: int) -> np.ndarray:
     """Two random traceless anti-Hermitian d x d matrices, Frobenius-normalised.
 
