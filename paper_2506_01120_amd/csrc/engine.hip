@@ -44,6 +44,9 @@ lie_status fail(lie_status st, const char *fmt, ...)
 
 // Blocks of at most this many rows use the split-K GEMV projection; larger ones the matrix-core GEMMs.
 constexpr int kGemvRows = 16;
+// Set while the batch API creates its problems: their passes are grouped launches that
+// need no split-K workspace.
+thread_local bool t_batch_member = false;
 // Block steps enqueued between two synchronisations: growth-size blocks, saturated blocks.
 constexpr int kGrowthQueued = 4;
 // Default SCREEN reject threshold on the FP32-screened residual (paper norm).
@@ -161,6 +164,8 @@ struct lie_closure {
     double *C = nullptr;         // block x cap FP64 coefficients
     float *Cs = nullptr;         // block x cap FP32 coefficients
     double *part = nullptr;      // FP64 split-K scratch + norm partials
+    double *splitws = nullptr;   // K slices of small matrix-core passes
+    size_t splitws_n = 0;
     double *normpart_s = nullptr;// block x tiles, screened residual partial norms
     double *cand_a2 = nullptr;   // block: squared residual of the first pass (screen or FP64)
     double *cand_n2 = nullptr;   // block: squared candidate norm of the first pass
@@ -232,7 +237,7 @@ struct lie_closure {
             if (p)
                 (void)hipFree(p);
         for (void *p : {(void *)d_cursor, (void *)V64, (void *)Vs, (void *)H64, (void *)Hs, (void *)C, (void *)Cs,
-                        (void *)part,
+                        (void *)part, (void *)splitws,
                         (void *)normpart_s, (void *)cand_a2, (void *)cand_n2, (void *)rho2, (void *)h2, (void *)h2b,
                         (void *)surv_rows, (void *)surv_pairs, (void *)slot, (void *)keep, (void *)nsurv,
                         (void *)st, (void *)scalar, (void *)B64, (void *)Bs, (void *)Graw, (void *)elem_src})
@@ -286,22 +291,35 @@ struct lie_closure {
             // matrix-core path: coefficients, then residual with fused norms, then the norm sums;
             // the coefficient rows span the capacity so that any basis size fits
             const int64_t ldc = lie::coef_ld(cap);
+            // small passes split K over workgroups (coefficient slices first in the workspace,
+            // then the residual's partial products)
+            const lie::SplitPlan sp = lie::gemm_split_plan_f64(cnt, sh.n_hi, D, ldc, splitws ? splitws_n : 0);
+            double *Cd = sp.kd > 1 ? splitws : C;
+            double *P = splitws + (sp.kd > 1 ? (size_t)sp.kd * cnt * ldc : 0);
             timer.begin(stream);
-            HIP_TRY(lie::launch_gemm_dot_f64(V64, st, H64, rows, nrows, cnt, D, sh.n_hi, ldc, C, stream));
+            HIP_TRY(lie::launch_gemm_dot_f64(V64, st, H64, rows, nrows, cnt, D, sh.n_hi, ldc, Cd, stream, sp.kd));
             timer.end(kid_dot, stream, 2.0 * N * Dd * c, (N * Dd + c * Dd + c * N) * w);
             timer.begin(stream);
-            HIP_TRY(lie::launch_gemm_sub_f64(V64, st, H64, rows, nrows, C, sh.n_hi, ldc, cnt, D, part, stream));
+            HIP_TRY(lie::launch_gemm_sub_f64(V64, st, H64, rows, nrows, Cd, sh.n_hi, ldc, cnt, D, part, stream, sp.kd,
+                                             sp.ks, P));
             timer.end(kid_sub, stream, 2.0 * N * Dd * c, (N * Dd + c * N + 2.0 * c * Dd) * w);
             timer.begin(stream);
-            HIP_TRY(lie::launch_norm_final(part, nrows, cnt, lie::gemm_sub_tiles_f64(D), st, rho2_out, h2_out, stream));
+            if (sp.ks > 1)
+                HIP_TRY(lie::launch_gemm_sub_finish_f64(P, sp.ks, H64, rows, nrows, cnt, D, st, rho2_out, h2_out,
+                                                        stream));
+            else
+                HIP_TRY(lie::launch_norm_final(part, nrows, cnt, lie::gemm_sub_tiles_f64(D), st, rho2_out, h2_out,
+                                               stream));
             timer.end(kid_red, stream, 0, 0);
             return LIE_OK;
         }
+        const int sd = lie::dot_slices_f64(sh, splitws ? splitws_n : 0);
+        double *Cd = sd > 1 ? splitws : C;
         timer.begin(stream);
-        HIP_TRY(lie::launch_dot_f64(V64, st, H64, rows, nrows, C, sh, stream));
+        HIP_TRY(lie::launch_dot_f64(V64, st, H64, rows, nrows, Cd, sh, stream, sd));
         timer.end(kid_dot, stream, 2.0 * N * Dd * c, (N * Dd + c * Dd + c * N) * w);
         timer.begin(stream);
-        HIP_TRY(lie::launch_sub_f64(V64, st, C, nrows, part, sh, stream));
+        HIP_TRY(lie::launch_sub_f64(V64, st, Cd, nrows, part, sh, stream, sd));
         timer.end(kid_sub, stream, 2.0 * N * Dd * c, (N * Dd + c * N + c * Dd) * w);
         const int ks = lie::project_split_k(D, cnt, sh.n_hi);
         timer.begin(stream);
@@ -1097,6 +1115,8 @@ lie_status lie_closure_init(lie_closure **out, const double *generators, int32_t
         (s = alloc(&h->h2b, bmax)) != LIE_OK || (s = alloc(&h->surv_rows, bmax)) != LIE_OK ||
         (s = alloc(&h->surv_pairs, bmax)) != LIE_OK || (s = alloc(&h->slot, bmax)) != LIE_OK ||
         (s = alloc(&h->keep, bmax)) != LIE_OK ||
+        (!t_batch_member && (s = alloc(&h->splitws, h->splitws_n = lie::gemm_split_ws_doubles(D, (int64_t)capr))) !=
+                                LIE_OK) ||
         (s = alloc(&h->nsurv, 1)) != LIE_OK || (s = alloc(&h->scalar, 1)) != LIE_OK ||
         (s = alloc(&h->d_cursor, 1)) != LIE_OK ||
         (s = alloc(&h->st, 1)) != LIE_OK)
@@ -1952,7 +1972,9 @@ lie_status lie_closure_batch_init(lie_closure_batch **out, int32_t n_problems, c
     pc.tune_cache = cfg_in ? cfg_in->tune_cache : nullptr;  // resolve_config drops the pointer
     for (int32_t i = 0; i < n_problems; ++i) {
         lie_closure *h = nullptr;
+        t_batch_member = true;  // the grouped launches need no split-K workspace
         s = lie_closure_init(&h, generators[i], n_gen[i], d[i], tol[i], &pc);
+        t_batch_member = false;
         if (s != LIE_OK) {
             std::string msg = g_last_error;
             delete b;

@@ -296,12 +296,16 @@ __global__ void __launch_bounds__(kThreads) k_comm_f64_global_b(Batch b)
 __device__ inline bool aborted(const DevState *st) { return st->done | st->numeric_error | st->full; }
 
 // C[r][k] = <H_row(r), V_k> for k < N (tiled: 16 basis rows x 16 pass rows per workgroup).
-constexpr int kDotT = 16, kDotJ = 32;
+// With grid.z = sd > 1 the element range is split in sd slices and slice z of the sums is
+// written at C + z * cslice (the consumer adds them); a few workgroups then no longer wait
+// on one load round trip per element chunk in turn.
+constexpr int kDotT = 16, kDotJ = 32, kMaxDotSlices = 16;
 
 __global__ void __launch_bounds__(kThreads) k_dot_f64(const double *__restrict__ V, const DevState *__restrict__ st,
                                                       int64_t N_fixed, const double *__restrict__ H,
                                                       const int *__restrict__ rows, const int *__restrict__ nrows,
-                                                      int cnt, int64_t D, double *__restrict__ C, int64_t ldc)
+                                                      int cnt, int64_t D, double *__restrict__ C, int64_t ldc,
+                                                      int64_t cslice)
 {
     if (st && aborted(st))
         return;
@@ -314,14 +318,17 @@ __global__ void __launch_bounds__(kThreads) k_dot_f64(const double *__restrict__
     __shared__ double Vs[kDotT][kDotJ + 1];
     __shared__ double Hs[kDotT][kDotJ + 1];
     const int tk = threadIdx.x % kDotT, tc = threadIdx.x / kDotT;
+    const int64_t nch = (D + kDotJ - 1) / kDotJ, per = (nch + gridDim.z - 1) / gridDim.z;
+    const int64_t jlo = std::min<int64_t>(D, (int64_t)blockIdx.z * per * kDotJ);
+    const int64_t jhi = std::min<int64_t>(D, jlo + per * kDotJ);
     double acc = 0.0;
-    for (int64_t j0 = 0; j0 < D; j0 += kDotJ) {
+    for (int64_t j0 = jlo; j0 < jhi; j0 += kDotJ) {
         for (int e = threadIdx.x; e < kDotT * kDotJ; e += blockDim.x) {
             const int r = e / kDotJ, jj = e % kDotJ;
             const int64_t j = j0 + jj;
-            Vs[r][jj] = (k0 + r < N && j < D) ? V[(k0 + r) * D + j] : 0.0;
+            Vs[r][jj] = (k0 + r < N && j < jhi) ? V[(k0 + r) * D + j] : 0.0;
             double hv = 0.0;
-            if (c0 + r < nr && j < D) {
+            if (c0 + r < nr && j < jhi) {
                 const int hr = rows ? rows[c0 + r] : c0 + r;
                 hv = H[(int64_t)hr * D + j];
             }
@@ -333,7 +340,7 @@ __global__ void __launch_bounds__(kThreads) k_dot_f64(const double *__restrict__
         __syncthreads();
     }
     if (k0 + tk < N && c0 + tc < nr)
-        C[(int64_t)(c0 + tc) * ldc + k0 + tk] = acc;
+        C[(int64_t)blockIdx.z * cslice + (int64_t)(c0 + tc) * ldc + k0 + tk] = acc;
 }
 
 // part[ks][r][j] = sum_{k in chunk ks} C[r][k] V[k][j]  (64 columns x 4 pass rows per workgroup)
@@ -342,6 +349,7 @@ constexpr int kSubJ = 64, kSubC = 4, kSubK = 16;
 __global__ void __launch_bounds__(kThreads) k_sub_partial_f64(const double *__restrict__ V,
                                                               const DevState *__restrict__ st,
                                                               const double *__restrict__ C, int64_t ldc,
+                                                              int cs, int64_t cslice,
                                                               const int *__restrict__ nrows, int cnt, int64_t D,
                                                               int ks_total, double *__restrict__ part)
 {
@@ -369,7 +377,20 @@ __global__ void __launch_bounds__(kThreads) k_sub_partial_f64(const double *__re
         if (threadIdx.x < kSubC * kSubK) {
             const int r = threadIdx.x / kSubK, kk = threadIdx.x % kSubK;
             const int64_t k = k0 + kk;
-            Ct[r][kk] = (k < ke && c0 + r < nr) ? C[(int64_t)(c0 + r) * ldc + k] : 0.0;
+            double cv = 0.0;
+            if (k < ke && c0 + r < nr) {
+                // the cs coefficient slices: loaded together, added in slice order
+                double sl[kMaxDotSlices];
+                const double *p = C + (int64_t)(c0 + r) * ldc + k;
+#pragma unroll
+                for (int q = 0; q < kMaxDotSlices; ++q)
+                    sl[q] = q < cs ? p[(int64_t)q * cslice] : 0.0;
+#pragma unroll
+                for (int q = 0; q < kMaxDotSlices; ++q)
+                    if (q < cs)
+                        cv += sl[q];
+            }
+            Ct[r][kk] = cv;
         }
         __syncthreads();
         for (int kk = 0; kk < kSubK; ++kk)
@@ -1613,20 +1634,35 @@ size_t proj_scratch_doubles(int64_t D, int cnt_max, int64_t cap)
 
 int project_split_k(int64_t D, int cnt, int64_t n_hi) { return split_k(D, cnt, std::max<int64_t>(n_hi, 1)); }
 
+int dot_slices_f64(ProjShape sh, size_t ws_doubles)
+{
+    const int64_t n_hi = std::max<int64_t>(sh.n_hi, 1);
+    const int64_t tiles = ((n_hi + kDotT - 1) / kDotT) * ((sh.cnt + kDotT - 1) / kDotT);
+    const int64_t nch = (sh.D + kDotJ - 1) / kDotJ;
+    if (sh.cnt <= 0 || tiles >= 64 || nch < 2)
+        return 1;
+    int64_t sd = std::min<int64_t>({(int64_t)kMaxDotSlices, nch, (128 + tiles - 1) / tiles});
+    while (sd > 1 && (size_t)sd * sh.cnt * n_hi > ws_doubles)
+        --sd;
+    return (int)std::max<int64_t>(sd, 1);
+}
+
 hipError_t launch_dot_f64(const double *V, const DevState *st, const double *H, const int *rows, const int *nrows,
-                          double *C, ProjShape sh, hipStream_t s)
+                          double *C, ProjShape sh, hipStream_t s, int sd)
 {
     const int cnt = sh.cnt;
     if (cnt <= 0)
         return hipSuccess;
     const int64_t n_hi = std::max<int64_t>(sh.n_hi, 1);
-    hipLaunchKernelGGL(k_dot_f64, dim3((unsigned)((n_hi + kDotT - 1) / kDotT), (cnt + kDotT - 1) / kDotT),
-                       dim3(kThreads), 0, s, V, st, (int64_t)0, H, rows, nrows, cnt, sh.D, C, n_hi);
+    sd = std::min(std::max(sd, 1), kMaxDotSlices);
+    hipLaunchKernelGGL(k_dot_f64, dim3((unsigned)((n_hi + kDotT - 1) / kDotT), (cnt + kDotT - 1) / kDotT, sd),
+                       dim3(kThreads), 0, s, V, st, (int64_t)0, H, rows, nrows, cnt, sh.D, C, n_hi,
+                       (int64_t)cnt * n_hi);
     return hipGetLastError();
 }
 
 hipError_t launch_sub_f64(const double *V, const DevState *st, const double *C, const int *nrows, double *part,
-                          ProjShape sh, hipStream_t s)
+                          ProjShape sh, hipStream_t s, int cs)
 {
     const int cnt = sh.cnt;
     if (cnt <= 0)
@@ -1635,7 +1671,8 @@ hipError_t launch_sub_f64(const double *V, const DevState *st, const double *C, 
     const int ks = split_k(sh.D, cnt, n_hi);
     hipLaunchKernelGGL(k_sub_partial_f64,
                        dim3((unsigned)((sh.D + kSubJ - 1) / kSubJ), (cnt + kSubC - 1) / kSubC, ks), dim3(kThreads), 0,
-                       s, V, st, C, n_hi, nrows, cnt, sh.D, ks, part);
+                       s, V, st, C, n_hi, std::min(std::max(cs, 1), kMaxDotSlices), (int64_t)cnt * n_hi, nrows, cnt,
+                       sh.D, ks, part);
     return hipGetLastError();
 }
 
@@ -1713,7 +1750,7 @@ hipError_t launch_orth_loss(const double *V, int64_t n, int64_t D, double *work,
         const int64_t rows = std::min<int64_t>(n - c0, (int64_t)65535 * kDotT);
         hipLaunchKernelGGL(k_dot_f64, dim3((unsigned)((n + kDotT - 1) / kDotT), (unsigned)((rows + kDotT - 1) / kDotT)),
                            dim3(kThreads), 0, s, V, (const DevState *)nullptr, n, V + c0 * D, (const int *)nullptr,
-                           (const int *)nullptr, (int)rows, D, G + c0 * n, n);
+                           (const int *)nullptr, (int)rows, D, G + c0 * n, n, (int64_t)0);
     }
     const int parts = 256;
     double *part = work + n * n;

@@ -6,6 +6,14 @@
 //                 with the squared norms of R (and of H) summed per output tile,
 //                 R optionally written back over H.
 //
+// Small passes (a growth-phase block of a few dozen candidates gives only a
+// handful of output tiles) split K across workgroups: grid.z = number of K
+// slices.  The coefficient slices are summed by the residual kernel as it loads
+// them; the residual's own slices (partial products C V) are summed, in slice
+// order, by a finishing kernel that forms R and its norms.  Without the split
+// such a pass runs on a few compute units and waits on one global-load round
+// trip per K chunk.
+//
 // Workgroup: 4 waves as 2 x 2; each wave owns SM x SN matrix-core tiles.
 // K is staged through LDS in chunks of 16 with a register prefetch of the next
 // chunk (one barrier per chunk).  Both operands are stored k-major in LDS so
@@ -57,6 +65,7 @@ struct Mma<double> {
 };
 
 constexpr int KC = 16;  // K chunk
+constexpr int kMaxSlices = 16;  // K slices of a split pass
 
 __device__ inline bool aborted(const DevState *st) { return st && (st->done | st->numeric_error | st->full); }
 
@@ -121,6 +130,39 @@ struct KContigLoader {
 };
 
 // Tile loader of a row-major K x N operand (rows k, contiguous n): k [k0, k0+KC) x n [n0, n0+BN) as S[k][n].
+// Loader of a K-contiguous operand held as `cs` <= CS slices whose sum is the operand
+// (coefficients of a split pass): all slices are loaded at once, so their loads are in
+// flight together, and added in slice order when the tile is stored.
+template <typename T, int BR, int CS>
+struct SlicedLoader {
+    KContigLoader<T, BR> part[CS];
+    int cs = 1;
+    int64_t stride = 0;
+
+    template <typename RowFn>
+    __device__ void load(const T *__restrict__ base, int64_t ld, int64_t r0, int64_t rows, int64_t k0, int64_t K,
+                         bool vec_ok, RowFn rowmap)
+    {
+#pragma unroll
+        for (int q = 0; q < CS; ++q)
+            if (q < cs)
+                part[q].load(base + (int64_t)q * stride, ld, r0, rows, k0, K, vec_ok, rowmap);
+    }
+    template <int LDW>
+    __device__ void store(T (*S)[LDW])
+    {
+#pragma unroll
+        for (int q = 1; q < CS; ++q)
+            if (q < cs)
+#pragma unroll
+                for (int i = 0; i < KContigLoader<T, BR>::PER_THREAD; ++i)
+#pragma unroll
+                    for (int u = 0; u < KContigLoader<T, BR>::VEC; ++u)
+                        part[0].v[i][u] += part[q].v[i][u];
+        part[0].store(S);
+    }
+};
+
 template <typename T, int BN>
 struct KRowLoader {
     static constexpr int VEC = 16 / sizeof(T);
@@ -181,9 +223,17 @@ struct KRowLoader {
 
 
 
+// K chunks [lo, hi) of slice kz out of ks (every chunk in exactly one slice).
+__device__ inline void slice_range(int nchunks, int kz, int ks, int &lo, int &hi)
+{
+    const int per = (nchunks + ks - 1) / ks;
+    lo = min(nchunks, kz * per);
+    hi = min(nchunks, lo + per);
+}
+
 // ---------------------------------------------------------------- coefficients
 template <typename T, int SM, int SN>
-__device__ void gemm_dot_body(const GemmArgs &g, int bx0, int by, int gxs)
+__device__ void gemm_dot_body(const GemmArgs &g, int bx0, int by, int gxs, int kz = 0)
 {
     using M = Mma<T>;
     constexpr int BM = 2 * SM * M::E, BN = 2 * SN * M::E;
@@ -214,15 +264,18 @@ __device__ void gemm_dot_body(const GemmArgs &g, int bx0, int by, int gxs)
 #pragma unroll
             for (int j = 0; j < SN; ++j)
                 acc[i][j] = M::zero();
-        const int nchunks = (int)((g.D + KC - 1) / KC);
-        la.load(H, g.D, m0, Mrows, 0, g.D, vec_ok, hmap);
-        lb.load(V, g.D, n0, N, 0, g.D, vec_ok, ident);
-        la.store(As[0]);
-        lb.store(Bs[0]);
+        int clo = 0, chi = 0;
+        slice_range((int)((g.D + KC - 1) / KC), kz, g.ksplit > 1 ? g.ksplit : 1, clo, chi);
+        if (clo < chi) {
+            la.load(H, g.D, m0, Mrows, (int64_t)clo * KC, g.D, vec_ok, hmap);
+            lb.load(V, g.D, n0, N, (int64_t)clo * KC, g.D, vec_ok, ident);
+            la.store(As[0]);
+            lb.store(Bs[0]);
+        }
         __syncthreads();
-        for (int c = 0; c < nchunks; ++c) {
-            const int buf = c & 1;
-            if (c + 1 < nchunks) {
+        for (int c = clo; c < chi; ++c) {
+            const int buf = (c - clo) & 1;
+            if (c + 1 < chi) {
                 la.load(H, g.D, m0, Mrows, (int64_t)(c + 1) * KC, g.D, vec_ok, hmap);
                 lb.load(V, g.D, n0, N, (int64_t)(c + 1) * KC, g.D, vec_ok, ident);
             }
@@ -241,13 +294,13 @@ __device__ void gemm_dot_body(const GemmArgs &g, int bx0, int by, int gxs)
                     for (int j = 0; j < SN; ++j)
                         acc[i][j] = M::mma(a[i], b[j], acc[i][j]);
             }
-            if (c + 1 < nchunks) {
+            if (c + 1 < chi) {
                 la.store(As[buf ^ 1]);
                 lb.store(Bs[buf ^ 1]);
             }
             __syncthreads();
         }
-        T *C = static_cast<T *>(g.C);
+        T *C = static_cast<T *>(g.C) + (int64_t)kz * g.cslice;
 #pragma unroll
         for (int i = 0; i < SM; ++i)
 #pragma unroll
@@ -263,8 +316,8 @@ __device__ void gemm_dot_body(const GemmArgs &g, int bx0, int by, int gxs)
 }
 
 // ---------------------------------------------------------------- residual + norms
-template <typename T, int SM, int SN>
-__device__ void gemm_sub_body(const GemmArgs &g, int bx, int by, int ntiles)
+template <typename T, int SM, int SN, int CS = 1>
+__device__ void gemm_sub_body(const GemmArgs &g, int bx, int by, int ntiles, int kz = 0)
 {
     using M = Mma<T>;
     constexpr int BM = 2 * SM * M::E, BN = 2 * SN * M::E;
@@ -283,10 +336,13 @@ __device__ void gemm_sub_body(const GemmArgs &g, int bx, int by, int ntiles)
     const T *Cc = static_cast<const T *>(g.C);
     const T *V = static_cast<const T *>(g.V);
     auto ident = [](int64_t r) -> int64_t { return r; };
-    KContigLoader<T, BM> la;  // C rows (K = basis index, contiguous)
-    KRowLoader<T, BN> lb;     // V rows
+    SlicedLoader<T, BM, CS> la;  // C rows (K = basis index, contiguous), as coefficient slices
+    KRowLoader<T, BN> lb;        // V rows
+    la.cs = CS > 1 ? min(max(g.cslices, 1), CS) : 1;
+    la.stride = g.cslice;
     const bool vec_c = (g.ldc % (16 / sizeof(T))) == 0;
     const bool vec_v = (g.D % (16 / sizeof(T))) == 0;
+    auto load_c = [&](int64_t k0) { la.load(Cc, g.ldc, m0, Mrows, k0, N, vec_c, ident); };
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int wm = w >> 1, wn = w & 1;
     typename M::Acc acc[SM][SN];
@@ -295,18 +351,19 @@ __device__ void gemm_sub_body(const GemmArgs &g, int bx, int by, int ntiles)
 #pragma unroll
         for (int j = 0; j < SN; ++j)
             acc[i][j] = M::zero();
-    const int nchunks = (int)((N + KC - 1) / KC);
-    if (nchunks > 0) {
-        la.load(Cc, g.ldc, m0, Mrows, 0, N, vec_c, ident);
-        lb.load(V, g.D, 0, N, j0, g.D, vec_v);
+    int clo = 0, chi = 0;
+    slice_range((int)((N + KC - 1) / KC), kz, g.ksplit > 1 ? g.ksplit : 1, clo, chi);
+    if (clo < chi) {
+        load_c((int64_t)clo * KC);
+        lb.load(V, g.D, (int64_t)clo * KC, N, j0, g.D, vec_v);
         la.store(As[0]);
         lb.store(Bs[0]);
     }
     __syncthreads();
-    for (int c = 0; c < nchunks; ++c) {
-        const int buf = c & 1;
-        if (c + 1 < nchunks) {
-            la.load(Cc, g.ldc, m0, Mrows, (int64_t)(c + 1) * KC, N, vec_c, ident);
+    for (int c = clo; c < chi; ++c) {
+        const int buf = (c - clo) & 1;
+        if (c + 1 < chi) {
+            load_c((int64_t)(c + 1) * KC);
             lb.load(V, g.D, (int64_t)(c + 1) * KC, N, j0, g.D, vec_v);
         }
 #pragma unroll
@@ -324,11 +381,27 @@ __device__ void gemm_sub_body(const GemmArgs &g, int bx, int by, int ntiles)
                 for (int j = 0; j < SN; ++j)
                     acc[i][j] = M::mma(a[i], b[j], acc[i][j]);
         }
-        if (c + 1 < nchunks) {
+        if (c + 1 < chi) {
             la.store(As[buf ^ 1]);
             lb.store(Bs[buf ^ 1]);
         }
         __syncthreads();
+    }
+    if (g.ksplit > 1) {
+        // one K slice of C V: stored for the finishing kernel
+        T *P = static_cast<T *>(g.P) + (int64_t)kz * g.pslice;
+#pragma unroll
+        for (int i = 0; i < SM; ++i)
+#pragma unroll
+            for (int j = 0; j < SN; ++j)
+#pragma unroll
+                for (int r = 0; r < M::NR; ++r) {
+                    const int m = m0 + wm * SM * M::E + i * M::E + M::out_row(lane, r);
+                    const int64_t col = j0 + wn * SN * M::E + j * M::E + M::out_col(lane);
+                    if (m < Mrows && col < g.D)
+                        P[(int64_t)m * g.D + col] = acc[i][j][r];
+                }
+        return;
     }
     // epilogue: R = H - acc, squared norms of R and H summed over this wave's columns
     T *H = const_cast<T *>(static_cast<const T *>(g.H));
@@ -380,13 +453,58 @@ __device__ void gemm_sub_body(const GemmArgs &g, int bx, int by, int ntiles)
 template <typename T, int SM, int SN>
 __global__ void __launch_bounds__(256) k_gemm_dot(GemmArgs g)
 {
-    gemm_dot_body<T, SM, SN>(g, blockIdx.x, blockIdx.y, gridDim.x);
+    gemm_dot_body<T, SM, SN>(g, blockIdx.x, blockIdx.y, gridDim.x, blockIdx.z);
 }
 
-template <typename T, int SM, int SN>
+template <typename T, int SM, int SN, int CS = 1>
 __global__ void __launch_bounds__(256) k_gemm_sub(GemmArgs g)
 {
-    gemm_sub_body<T, SM, SN>(g, blockIdx.x, blockIdx.y, gridDim.x);
+    gemm_sub_body<T, SM, SN, CS>(g, blockIdx.x, blockIdx.y, gridDim.x, blockIdx.z);
+}
+
+// Finishing step of a split residual pass, one workgroup per row m: R = H - sum_z P_z
+// (slices added in order), written over H when asked, and the squared norms of R and H.
+__global__ void __launch_bounds__(256) k_gemm_sub_finish(GemmArgs g, double *rho2, double *h2)
+{
+    __shared__ double red[2][4];
+    const int m = blockIdx.x;
+    const int Mrows = g.nrows ? *g.nrows : g.cnt;
+    if (m >= Mrows || aborted(g.st))
+        return;
+    double *H = const_cast<double *>(static_cast<const double *>(g.H)) + (int64_t)(g.rows ? g.rows[m] : m) * g.D;
+    const double *P = static_cast<const double *>(g.P) + (int64_t)m * g.D;
+    double rs = 0.0, hs = 0.0;
+    for (int64_t j = threadIdx.x; j < g.D; j += blockDim.x) {
+        double acc = 0.0;
+        for (int z = 0; z < g.ksplit; ++z)
+            acc += P[(int64_t)z * g.pslice + j];
+        const double h = H[j], r = h - acc;
+        if (g.write_r)
+            H[j] = r;
+        rs += r * r;
+        hs += h * h;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        rs += __shfl_xor(rs, off, 64);
+        hs += __shfl_xor(hs, off, 64);
+    }
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) {
+        red[0][w] = rs;
+        red[1][w] = hs;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int nw = blockDim.x >> 6;
+        double a = 0.0, b = 0.0;
+        for (int q = 0; q < nw; ++q) {
+            a += red[0][q];
+            b += red[1][q];
+        }
+        rho2[m] = a;
+        if (h2)
+            h2[m] = b;
+    }
 }
 
 template <typename T, int SM, int SN>
@@ -437,8 +555,9 @@ hipError_t dot_impl(const GemmArgs &g, int64_t n_hi, hipStream_t s)
 {
     constexpr int E = Mma<T>::E;
     constexpr int BM = 2 * SM * E, BN = 2 * SN * E;
-    hipLaunchKernelGGL((k_gemm_dot<T, SM, SN>), dim3((unsigned)((n_hi + BN - 1) / BN), (g.cnt + BM - 1) / BM),
-                       dim3(256), 0, s, g);
+    hipLaunchKernelGGL((k_gemm_dot<T, SM, SN>),
+                       dim3((unsigned)((n_hi + BN - 1) / BN), (g.cnt + BM - 1) / BM, std::max(g.ksplit, 1)), dim3(256),
+                       0, s, g);
     return hipGetLastError();
 }
 
@@ -448,8 +567,23 @@ hipError_t sub_impl(const GemmArgs &g, hipStream_t s)
     constexpr int E = Mma<T>::E;
     constexpr int BM = 2 * SM * E, BN = 2 * SN * E;
     const int tiles = (int)((g.D + BN - 1) / BN);
-    hipLaunchKernelGGL((k_gemm_sub<T, SM, SN>), dim3(tiles, (g.cnt + BM - 1) / BM), dim3(256), 0, s, g);
+    const dim3 grid(tiles, (g.cnt + BM - 1) / BM, std::max(g.ksplit, 1));
+    if (g.cslices > 1)
+        hipLaunchKernelGGL((k_gemm_sub<T, SM, SN, kMaxSlices>), grid, dim3(256), 0, s, g);
+    else
+        hipLaunchKernelGGL((k_gemm_sub<T, SM, SN>), grid, dim3(256), 0, s, g);
     return hipGetLastError();
+}
+
+// Slices for a K extent of `nchunks` chunks when the output has `tiles` tiles: enough
+// to give about 256 workgroups, at most 16, every slice non-empty (one slice: no split).
+int slices_for(int64_t tiles, int64_t nchunks)
+{
+    if (tiles >= 128 || nchunks < 2)
+        return 1;
+    const int64_t want = std::min<int64_t>({kMaxSlices, nchunks, (256 + tiles - 1) / tiles});
+    const int64_t per = (nchunks + want - 1) / want;
+    return (int)((nchunks + per - 1) / per);
 }
 
 
@@ -500,9 +634,31 @@ hipError_t launch_gemm_sub_f32(const float *Vs, const DevState *st, const float 
 
 int gemm_sub_tiles_f64(int64_t D) { return (int)((D + 63) / 64); }
 
+SplitPlan gemm_split_plan_f64(int cnt, int64_t n_hi, int64_t D, int64_t ldc, size_t ws_doubles)
+{
+    SplitPlan p{1, 1};
+    if (cnt <= 0 || cnt > kSplitRows)
+        return p;
+    n_hi = std::max<int64_t>(n_hi, 1);
+    const int64_t mt = (cnt + 63) / 64;
+    p.kd = slices_for(((n_hi + 63) / 64) * mt, (D + KC - 1) / KC);
+    p.ks = slices_for(((D + 63) / 64) * mt, (n_hi + KC - 1) / KC);
+    auto need = [&]() { return (size_t)(p.kd > 1 ? p.kd : 0) * cnt * ldc + (size_t)(p.ks > 1 ? p.ks : 0) * cnt * D; };
+    while (need() > ws_doubles && p.ks > 1)
+        p.ks = std::max(1, p.ks / 2);
+    while (need() > ws_doubles && p.kd > 1)
+        p.kd = std::max(1, p.kd / 2);
+    return p;
+}
+
+size_t gemm_split_ws_doubles(int64_t D, int64_t ldc)
+{
+    return std::min<size_t>((size_t)8 << 20, (size_t)16 * kSplitRows * (size_t)(ldc + D));
+}
+
 hipError_t launch_gemm_dot_f64(const double *V, const DevState *st, const double *H, const int *rows,
                                const int *nrows, int cnt, int64_t D, int64_t n_hi, int64_t ldc, double *C,
-                               hipStream_t s)
+                               hipStream_t s, int ksplit)
 {
     if (cnt <= 0)
         return hipSuccess;
@@ -516,12 +672,14 @@ hipError_t launch_gemm_dot_f64(const double *V, const DevState *st, const double
     g.ldc = ldc;
     g.D = D;
     g.st = st;
+    g.ksplit = ksplit;
+    g.cslice = (int64_t)cnt * ldc;
     return dot_impl<double, 2, 2>(g, std::max<int64_t>(n_hi, 1), s);
 }
 
 hipError_t launch_gemm_sub_f64(const double *V, const DevState *st, double *H, const int *rows, const int *nrows,
                                const double *C, int64_t n_hi, int64_t ldc, int cnt, int64_t D, double *normpart,
-                               hipStream_t s)
+                               hipStream_t s, int cslices, int ksplit, double *P)
 {
     if (cnt <= 0)
         return hipSuccess;
@@ -537,7 +695,32 @@ hipError_t launch_gemm_sub_f64(const double *V, const DevState *st, double *H, c
     g.st = st;
     g.normpart = normpart;
     g.write_r = 1;
+    g.cslices = cslices;
+    g.cslice = (int64_t)cnt * ldc;
+    g.ksplit = ksplit > 1 && P ? ksplit : 1;
+    g.P = P;
+    g.pslice = (int64_t)cnt * D;
     return sub_impl<double, 2, 2>(g, s);
+}
+
+hipError_t launch_gemm_sub_finish_f64(const double *P, int ksplit, double *H, const int *rows, const int *nrows,
+                                      int cnt, int64_t D, const DevState *st, double *rho2, double *h2, hipStream_t s)
+{
+    if (cnt <= 0)
+        return hipSuccess;
+    GemmArgs g{};
+    g.H = H;
+    g.rows = rows;
+    g.nrows = nrows;
+    g.cnt = cnt;
+    g.D = D;
+    g.st = st;
+    g.write_r = 1;
+    g.ksplit = ksplit;
+    g.P = const_cast<double *>(P);
+    g.pslice = (int64_t)cnt * D;
+    hipLaunchKernelGGL(k_gemm_sub_finish, dim3(cnt), dim3(256), 0, s, g, rho2, h2);
+    return hipGetLastError();
 }
 
 hipError_t launch_norm_final(const double *normpart, const int *nrows, int cnt, int tiles, const DevState *st,

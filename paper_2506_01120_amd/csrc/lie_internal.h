@@ -134,6 +134,11 @@ struct GemmArgs {
     int64_t N_fixed;      // used when st is null
     double *normpart;     // residual: per (row, column tile) squared norms [rows][tiles][2]
     int write_r;          // residual: write R over H
+    int ksplit;           // K slices (grid.z); <= 1: no split
+    int cslices;          // residual: coefficient slices to add while loading C (<= 1: one)
+    int64_t cslice;       // element stride between coefficient slices
+    void *P;              // residual with ksplit > 1: partial products, ksplit slices of cnt x D
+    int64_t pslice;       // element stride between partial-product slices
 };
 
 // Candidate policies of the classification kernel (a2: squared residual, n2: squared norm).
@@ -174,12 +179,15 @@ struct ProjShape {
 };
 size_t proj_scratch_doubles(int64_t D, int cnt_max, int64_t cap);
 int project_split_k(int64_t D, int cnt, int64_t n_hi);
-// C[r][k] = <H_row(r), V_k>, leading dimension n_hi
+// Element-range slices of the coefficient pass below (1: none) that fit `ws_doubles`.
+int dot_slices_f64(ProjShape sh, size_t ws_doubles);
+// C[r][k] = <H_row(r), V_k>, leading dimension n_hi; with sd > 1, sd partial slices at a
+// stride of cnt * n_hi elements (needs sd * cnt * n_hi doubles at C)
 hipError_t launch_dot_f64(const double *V, const DevState *st, const double *H, const int *rows, const int *nrows,
-                          double *C, ProjShape sh, hipStream_t s);
-// split-K partial products of C V into `part`
+                          double *C, ProjShape sh, hipStream_t s, int sd = 1);
+// split-K partial products of C V into `part`; C holds `cs` slices (as written above)
 hipError_t launch_sub_f64(const double *V, const DevState *st, const double *C, const int *nrows, double *part,
-                          ProjShape sh, hipStream_t s);
+                          ProjShape sh, hipStream_t s, int cs = 1);
 // R = H - sum(part) written over H_row(r); squared norms of R and of the input into rho2[r], h2[r]
 hipError_t launch_reduce_f64(double *H, const int *rows, const int *nrows, double *part, const DevState *st,
                              double *rho2, double *h2, ProjShape sh, hipStream_t s);
@@ -241,13 +249,27 @@ hipError_t launch_gemm_dot_f32(const float *Vs, const DevState *st, const float 
                                int64_t ldc, float *C, int tile, hipStream_t s);
 hipError_t launch_gemm_sub_f32(const float *Vs, const DevState *st, const float *Hs, const float *C, int64_t n_hi,
                                int64_t ldc, int cnt, int64_t D, double *normpart, int tile, hipStream_t s);
+// Split of a small FP64 pass over K (coefficients: kd slices of cnt x ldc; residual:
+// ks slices of cnt x D partial products), sized to fit `ws_doubles` of workspace.
+constexpr int kSplitRows = 128;  // passes over more rows are never split
+struct SplitPlan {
+    int kd, ks;
+};
+SplitPlan gemm_split_plan_f64(int cnt, int64_t n_hi, int64_t D, int64_t ldc, size_t ws_doubles);
+size_t gemm_split_ws_doubles(int64_t D, int64_t ldc);
+// With ksplit > 1, C receives ksplit slices at a stride of cnt * ldc elements.
 hipError_t launch_gemm_dot_f64(const double *V, const DevState *st, const double *H, const int *rows,
                                const int *nrows, int cnt, int64_t D, int64_t n_hi, int64_t ldc, double *C,
-                               hipStream_t s);
-// R written over H_row(m)
+                               hipStream_t s, int ksplit = 1);
+// R written over H_row(m), per-tile norms into normpart.  C holds `cslices` slices (summed
+// on load).  With ksplit > 1 the pass stores ksplit slices of partial products in P
+// (stride cnt * D) instead, and launch_gemm_sub_finish_f64 completes it.
 hipError_t launch_gemm_sub_f64(const double *V, const DevState *st, double *H, const int *rows, const int *nrows,
                                const double *C, int64_t n_hi, int64_t ldc, int cnt, int64_t D, double *normpart,
-                               hipStream_t s);
+                               hipStream_t s, int cslices = 1, int ksplit = 1, double *P = nullptr);
+// R = H - sum of the P slices written over H_row(m); rho2[m] = ||R||^2, h2[m] (if non-null) = ||H||^2
+hipError_t launch_gemm_sub_finish_f64(const double *P, int ksplit, double *H, const int *rows, const int *nrows,
+                                      int cnt, int64_t D, const DevState *st, double *rho2, double *h2, hipStream_t s);
 // rho2[m] = sum of tile partials of ||R||^2, h2[m] (if non-null) of ||H||^2
 hipError_t launch_norm_final(const double *normpart, const int *nrows, int cnt, int tiles, const DevState *st,
                              double *rho2, double *h2, hipStream_t s);
