@@ -216,6 +216,174 @@ __device__ void comm_f64_global_body(const CommArgs &A, int bx, int c)
     }
 }
 
+typedef double f64x4_t __attribute__((ext_vector_type(4)));
+
+// ---- the bracket on the matrix cores (FP64 16x16x4 MFMA)
+// P = (Ar + i Ai)(Br + i Bi) as four real products.  Each MFMA operand is gathered
+// straight from the packed rows: entry (i, k) of Ar and of Ai both come from the two
+// packed values p[i][k] and p[k][i], so one pair of loads serves both (no unpacking
+// pass through LDS).  Lane l supplies A[l%16][k0 + l/16] and B[k0 + l/16][l%16]; result
+// register r of lane l is P[4r + l/16][l%16].  P goes through LDS only to be read
+// transposed for the packed output sqrt(d/2)(P - P^H).
+
+// Entry (i, k) of Ar and Ai (zero outside d x d) from the two packed values x = p[i][k]
+// and y = p[k][i].
+struct CommRaw {
+    double x, y;
+};
+__device__ inline void comm_frag(CommRaw v, int d, int i, int k, double &ar, double &ai)
+{
+    const bool in = i < d && k < d;
+    ar = !in || i == k ? 0.0 : (i < k ? v.x : -v.y);
+    ai = !in ? 0.0 : (i < k ? v.y : (i > k ? v.x : 1.4142135623730951 * v.x));
+}
+
+// Packed output element e of the bracket from P = Pr + i Pi held in LDS (row stride ld).
+__device__ inline double comm_out(const double *Pr, const double *Pi, int ld, int d, int e)
+{
+    const int i = e / d, j = e % d;
+    if (i < j)
+        return sqrt(0.5 * d) * (Pr[i * ld + j] - Pr[j * ld + i]);
+    if (i > j)
+        return sqrt(0.5 * d) * (Pi[j * ld + i] + Pi[i * ld + j]);
+    return sqrt((double)d) * Pi[i * ld + i];
+}
+
+// d <= 16: one wave per candidate (four per workgroup).  The wave copies its two packed
+// operands into its LDS tile with coalesced loads (row stride 17), gathers the MFMA
+// fragments from there, and reuses the tile for P.
+__global__ void __launch_bounds__(kThreads) k_comm_f64_mfma16(CommArgs A)
+{
+    __shared__ double Pbuf[4][2][16 * 17];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int c = blockIdx.x * 4 + w;
+    const DevState *st = A.st;
+    if (c >= (A.ncnt ? *A.ncnt : A.cnt) || (st && (st->done | st->numeric_error | st->full)))
+        return;
+    const double *V = static_cast<const double *>(A.V);
+    const int d = A.d;
+    const int64_t D = (int64_t)d * d;
+    int64_t l, m;
+    decode_pair(A.pair_list ? A.pair_list[c] : (A.dp0 ? *A.dp0 : A.p0) + c, l, m);
+    double *Sa = Pbuf[w][0], *Sb = Pbuf[w][1];
+    {
+        const double *pa = V + l * D, *pb = V + m * D;
+        for (int e = lane; e < D; e += 64) {
+            const int i = e / d, k = e % d;
+            Sa[i * 17 + k] = pa[e];
+            Sb[i * 17 + k] = pb[e];
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    const int lr = lane & 15, lk = lane >> 4;
+    f64x4_t pr = {0.0, 0.0, 0.0, 0.0}, pi = {0.0, 0.0, 0.0, 0.0};
+    CommRaw ra[4], rb[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const int k = 4 * s + lk;
+        const bool ina = lr < d && k < d;
+        ra[s] = ina ? CommRaw{Sa[lr * 17 + k], Sa[k * 17 + lr]} : CommRaw{0.0, 0.0};
+        rb[s] = ina ? CommRaw{Sb[k * 17 + lr], Sb[lr * 17 + k]} : CommRaw{0.0, 0.0};
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");  // the tile is read; P may overwrite it
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const int k0 = 4 * s;
+        double ar, ai, br, bi;
+        comm_frag(ra[s], d, lr, k0 + lk, ar, ai);
+        comm_frag(rb[s], d, k0 + lk, lr, br, bi);
+        pr = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, br, pr, 0, 0, 0);
+        pr = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai, bi, pr, 0, 0, 0);
+        pi = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, bi, pi, 0, 0, 0);
+        pi = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, br, pi, 0, 0, 0);
+    }
+    double *Pr = Pbuf[w][0], *Pi = Pbuf[w][1];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        Pr[(4 * r + lk) * 17 + lr] = pr[r];
+        Pi[(4 * r + lk) * 17 + lr] = pi[r];
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");  // the wave's own LDS writes, read across lanes
+    double *out = static_cast<double *>(A.H) + (int64_t)c * D;
+    for (int e = lane; e < D; e += 64)
+        out[e] = comm_out(Pr, Pi, 17, d, e);
+}
+
+// 16 < d <= 16 T: one workgroup per candidate.  The two packed operands are first copied
+// into LDS with coalesced loads (row stride d + 1, so that a fragment gather down a
+// column does not hit one bank), and the MFMA fragments are gathered from there; wave w
+// owns column block J = w % T and row blocks I = w / T, w / T + 4 / T, ...
+// Dynamic LDS: max(2 d (d + 1), 2 x 16T x (16T + 1)) doubles (operands, then P).
+template <int T>
+__global__ void __launch_bounds__(kThreads) k_comm_f64_mfma(CommArgs A)
+{
+    extern __shared__ double Pl[];
+    constexpr int NI = T * T / 4;  // row blocks per wave
+    constexpr int ld = 16 * T + 1;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int c = blockIdx.x;
+    const DevState *st = A.st;
+    if (c >= (A.ncnt ? *A.ncnt : A.cnt) || (st && (st->done | st->numeric_error | st->full)))
+        return;
+    const double *V = static_cast<const double *>(A.V);
+    const int d = A.d;
+    const int64_t D = (int64_t)d * d;
+    int64_t l, m;
+    decode_pair(A.pair_list ? A.pair_list[c] : (A.dp0 ? *A.dp0 : A.p0) + c, l, m);
+    const int lo = d + 1;  // operand row stride in LDS
+    double *Sa = Pl, *Sb = Pl + d * lo;
+    {
+        const double *pa = V + l * D, *pb = V + m * D;
+        for (int64_t e = threadIdx.x; e < D; e += blockDim.x) {
+            const int i = (int)(e / d), k = (int)(e % d);
+            Sa[i * lo + k] = pa[e];
+            Sb[i * lo + k] = pb[e];
+        }
+    }
+    __syncthreads();
+    const int lr = lane & 15, lk = lane >> 4;
+    const int J = w % T, I0 = w / T;
+    f64x4_t pr[NI], pi[NI];
+#pragma unroll
+    for (int q = 0; q < NI; ++q)
+        pr[q] = pi[q] = f64x4_t{0.0, 0.0, 0.0, 0.0};
+    auto frag = [&](const double *S, int i, int k, double &ar, double &ai) {
+        const bool in = i < d && k < d;
+        const int ic = in ? i : 0, kc = in ? k : 0;
+        comm_frag(CommRaw{S[ic * lo + kc], S[kc * lo + ic]}, d, i, k, ar, ai);
+    };
+#pragma unroll 4
+    for (int k0 = 0; k0 < 16 * T; k0 += 4) {
+        const int k = k0 + lk;
+        double br, bi;
+        frag(Sb, k, 16 * J + lr, br, bi);
+#pragma unroll
+        for (int q = 0; q < NI; ++q) {
+            double ar, ai;
+            frag(Sa, 16 * (I0 + q * (4 / T)) + lr, k, ar, ai);
+            pr[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, br, pr[q], 0, 0, 0);
+            pr[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai, bi, pr[q], 0, 0, 0);
+            pi[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, bi, pi[q], 0, 0, 0);
+            pi[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, br, pi[q], 0, 0, 0);
+        }
+    }
+    __syncthreads();  // the operands are consumed; P takes their place
+    double *Pr = Pl, *Pi = Pl + 16 * T * ld;
+#pragma unroll
+    for (int q = 0; q < NI; ++q) {
+        const int I = I0 + q * (4 / T);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            Pr[(16 * I + 4 * r + lk) * ld + 16 * J + lr] = pr[q][r];
+            Pi[(16 * I + 4 * r + lk) * ld + 16 * J + lr] = pi[q][r];
+        }
+    }
+    __syncthreads();
+    double *out = static_cast<double *>(A.H) + (int64_t)c * D;
+    for (int e = threadIdx.x; e < D; e += blockDim.x)
+        out[e] = comm_out(Pr, Pi, ld, d, e);
+}
+
 __global__ void __launch_bounds__(kThreads) k_comm_f64_lds(CommArgs a) { comm_f64_lds_body(a, blockIdx.x); }
 __global__ void __launch_bounds__(kThreads) k_comm_f64_global(CommArgs a)
 {
@@ -488,7 +656,6 @@ __device__ inline void atomic_min_pos(double *addr, double v)
     atomicMin(reinterpret_cast<unsigned long long *>(addr), (unsigned long long)__double_as_longlong(v));
 }
 
-typedef double f64x4_t __attribute__((ext_vector_type(4)));
 
 // One 16 x 16 FP64 tile of A B^T over a K-extent of D: lane l supplies row l%16 of
 // A through pa and of B through pb (nullptr: a zero row).  Loads are issued 16 at a
@@ -1546,6 +1713,29 @@ hipError_t launch_comm_f64(const double *V, int d, int64_t p0, const int64_t *pa
             (void)hipGetLastError();  // clear the failed request; the fallback kernel is used
     }
     CommArgs a{V, d, p0, pair_list, dp0, ncnt, cnt, st, H, nullptr};
+    if (d <= 16) {
+        hipLaunchKernelGGL(k_comm_f64_mfma16, dim3((unsigned)((cnt + 3) / 4)), dim3(kThreads), 0, s, a);
+        return hipGetLastError();
+    }
+    if (d <= 32) {
+        hipLaunchKernelGGL(k_comm_f64_mfma<2>, dim3(cnt), dim3(kThreads), (size_t)2 * 32 * 33 * sizeof(double), s, a);
+        return hipGetLastError();
+    }
+    if (d <= 64) {
+        static bool granted64 = false;
+        const size_t l64 = (size_t)2 * 64 * 65 * sizeof(double);
+        if (!granted64) {
+            if (hipFuncSetAttribute((const void *)k_comm_f64_mfma<4>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)l64) == hipSuccess)
+                granted64 = true;
+            else
+                (void)hipGetLastError();  // the LDS kernel below is used instead
+        }
+        if (granted64) {
+            hipLaunchKernelGGL(k_comm_f64_mfma<4>, dim3(cnt), dim3(kThreads), l64, s, a);
+            return hipGetLastError();
+        }
+    }
     if (d <= 64 && lds <= granted) {
         hipLaunchKernelGGL(k_comm_f64_lds, dim3(cnt), dim3(kThreads), lds, s, a);
     } else {

@@ -131,6 +131,193 @@ __device__ void comm_f32_mfma_body(const CommArgs &A, int c)
         hs2[c] = (double)red[0] + red[1] + red[2] + red[3];
 }
 
+// ---- gathered variant (d <= 64): the two packed operands are copied into LDS with
+// coalesced loads (row stride d + 1 against bank conflicts) and each MFMA operand is
+// gathered from there -- entry (i, k) of Ar and Ai both come from p[i][k] and p[k][i],
+// so no unpacked copies are written.  P then reuses the LDS to be read transposed.
+// FP32 16x16x4: lane l supplies A[l%16][k0 + l/16] and B[k0 + l/16][l%16]; result
+// register r of lane l is P[4(l/16) + r][l%16].
+struct RawF {
+    float x, y;
+};
+// (x, y) = (S[i][k], S[k][i]) of a staged operand with row stride ls (zero outside d x d).
+__device__ inline RawF raw_load(const float *S, int ls, int d, int i, int k)
+{
+    const bool in = i < d && k < d;
+    const int ic = in ? i : 0, kc = in ? k : 0;
+    return RawF{S[ic * ls + kc], S[kc * ls + ic]};
+}
+__device__ inline void raw_frag(RawF v, int d, int i, int k, float &ar, float &ai)
+{
+    const bool in = i < d && k < d;
+    ar = !in || i == k ? 0.f : (i < k ? v.x : -v.y);
+    ai = !in ? 0.f : (i < k ? v.y : (i > k ? v.x : 1.41421356237309515f * v.x));
+}
+
+// Output element e of the packed bracket from P (row stride ld) in LDS.
+__device__ inline float bracket_out(const float *Pr, const float *Pi, int ld, int d, int e, float so, float sd)
+{
+    const int i = e / d, j = e % d;
+    if (i < j)
+        return so * (Pr[i * ld + j] - Pr[j * ld + i]);
+    if (i > j)
+        return so * (Pi[j * ld + i] + Pi[i * ld + j]);
+    return sd * Pi[i * ld + i];
+}
+
+// d <= 16: one wave per candidate, four candidates per workgroup.
+__global__ void __launch_bounds__(kThreads) k_comm_f32_reg16(CommArgs A)
+{
+    __shared__ float Pbuf[4][2][16 * 17];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int c = blockIdx.x * 4 + w;
+    if (c >= A.cnt || aborted(A.st))
+        return;
+    const float *Vs = static_cast<const float *>(A.V);
+    const int d = A.d;
+    const int64_t D = (int64_t)d * d;
+    int64_t l, m;
+    decode_pair((A.dp0 ? *A.dp0 : A.p0) + c, l, m);
+    float *Sa = Pbuf[w][0], *Sb = Pbuf[w][1];
+    {
+        const float *pa = Vs + l * D, *pb = Vs + m * D;
+        for (int e = lane; e < D; e += 64) {
+            const int i = e / d, k = e % d;
+            Sa[i * 17 + k] = pa[e];
+            Sb[i * 17 + k] = pb[e];
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    const int lr = lane & 15, lk = lane >> 4;
+    RawF ra[4], rb[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        ra[s] = raw_load(Sa, 17, d, lr, 4 * s + lk);
+        rb[s] = raw_load(Sb, 17, d, 4 * s + lk, lr);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");  // the tile is read; P may overwrite it
+    f32x4 pr = {0.f, 0.f, 0.f, 0.f}, pi = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        float ar, ai, br, bi;
+        raw_frag(ra[s], d, lr, 4 * s + lk, ar, ai);
+        raw_frag(rb[s], d, 4 * s + lk, lr, br, bi);
+        pr = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, br, pr, 0, 0, 0);
+        pr = __builtin_amdgcn_mfma_f32_16x16x4f32(-ai, bi, pr, 0, 0, 0);
+        pi = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, bi, pi, 0, 0, 0);
+        pi = __builtin_amdgcn_mfma_f32_16x16x4f32(ai, br, pi, 0, 0, 0);
+    }
+    float *Pr = Pbuf[w][0], *Pi = Pbuf[w][1];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        Pr[(4 * lk + r) * 17 + lr] = pr[r];
+        Pi[(4 * lk + r) * 17 + lr] = pi[r];
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");  // the wave's own LDS writes, read across lanes
+    const float so = sqrtf(0.5f * d), sd = sqrtf((float)d);
+    float *out = static_cast<float *>(A.H) + (int64_t)c * D;
+    float sq = 0.f;
+    for (int e = lane; e < D; e += 64) {
+        const float v = bracket_out(Pr, Pi, 17, d, e, so, sd);
+        out[e] = v;
+        sq += v * v;
+    }
+    sq = wave_sum_f(sq);
+    if (lane == 0)
+        A.hs2[c] = (double)sq;
+}
+
+// 16 < d <= 16 T: one workgroup per candidate; wave w owns column block J = w % T and
+// row blocks I = w / T, w / T + 4 / T, ...  Dynamic LDS: 2 x 16T x (16T + 1) floats
+// (the operands, then P).
+template <int T>
+__global__ void __launch_bounds__(kThreads) k_comm_f32_reg(CommArgs A)
+{
+    extern __shared__ float Pl[];
+    __shared__ float red[4];
+    constexpr int NI = T * T / 4;
+    constexpr int ld = 16 * T + 1;
+    constexpr int G = T == 2 ? 8 : 4;  // k-steps per load group
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int c = blockIdx.x;
+    if (c >= A.cnt || aborted(A.st))
+        return;
+    const float *Vs = static_cast<const float *>(A.V);
+    const int d = A.d;
+    const int64_t D = (int64_t)d * d;
+    int64_t l, m;
+    decode_pair((A.dp0 ? *A.dp0 : A.p0) + c, l, m);
+    const int lo = d + 1;
+    float *Sa = Pl, *Sb = Pl + d * lo;
+    {
+        const float *pa = Vs + l * D, *pb = Vs + m * D;
+        for (int64_t e = threadIdx.x; e < D; e += blockDim.x) {
+            const int i = (int)(e / d), k = (int)(e % d);
+            Sa[i * lo + k] = pa[e];
+            Sb[i * lo + k] = pb[e];
+        }
+    }
+    __syncthreads();
+    const int lr = lane & 15, lk = lane >> 4;
+    const int J = w % T, I0 = w / T;
+    f32x4 pr[NI], pi[NI];
+#pragma unroll
+    for (int q = 0; q < NI; ++q)
+        pr[q] = pi[q] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int g0 = 0; g0 < 4 * T; g0 += G) {
+        RawF ra[NI][G], rb[G];
+#pragma unroll
+        for (int s = 0; s < G; ++s) {
+            const int k = 4 * (g0 + s) + lk;
+            rb[s] = raw_load(Sb, lo, d, k, 16 * J + lr);
+#pragma unroll
+            for (int q = 0; q < NI; ++q)
+                ra[q][s] = raw_load(Sa, lo, d, 16 * (I0 + q * (4 / T)) + lr, k);
+        }
+#pragma unroll
+        for (int s = 0; s < G; ++s) {
+            const int k = 4 * (g0 + s) + lk;
+            float br, bi;
+            raw_frag(rb[s], d, k, 16 * J + lr, br, bi);
+#pragma unroll
+            for (int q = 0; q < NI; ++q) {
+                float ar, ai;
+                raw_frag(ra[q][s], d, 16 * (I0 + q * (4 / T)) + lr, k, ar, ai);
+                pr[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, br, pr[q], 0, 0, 0);
+                pr[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(-ai, bi, pr[q], 0, 0, 0);
+                pi[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, bi, pi[q], 0, 0, 0);
+                pi[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai, br, pi[q], 0, 0, 0);
+            }
+        }
+    }
+    __syncthreads();  // the operands are consumed; P takes their place
+    float *Pr = Pl, *Pi = Pl + 16 * T * ld;
+#pragma unroll
+    for (int q = 0; q < NI; ++q) {
+        const int I = I0 + q * (4 / T);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            Pr[(16 * I + 4 * lk + r) * ld + 16 * J + lr] = pr[q][r];
+            Pi[(16 * I + 4 * lk + r) * ld + 16 * J + lr] = pi[q][r];
+        }
+    }
+    __syncthreads();
+    const float so = sqrtf(0.5f * d), sd = sqrtf((float)d);
+    float *out = static_cast<float *>(A.H) + (int64_t)c * D;
+    float sq = 0.f;
+    for (int e = threadIdx.x; e < D; e += blockDim.x) {
+        const float v = bracket_out(Pr, Pi, ld, d, e, so, sd);
+        out[e] = v;
+        sq += v * v;
+    }
+    sq = wave_sum_f(sq);
+    if (lane == 0)
+        red[w] = sq;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        A.hs2[c] = (double)red[0] + red[1] + red[2] + red[3];
+}
+
 // FP32 bracket straight from global memory, for d beyond the LDS kernel.
 __device__ void comm_f32_global_body(const CommArgs &A, int bx, int c)
 {
@@ -333,6 +520,18 @@ hipError_t launch_comm_f32(const float *Vs, int d, int64_t p0, int cnt, const De
             (void)hipGetLastError();  // clear the failed request; the fallback kernel is used
     }
     CommArgs a{Vs, d, p0, nullptr, dp0, nullptr, cnt, st, Hs, hs2};
+    if (d <= 16) {
+        hipLaunchKernelGGL(k_comm_f32_reg16, dim3((unsigned)((cnt + 3) / 4)), dim3(kThreads), 0, s, a);
+        return hipGetLastError();
+    }
+    if (d <= 32) {
+        hipLaunchKernelGGL(k_comm_f32_reg<2>, dim3(cnt), dim3(kThreads), (size_t)2 * 32 * 33 * sizeof(float), s, a);
+        return hipGetLastError();
+    }
+    if (d <= 64) {
+        hipLaunchKernelGGL(k_comm_f32_reg<4>, dim3(cnt), dim3(kThreads), (size_t)2 * 64 * 65 * sizeof(float), s, a);
+        return hipGetLastError();
+    }
     if (lds <= granted) {
         hipLaunchKernelGGL(k_comm_f32_mfma, dim3(cnt), dim3(kThreads), lds, s, a);
     } else {
