@@ -694,16 +694,15 @@ __device__ inline double lane_bcast(double x, int src)
 __device__ inline int lane_bcast_int(int x, int src) { return __builtin_amdgcn_readlane(x, __builtin_amdgcn_readfirstlane(src)); }
 
 // Row stride of the small Gram matrix in LDS: odd, so that a column read by
-// 64 lanes spreads over the banks, and at least 17 (the same array later holds
-// 16 rows of per-wave partial sums).
+// 64 lanes spreads over the banks, and at least 17.
 __host__ __device__ constexpr int gram_ld(int nsv) { return nsv < 17 ? 17 : (nsv | 1); }
 
-// LDS (in doubles) of the block Cholesky-QR pass over nsv survivors with nw waves:
-// Gram / factor / inverse (nsv x gram_ld) | pivots | verified norms | two index
-// lists (ints) | per-wave norm partials (nw x nsv).
+// LDS (in doubles) of the block Cholesky-QR pass over nsv survivors with nw >= 16 waves:
+// Gram / factor / inverse (nsv x gram_ld) | pivots | verified norms | two index lists
+// (ints) | panel products of the inverse (16 x nsv), then per-wave norm partials (nw x nsv).
 __host__ __device__ constexpr int64_t bqr_lds(int nsv, int nw)
 {
-    return 2 * (int64_t)nsv * gram_ld(nsv) + 4 * (int64_t)nsv + (int64_t)nw * nsv;
+    return (int64_t)nsv * gram_ld(nsv) + 4 * (int64_t)nsv + (int64_t)nw * nsv;
 }
 
 struct BqrOut {
@@ -737,8 +736,7 @@ __device__ __forceinline__ BqrOut block_qr(const AcceptArgs &a, int nsv, int64_t
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
     double *Gm = lds, *piv = Gm + (int64_t)nsv * ld, *vn = piv + nsv;
     int *acc_idx = reinterpret_cast<int *>(vn + nsv), *rej_idx = acc_idx + nsv, *hrow = rej_idx + nsv;
-    double *part = vn + 3 * nsv;
-    double *Gc = part + (int64_t)nw * nsv;  // copy of G for the verification coefficients
+    double *part = vn + 3 * nsv;  // panel products of the inverse, then per-wave norm partials
     __shared__ int s_u, s_nrej, s_stop, s_resume, s_uk;
     for (int r = threadIdx.x; r < nsv; r += blockDim.x) {
         const int sr = a.rho2 && a.keep ? a.keep[r] : r;  // the caller's survivor order (see sv_of)
@@ -799,7 +797,7 @@ __device__ __forceinline__ BqrOut block_qr(const AcceptArgs &a, int nsv, int64_t
             for (int r = 0; r < 4; ++r) {
                 const int i = tI * 16 + 4 * r + (lane >> 4), j = tJ * 16 + (lane & 15);
                 if (i < nsv && j <= i)
-                    Gm[i * ld + j] = Gc[i * ld + j] = acc[r];
+                    Gm[i * ld + j] = acc[r];
             }
         }
     } else if (w < ntile) {
@@ -809,7 +807,7 @@ __device__ __forceinline__ BqrOut block_qr(const AcceptArgs &a, int nsv, int64_t
         for (int r = 0; r < 4; ++r) {
             const int i = tI * 16 + 4 * r + (lane >> 4), j = tJ * 16 + (lane & 15);
             if (i < nsv && j <= i)
-                Gm[i * ld + j] = Gc[i * ld + j] = acc[r];
+                Gm[i * ld + j] = acc[r];
         }
     }
     __syncthreads();
@@ -1013,37 +1011,11 @@ __device__ __forceinline__ BqrOut block_qr(const AcceptArgs &a, int nsv, int64_t
         }
     }
     __syncthreads();  // Q is complete (global and LDS); T is no longer needed
-    // 5. explicit residual norms of the provisional rejections: C = R_rej Q^T (masked to the
-    // accepted rows that precede each rejected row), then ||R_rej - C Q|| without storing it
-    const int ldc = u > 0 ? u : 1;
-    double *C = part;  // nrej x u <= (nsv/2)^2 <= 16 nsv
+    // 5. explicit residual norms of the provisional rejections, ||R_rej - C Q|| without storing
+    // it.  The coefficients need no pass of their own: for a row i that was not accepted, the
+    // factor entry L[i][c] of every accepted c before it (acc_idx[c] < i) is <R_i, Q_c>, and
+    // the recurrence left it in row i of the array (the inverse overwrote accepted rows only).
     auto qrow = [&](int c) -> const double * { return c < cslots ? cache2 + (int64_t)c * D : a.V + (N0 + c) * D; };
-    if (nrej > 0 && u > 0) {
-        // <R_rej, Q_c> = sum_{k <= c} T[c][k] G[rej][acc_k], from the copy of G (T is row
-        // acc_idx[c] of Gm, columns k <= c); one 16 x 16 tile of C per wave
-        const int RT = (nrej + 15) / 16, CT = (u + 15) / 16;
-        auto gsym = [&](int p, int q) -> double { return p >= q ? Gc[p * ld + q] : Gc[q * ld + p]; };
-        for (int t = w; t < RT * CT; t += nw) {
-            const int I = t / CT, J = t % CT;
-            const int ir = I * 16 + (lane & 15), jq = J * 16 + (lane & 15);
-            const int rrow = ir < nrej ? rej_idx[ir] : 0;
-            const double *trow = jq < u ? Gm + (int64_t)acc_idx[jq] * ld : nullptr;
-            f64x4_t acc = {0.0, 0.0, 0.0, 0.0};
-            for (int k0 = 0; k0 < u; k0 += 4) {
-                const int k = k0 + (lane >> 4);
-                const double av = (ir < nrej && k < u) ? gsym(rrow, acc_idx[k]) : 0.0;
-                const double bv = (trow && k <= jq) ? trow[k] : 0.0;
-                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
-            }
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int i = I * 16 + 4 * r + (lane >> 4), c = J * 16 + (lane & 15);
-                if (i < nrej && c < u)
-                    C[i * ldc + c] = acc_idx[c] < rej_idx[i] ? acc[r] : 0.0;
-            }
-        }
-        __syncthreads();
-    }
     if (nrej > 0) {
         // wave w takes the column tiles J = w, w + nw, ... in a fixed order (the Q values of a
         // column tile are loaded once for all rejected rows); the per-wave partial sums are
@@ -1072,7 +1044,8 @@ __device__ __forceinline__ BqrOut block_qr(const AcceptArgs &a, int nsv, int64_t
                     for (int q = 0; q < 16; ++q) {
                         if (4 * q < u) {
                             const int k = 4 * q + (lane >> 4);
-                            const double av = (ir < nrej && k < u) ? -C[ir * ldc + k] : 0.0;
+                            const double av =
+                                (ir < nrej && k < u && acc_idx[k] < rej_idx[ir]) ? -Gm[rej_idx[ir] * ld + k] : 0.0;
                             acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bq[q], acc, 0, 0, 0);
                         }
                     }
@@ -1091,14 +1064,14 @@ __device__ __forceinline__ BqrOut block_qr(const AcceptArgs &a, int nsv, int64_t
                     v += __shfl_xor(v, off, 64);
                 const int i = I * 16 + 4 * r + (lane >> 4);
                 if ((lane & 15) == 0 && i < nrej)
-                    Gc[w * nsv + i] = v;  // the Gram copy is no longer needed
+                    part[w * nsv + i] = v;
             }
         }
         __syncthreads();
         for (int i = threadIdx.x; i < nrej; i += blockDim.x) {
             double t = 0.0;
             for (int q = 0; q < nw; ++q)
-                t += Gc[q * nsv + i];
+                t += part[q * nsv + i];
             vn[i] = sqrt(t);
         }
         __syncthreads();
