@@ -315,13 +315,12 @@ __global__ void __launch_bounds__(kThreads) k_comm_f64_mfma16(CommArgs A)
 // owns column block J = w % T and row blocks I = w / T, w / T + 4 / T, ...
 // Dynamic LDS: max(2 d (d + 1), 2 x 16T x (16T + 1)) doubles (operands, then P).
 template <int T>
-__global__ void __launch_bounds__(kThreads) k_comm_f64_mfma(CommArgs A)
+__device__ void comm_f64_mfma_body(const CommArgs &A, int c)
 {
     extern __shared__ double Pl[];
     constexpr int NI = T * T / 4;  // row blocks per wave
     constexpr int ld = 16 * T + 1;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int c = blockIdx.x;
     const DevState *st = A.st;
     if (c >= (A.ncnt ? *A.ncnt : A.cnt) || (st && (st->done | st->numeric_error | st->full)))
         return;
@@ -382,6 +381,21 @@ __global__ void __launch_bounds__(kThreads) k_comm_f64_mfma(CommArgs A)
     double *out = static_cast<double *>(A.H) + (int64_t)c * D;
     for (int e = threadIdx.x; e < D; e += blockDim.x)
         out[e] = comm_out(Pr, Pi, ld, d, e);
+}
+
+template <int T>
+__global__ void __launch_bounds__(kThreads) k_comm_f64_mfma(CommArgs A)
+{
+    comm_f64_mfma_body<T>(A, blockIdx.x);
+}
+
+// Grouped form: one workgroup per candidate of any problem with d <= 16 T.
+template <int T>
+__global__ void __launch_bounds__(kThreads) k_comm_f64_mfma_b(Batch b)
+{
+    const int p = batch_find(b.start, b.nprob, blockIdx.x);
+    const CommArgs a = static_cast<const CommArgs *>(b.args)[p];
+    comm_f64_mfma_body<T>(a, blockIdx.x - b.start[p]);
 }
 
 __global__ void __launch_bounds__(kThreads) k_comm_f64_lds(CommArgs a) { comm_f64_lds_body(a, blockIdx.x); }
@@ -1735,6 +1749,26 @@ hipError_t launch_comm_f64_batched(const Batch &b, bool lds_variant, int dmax, h
 {
     if (b.total <= 0)
         return hipSuccess;
+    if (lds_variant && dmax <= 32) {
+        hipLaunchKernelGGL(k_comm_f64_mfma_b<2>, dim3(b.total), dim3(kThreads), (size_t)2 * 32 * 33 * sizeof(double), s,
+                           b);
+        return hipGetLastError();
+    }
+    if (lds_variant && dmax <= 64) {
+        static bool granted64 = false;
+        const size_t l64 = (size_t)2 * 64 * 65 * sizeof(double);
+        if (!granted64) {
+            if (hipFuncSetAttribute((const void *)k_comm_f64_mfma_b<4>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)l64) == hipSuccess)
+                granted64 = true;
+            else
+                (void)hipGetLastError();  // the LDS kernel below is used instead
+        }
+        if (granted64) {
+            hipLaunchKernelGGL(k_comm_f64_mfma_b<4>, dim3(b.total), dim3(kThreads), l64, s, b);
+            return hipGetLastError();
+        }
+    }
     if (lds_variant) {
         const size_t lds = (size_t)4 * dmax * (dmax + 1) * sizeof(double);
         static size_t granted = 65536;

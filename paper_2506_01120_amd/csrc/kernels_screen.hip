@@ -231,7 +231,7 @@ __global__ void __launch_bounds__(kThreads) k_comm_f32_reg16(CommArgs A)
 // row blocks I = w / T, w / T + 4 / T, ...  Dynamic LDS: 2 x 16T x (16T + 1) floats
 // (the operands, then P).
 template <int T>
-__global__ void __launch_bounds__(kThreads) k_comm_f32_reg(CommArgs A)
+__device__ void comm_f32_reg_body(const CommArgs &A, int c)
 {
     extern __shared__ float Pl[];
     __shared__ float red[4];
@@ -239,7 +239,6 @@ __global__ void __launch_bounds__(kThreads) k_comm_f32_reg(CommArgs A)
     constexpr int ld = 16 * T + 1;
     constexpr int G = T == 2 ? 8 : 4;  // k-steps per load group
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int c = blockIdx.x;
     if (c >= A.cnt || aborted(A.st))
         return;
     const float *Vs = static_cast<const float *>(A.V);
@@ -316,6 +315,21 @@ __global__ void __launch_bounds__(kThreads) k_comm_f32_reg(CommArgs A)
     __syncthreads();
     if (threadIdx.x == 0)
         A.hs2[c] = (double)red[0] + red[1] + red[2] + red[3];
+}
+
+template <int T>
+__global__ void __launch_bounds__(kThreads) k_comm_f32_reg(CommArgs A)
+{
+    comm_f32_reg_body<T>(A, blockIdx.x);
+}
+
+// Grouped form: one workgroup per candidate of any problem with d <= 16 T.
+template <int T>
+__global__ void __launch_bounds__(kThreads) k_comm_f32_reg_b(Batch b)
+{
+    const int p = batch_find(b.start, b.nprob, blockIdx.x);
+    const CommArgs a = static_cast<const CommArgs *>(b.args)[p];
+    comm_f32_reg_body<T>(a, blockIdx.x - b.start[p]);
 }
 
 // FP32 bracket straight from global memory, for d beyond the LDS kernel.
@@ -557,7 +571,13 @@ hipError_t launch_comm_f32_batched(const Batch &b, bool lds_variant, int dmax, h
 {
     if (b.total <= 0)
         return hipSuccess;
-    if (lds_variant) {
+    if (lds_variant && dmax <= 32) {
+        hipLaunchKernelGGL(k_comm_f32_reg_b<2>, dim3(b.total), dim3(kThreads), (size_t)2 * 32 * 33 * sizeof(float), s,
+                           b);
+    } else if (lds_variant && dmax <= 64) {
+        hipLaunchKernelGGL(k_comm_f32_reg_b<4>, dim3(b.total), dim3(kThreads), (size_t)2 * 64 * 65 * sizeof(float), s,
+                           b);
+    } else if (lds_variant) {
         const int dp = (dmax + 15) & ~15;
         const size_t lds = (size_t)6 * dp * (dp + 1) * sizeof(float);
         static size_t granted = 65536;
