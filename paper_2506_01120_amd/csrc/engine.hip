@@ -1633,7 +1633,7 @@ struct lie_closure_batch {
     }
 
     // A recorded grouped launch of the round being built.
-    enum Kind { COMM_F64, COMM_F32, ROWNORM_F32, DOT_F64, DOT_F32, DOT_BF, SUB_F64, SUB_F32, SUB_BF, NORM, CLASSIFY,
+    enum Kind { COMM_F64, COMM_F32, DOT_F64, DOT_F32, DOT_BF, SUB_F64, SUB_F32, SUB_BF, NORM, CLASSIFY,
                 ACCEPT };
     struct Rec {
         Kind kind;
@@ -1676,8 +1676,7 @@ struct lie_closure_batch {
                 lds.add(a, it.cnt, 1);
                 dmax = std::max(dmax, h->d);
             } else {
-                const int tiles = (int)((h->D + 255) / 256);
-                glob.add(a, tiles * it.cnt, tiles);
+                glob.add(a, it.cnt, 1);  // one workgroup per candidate (tile-pair kernel)
             }
             if (!from_survivors)
                 fl += 8.0 * h->d * h->d * (double)h->d * it.cnt;
@@ -1806,7 +1805,7 @@ struct lie_closure_batch {
     {
         if (items.empty())
             return LIE_OK;
-        Group<lie::CommArgs> lds, glob, rn;
+        Group<lie::CommArgs> lds, glob;
         Group<lie::GemmArgs> dot, sub;
         Group<lie::NormArgs> nrm;
         int dmax = 1;
@@ -1819,9 +1818,7 @@ struct lie_closure_batch {
                 lds.add(a, it.cnt, 1);
                 dmax = std::max(dmax, h->d);
             } else {
-                const int tiles = (int)((h->D + 255) / 256);
-                glob.add(a, tiles * it.cnt, tiles);
-                rn.add(a, it.cnt, 1);
+                glob.add(a, it.cnt, 1);  // one workgroup per candidate (tile-pair kernel, row norms included)
             }
             const int64_t nh = std::min(std::max<int64_t>(it.n_hi, 1), h->cap);
             lie::GemmArgs g{};
@@ -1847,7 +1844,6 @@ struct lie_closure_batch {
         lie_status s = LIE_OK;
         if ((s = record(COMM_F32, lds, true, dmax, LIE_K_COMM, flc)) != LIE_OK ||
             (s = record(COMM_F32, glob, false, 0, LIE_K_COMM, lds.empty() ? flc : 0)) != LIE_OK ||
-            (s = record(ROWNORM_F32, rn, false, 0, LIE_K_COMM, 0)) != LIE_OK ||
             (s = record(bf_items ? DOT_BF : DOT_F32, dot, false, 0, LIE_K_DOT, flp)) != LIE_OK ||
             (s = record(bf_items ? SUB_BF : SUB_F32, sub, false, 0, LIE_K_SUB, flp)) != LIE_OK ||
             (s = record(NORM, nrm, false, 0, LIE_K_REDUCE, 0)) != LIE_OK)
@@ -1870,7 +1866,6 @@ struct lie_closure_batch {
         switch (r.kind) {
         case COMM_F64: return status_of(lie::launch_comm_f64_batched(r.b, r.lds, r.dmax, stream));
         case COMM_F32: return status_of(lie::launch_comm_f32_batched(r.b, r.lds, r.dmax, stream));
-        case ROWNORM_F32: return status_of(lie::launch_rownorm_f32_batched(r.b, stream));
         case DOT_F64: return status_of(lie::launch_gemm_dot_batched(r.b, false, stream));
         case DOT_F32: return status_of(lie::launch_gemm_dot_batched(r.b, true, stream));
         case DOT_BF: return status_of(lie::launch_gemm_dot_bf16x3_batched(r.b, stream));

@@ -1,0 +1,212 @@
+// Bracket of large operators (d > 64) on the matrix cores, FP64 and FP32.
+//
+// With A = sqrt(d/2)(Ar + i Ai) read from the packed array (entry (i, k) of Ar and Ai
+// both come from p[i][k] and p[k][i]), the bracket is [A, B] = (d/2)(P - P^H) with
+// P = (Ar + i Ai)(Br + i Bi), formed as four real products.  Its packed output needs
+// P[i][j] and P[j][i] together, and a whole P (2 d^2 values) no longer fits in LDS
+// at d = 128, so the work is cut into mirrored 16 x 16 tile pairs {(I, J), (J, I)},
+// I <= J: a wave forms both tiles of a pair with 16x16x4 MFMAs, operands gathered
+// from the packed rows in L2 four k-steps at a time, puts them in its own LDS buffer
+// and writes every output element of the two tiles.  One workgroup per candidate,
+// four waves sharing its tile pairs.
+#include "lie_internal.h"
+
+#include <algorithm>
+
+namespace lie {
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kTileLd = 17;  // LDS row stride of a 16 x 16 tile
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+template <typename T>
+struct PairMma;
+
+// 16x16x4 f64: result register r of lane l is D[4r + l/16][l%16].
+template <>
+struct PairMma<double> {
+    typedef f64x4 Acc;
+    __device__ static Acc mma(double a, double b, Acc c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+    __device__ static int row(int lane, int r) { return 4 * r + (lane >> 4); }
+};
+
+// 16x16x4 f32: result register r of lane l is D[4(l/16) + r][l%16].
+template <>
+struct PairMma<float> {
+    typedef f32x4 Acc;
+    __device__ static Acc mma(float a, float b, Acc c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+    __device__ static int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+};
+
+// (x, y) = (p[i][k], p[k][i]); an index outside d x d reads entry (0, 0) and is dropped later.
+template <typename T>
+struct Raw {
+    T x, y;
+};
+template <typename T>
+__device__ inline Raw<T> raw_at(const T *p, int d, int i, int k)
+{
+    const bool in = i < d && k < d;
+    const int ic = in ? i : 0, kc = in ? k : 0;
+    return Raw<T>{p[ic * d + kc], p[kc * d + ic]};
+}
+// Entry (i, k) of Ar and Ai (zero outside d x d).
+template <typename T>
+__device__ inline void frag(Raw<T> v, int d, int i, int k, T &ar, T &ai)
+{
+    const bool in = i < d && k < d;
+    ar = !in || i == k ? T(0) : (i < k ? v.x : -v.y);
+    ai = !in ? T(0) : (i < k ? v.y : (i > k ? v.x : T(1.4142135623730951) * v.x));
+}
+
+template <typename T>
+__device__ void comm_pairs_body(const CommArgs &A, int c)
+{
+    using M = PairMma<T>;
+    using Acc = typename M::Acc;
+    __shared__ T buf[4][4][16 * kTileLd];  // per wave: Pr(I,J), Pi(I,J), Pr(J,I), Pi(J,I)
+    __shared__ double red[4];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const DevState *st = A.st;
+    if (c >= (A.ncnt ? *A.ncnt : A.cnt) || (st && (st->done | st->numeric_error | st->full)))
+        return;
+    const T *V = static_cast<const T *>(A.V);
+    const int d = A.d;
+    const int64_t D = (int64_t)d * d;
+    int64_t l, m;
+    decode_pair(A.pair_list ? A.pair_list[c] : (A.dp0 ? *A.dp0 : A.p0) + c, l, m);
+    const T *pa = V + l * D, *pb = V + m * D;
+    T *out = static_cast<T *>(A.H) + (int64_t)c * D;
+    const T so = (T)sqrt(0.5 * d), sd = (T)sqrt((double)d);
+    const int lr = lane & 15, lk = lane >> 4;
+    const int TT = (d + 15) / 16, npairs = TT * (TT + 1) / 2;
+    T *Pr1 = buf[w][0], *Pi1 = buf[w][1], *Pr2 = buf[w][2], *Pi2 = buf[w][3];
+    double sq = 0.0;
+    for (int t = w; t < npairs; t += 4) {
+        int I = 0, rem = t;  // t -> (I, J), I <= J, row-major over the upper triangle of tiles
+        while (rem >= TT - I) {
+            rem -= TT - I;
+            ++I;
+        }
+        const int J = I + rem;
+        const bool diag = I == J;
+        Acc r1, i1, r2, i2;  // tile (I, J) and (J, I)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            r1[r] = i1[r] = r2[r] = i2[r] = T(0);
+        for (int k0 = 0; k0 < 16 * TT; k0 += 16) {
+            Raw<T> aI[4], aJ[4], bJ[4], bI[4];
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const int k = k0 + 4 * s + lk;
+                aI[s] = raw_at(pa, d, 16 * I + lr, k);
+                bJ[s] = raw_at(pb, d, k, 16 * J + lr);
+                if (!diag) {
+                    aJ[s] = raw_at(pa, d, 16 * J + lr, k);
+                    bI[s] = raw_at(pb, d, k, 16 * I + lr);
+                }
+            }
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const int k = k0 + 4 * s + lk;
+                T ar, ai, br, bi;
+                frag(aI[s], d, 16 * I + lr, k, ar, ai);
+                frag(bJ[s], d, k, 16 * J + lr, br, bi);
+                r1 = M::mma(ar, br, r1);
+                r1 = M::mma(-ai, bi, r1);
+                i1 = M::mma(ar, bi, i1);
+                i1 = M::mma(ai, br, i1);
+                if (!diag) {
+                    frag(aJ[s], d, 16 * J + lr, k, ar, ai);
+                    frag(bI[s], d, k, 16 * I + lr, br, bi);
+                    r2 = M::mma(ar, br, r2);
+                    r2 = M::mma(-ai, bi, r2);
+                    i2 = M::mma(ar, bi, i2);
+                    i2 = M::mma(ai, br, i2);
+                }
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int row = M::row(lane, r);
+            Pr1[row * kTileLd + lr] = r1[r];
+            Pi1[row * kTileLd + lr] = i1[r];
+            Pr2[row * kTileLd + lr] = diag ? r1[r] : r2[r];
+            Pi2[row * kTileLd + lr] = diag ? i1[r] : i2[r];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");  // the tiles, read across lanes
+        // element (a, b) of tile (I, J) is P[16I + a][16J + b]; its mirror P[16J + b][16I + a]
+        // is element (b, a) of tile (J, I)
+        for (int e = lane; e < 256; e += 64) {
+            const int a = e >> 4, b = e & 15;
+            const int i = 16 * I + a, j = 16 * J + b;
+            if (i >= d || j >= d || i > j)
+                continue;
+            if (i < j) {
+                const T v1 = so * (Pr1[a * kTileLd + b] - Pr2[b * kTileLd + a]);
+                const T v2 = so * (Pi1[a * kTileLd + b] + Pi2[b * kTileLd + a]);
+                out[(int64_t)i * d + j] = v1;
+                out[(int64_t)j * d + i] = v2;
+                sq += (double)v1 * v1 + (double)v2 * v2;
+            } else {
+                const T v = sd * Pi1[a * kTileLd + b];
+                out[(int64_t)i * d + i] = v;
+                sq += (double)v * v;
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");  // read before the next pair overwrites
+    }
+    if (A.hs2) {
+        for (int off = 32; off > 0; off >>= 1)
+            sq += __shfl_down(sq, off, 64);
+        if (lane == 0)
+            red[w] = sq;
+        __syncthreads();
+        if (threadIdx.x == 0)
+            A.hs2[c] = red[0] + red[1] + red[2] + red[3];
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_comm_pairs(CommArgs a)
+{
+    comm_pairs_body<T>(a, blockIdx.x);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_comm_pairs_b(Batch b)
+{
+    const int p = batch_find(b.start, b.nprob, blockIdx.x);
+    const CommArgs a = static_cast<const CommArgs *>(b.args)[p];
+    comm_pairs_body<T>(a, blockIdx.x - b.start[p]);
+}
+
+}  // namespace
+
+hipError_t launch_comm_pairs(const CommArgs &a, bool f64, hipStream_t s)
+{
+    if (a.cnt <= 0)
+        return hipSuccess;
+    if (f64)
+        hipLaunchKernelGGL(k_comm_pairs<double>, dim3(a.cnt), dim3(kThreads), 0, s, a);
+    else
+        hipLaunchKernelGGL(k_comm_pairs<float>, dim3(a.cnt), dim3(kThreads), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_comm_pairs_batched(const Batch &b, bool f64, hipStream_t s)
+{
+    if (b.total <= 0)
+        return hipSuccess;
+    if (f64)
+        hipLaunchKernelGGL(k_comm_pairs_b<double>, dim3(b.total), dim3(kThreads), 0, s, b);
+    else
+        hipLaunchKernelGGL(k_comm_pairs_b<float>, dim3(b.total), dim3(kThreads), 0, s, b);
+    return hipGetLastError();
+}
+
+}  // namespace lie

@@ -173,7 +173,8 @@ __device__ void comm_f64_lds_body(const CommArgs &A, int c)
     }
 }
 
-// Same bracket reading operands directly from global memory (any d).
+// Same bracket reading operands directly from global memory (any d); scalar, used for
+// the occasional raw row that Algorithm 3 rebuilds at d > 64.
 __device__ void comm_f64_global_body(const CommArgs &A, int bx, int c)
 {
     const double *V = static_cast<const double *>(A.V);
@@ -399,10 +400,6 @@ __global__ void __launch_bounds__(kThreads) k_comm_f64_mfma_b(Batch b)
 }
 
 __global__ void __launch_bounds__(kThreads) k_comm_f64_lds(CommArgs a) { comm_f64_lds_body(a, blockIdx.x); }
-__global__ void __launch_bounds__(kThreads) k_comm_f64_global(CommArgs a)
-{
-    comm_f64_global_body(a, blockIdx.x, blockIdx.y);
-}
 __global__ void __launch_bounds__(kThreads) k_comm_f64_lds_b(Batch b)
 {
     const int p = batch_find(b.start, b.nprob, blockIdx.x);
@@ -461,13 +458,6 @@ __global__ void __launch_bounds__(kThreads) k_raw_append(const double *G, double
     }
 }
 
-__global__ void __launch_bounds__(kThreads) k_comm_f64_global_b(Batch b)
-{
-    const int p = batch_find(b.start, b.nprob, blockIdx.x);
-    const CommArgs a = static_cast<const CommArgs *>(b.args)[p];
-    const int l = blockIdx.x - b.start[p], gx = b.gx[p];
-    comm_f64_global_body(a, l % gx, l / gx);
-}
 
 // ------------------------------------------------------------------ projection
 //
@@ -1725,12 +1715,9 @@ hipError_t launch_comm_f64(const double *V, int d, int64_t p0, const int64_t *pa
     }
     if (d <= 64 && lds <= granted) {
         hipLaunchKernelGGL(k_comm_f64_lds, dim3(cnt), dim3(kThreads), lds, s, a);
-    } else {
-        const int64_t D = (int64_t)d * d;
-        hipLaunchKernelGGL(k_comm_f64_global, dim3((unsigned)((D + kThreads - 1) / kThreads), cnt), dim3(kThreads), 0,
-                           s, a);
+        return hipGetLastError();
     }
-    return hipGetLastError();
+    return launch_comm_pairs(a, true, s);
 }
 
 bool comm_f64_fits_lds(int d)
@@ -1779,10 +1766,9 @@ hipError_t launch_comm_f64_batched(const Batch &b, bool lds_variant, int dmax, h
             granted = lds;
         }
         hipLaunchKernelGGL(k_comm_f64_lds_b, dim3(b.total), dim3(kThreads), lds, s, b);
-    } else {
-        hipLaunchKernelGGL(k_comm_f64_global_b, dim3(b.total), dim3(kThreads), 0, s, b);
+        return hipGetLastError();
     }
-    return hipGetLastError();
+    return launch_comm_pairs_batched(b, true, s);
 }
 
 hipError_t launch_accept_batched(const Batch &b, int64_t lds_doubles, hipStream_t s)

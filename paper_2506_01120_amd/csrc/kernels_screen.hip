@@ -30,106 +30,11 @@ __device__ inline float wave_sum_f(float v)
 
 // ------------------------------------------------------------------ bracket (FP32 MFMA)
 //
-// Same algebra as the FP64 bracket: A = sqrt(d/2)(Ar + i Ai) read from the
-// packed array, P = (Ar + i Ai)(Br + i Bi) on the matrix cores as four real
-// products (16x16x4 f32 tiles, operands zero-padded to a multiple of 16),
-// then the packed bracket sqrt(d/2)(P - P^H) with diagonal sqrt(d) Im P_ii.
-// One workgroup per candidate; operands and P live in LDS (d <= 64).
-
-__device__ void comm_f32_mfma_body(const CommArgs &A, int c)
-{
-    extern __shared__ float smem[];
-    const float *Vs = static_cast<const float *>(A.V);
-    const int d = A.d;
-    const int64_t p0 = A.dp0 ? *A.dp0 : A.p0;
-    const int cnt = A.cnt;
-    const DevState *st = A.st;
-    float *Hs = static_cast<float *>(A.H);
-    double *hs2 = A.hs2;
-    if (c >= cnt || aborted(st))
-        return;
-    const int D = d * d;
-    const int dp = (d + 15) & ~15;
-    const int ld = dp + 1;
-    float *Ar = smem, *Ai = Ar + dp * ld, *Br = Ai + dp * ld, *Bi = Br + dp * ld, *Pr = Bi + dp * ld,
-          *Pi = Pr + dp * ld;
-    __shared__ float red[4];
-    int64_t l, m;
-    decode_pair(p0 + c, l, m);
-    const float *pa = Vs + l * (int64_t)D, *pb = Vs + m * (int64_t)D;
-    const float r2 = 1.41421356237309515f;
-    for (int idx = threadIdx.x; idx < dp * dp; idx += blockDim.x) {
-        const int i = idx / dp, k = idx % dp;
-        float ar = 0.f, ai = 0.f, br = 0.f, bi = 0.f;
-        if (i < d && k < d) {
-            if (i < k) {
-                ar = pa[i * d + k];
-                ai = pa[k * d + i];
-                br = pb[i * d + k];
-                bi = pb[k * d + i];
-            } else if (i > k) {
-                ar = -pa[k * d + i];
-                ai = pa[i * d + k];
-                br = -pb[k * d + i];
-                bi = pb[i * d + k];
-            } else {
-                ai = r2 * pa[i * d + i];
-                bi = r2 * pb[i * d + i];
-            }
-        }
-        Ar[i * ld + k] = ar;
-        Ai[i * ld + k] = ai;
-        Br[i * ld + k] = br;
-        Bi[i * ld + k] = bi;
-    }
-    __syncthreads();
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int T = dp / 16;
-    const int lr = lane & 15, lk = lane >> 4;
-    for (int t = w; t < 2 * T * T; t += 4) {
-        const int part = t / (T * T);  // 0: real part, 1: imaginary part
-        const int I = (t % (T * T)) / T, J = t % T;
-        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-        const int row = I * 16 + lr, col = J * 16 + lr;
-        for (int k0 = 0; k0 < dp; k0 += 4) {
-            const int k = k0 + lk;
-            const float ar = Ar[row * ld + k], ai = Ai[row * ld + k];
-            const float br = Br[k * ld + col], bi = Bi[k * ld + col];
-            if (part == 0) {
-                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, br, acc, 0, 0, 0);
-                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(-ai, bi, acc, 0, 0, 0);
-            } else {
-                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, bi, acc, 0, 0, 0);
-                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(ai, br, acc, 0, 0, 0);
-            }
-        }
-        float *P = part == 0 ? Pr : Pi;
-        for (int r = 0; r < 4; ++r)
-            P[(I * 16 + 4 * lk + r) * ld + J * 16 + lr] = acc[r];
-    }
-    __syncthreads();
-    const float so = sqrtf(0.5f * d), sd = sqrtf((float)d);
-    float *out = Hs + (int64_t)c * D;
-    float sq = 0.f;
-    for (int e = threadIdx.x; e < D; e += blockDim.x) {
-        const int i = e / d, j = e % d;
-        float v;
-        if (i < j)
-            v = so * (Pr[i * ld + j] - Pr[j * ld + i]);
-        else if (i > j)
-            v = so * (Pi[j * ld + i] + Pi[i * ld + j]);
-        else
-            v = sd * Pi[i * ld + i];
-        out[e] = v;
-        sq += v * v;
-    }
-    sq = wave_sum_f(sq);
-    if (lane == 0)
-        red[w] = sq;
-    __syncthreads();
-    if (threadIdx.x == 0)
-        hs2[c] = (double)red[0] + red[1] + red[2] + red[3];
-}
+// Same algebra as the FP64 bracket: A = sqrt(d/2)(Ar + i Ai) read from the packed
+// array, P = (Ar + i Ai)(Br + i Bi) on the matrix cores as four real products
+// (16x16x4 f32 tiles, operands zero-padded to a multiple of 16), then the packed
+// bracket sqrt(d/2)(P - P^H) with diagonal sqrt(d) Im P_ii, and the squared norm of
+// the output row.  d <= 64 here; larger operators go to the tile-pair kernel.
 
 // ---- gathered variant (d <= 64): the two packed operands are copied into LDS with
 // coalesced loads (row stride d + 1 against bank conflicts) and each MFMA operand is
@@ -332,100 +237,6 @@ __global__ void __launch_bounds__(kThreads) k_comm_f32_reg_b(Batch b)
     comm_f32_reg_body<T>(a, blockIdx.x - b.start[p]);
 }
 
-// FP32 bracket straight from global memory, for d beyond the LDS kernel.
-__device__ void comm_f32_global_body(const CommArgs &A, int bx, int c)
-{
-    const float *Vs = static_cast<const float *>(A.V);
-    const int d = A.d;
-    const int64_t p0 = A.dp0 ? *A.dp0 : A.p0;
-    const int cnt = A.cnt;
-    const DevState *st = A.st;
-    float *Hs = static_cast<float *>(A.H);
-    if (c >= cnt || aborted(st))
-        return;
-    const int64_t D = (int64_t)d * d;
-    const int64_t idx = (int64_t)bx * blockDim.x + threadIdx.x;
-    if (idx >= D)
-        return;
-    const int i = (int)(idx / d), j = (int)(idx % d);
-    if (i > j)
-        return;
-    int64_t l, m;
-    decode_pair(p0 + c, l, m);
-    const float *pa = Vs + l * D, *pb = Vs + m * D;
-    auto re = [d](const float *p, int a, int b) { return a < b ? p[a * d + b] : (a > b ? -p[b * d + a] : 0.f); };
-    auto im = [d](const float *p, int a, int b) {
-        return a < b ? p[b * d + a] : (a > b ? p[a * d + b] : 1.41421356237309515f * p[a * d + a]);
-    };
-    float prij = 0, piij = 0, prji = 0, piji = 0;
-    for (int k = 0; k < d; ++k) {
-        const float ar = re(pa, i, k), ai = im(pa, i, k), br = re(pb, k, j), bi = im(pb, k, j);
-        prij += ar * br - ai * bi;
-        piij += ar * bi + ai * br;
-        const float ar2 = re(pa, j, k), ai2 = im(pa, j, k), br2 = re(pb, k, i), bi2 = im(pb, k, i);
-        prji += ar2 * br2 - ai2 * bi2;
-        piji += ar2 * bi2 + ai2 * br2;
-    }
-    const float so = sqrtf(0.5f * d), sd = sqrtf((float)d);
-    float *out = Hs + (int64_t)c * D;
-    if (i < j) {
-        out[i * d + j] = so * (prij - prji);
-        out[j * d + i] = so * (piij + piji);
-    } else {
-        out[i * d + i] = sd * piij;
-    }
-}
-
-__device__ void rownorm_f32_body(const CommArgs &A, int c)
-{
-    const float *Hs = static_cast<const float *>(A.H);
-    const int cnt = A.cnt;
-    const int64_t D = (int64_t)A.d * A.d;
-    const DevState *st = A.st;
-    double *hs2 = A.hs2;
-    __shared__ double red[4];
-    if (c >= cnt || aborted(st))
-        return;
-    double s = 0.0;
-    for (int64_t j = threadIdx.x; j < D; j += blockDim.x) {
-        const double v = Hs[(int64_t)c * D + j];
-        s += v * v;
-    }
-    for (int off = 32; off > 0; off >>= 1)
-        s += __shfl_down(s, off, 64);
-    if ((threadIdx.x & 63) == 0)
-        red[threadIdx.x >> 6] = s;
-    __syncthreads();
-    if (threadIdx.x == 0)
-        hs2[c] = red[0] + red[1] + red[2] + red[3];
-}
-
-__global__ void __launch_bounds__(kThreads) k_comm_f32_mfma(CommArgs a) { comm_f32_mfma_body(a, blockIdx.x); }
-__global__ void __launch_bounds__(kThreads) k_comm_f32_global(CommArgs a)
-{
-    comm_f32_global_body(a, blockIdx.x, blockIdx.y);
-}
-__global__ void __launch_bounds__(kThreads) k_rownorm_f32(CommArgs a) { rownorm_f32_body(a, blockIdx.x); }
-__global__ void __launch_bounds__(kThreads) k_comm_f32_mfma_b(Batch b)
-{
-    const int p = batch_find(b.start, b.nprob, blockIdx.x);
-    const CommArgs a = static_cast<const CommArgs *>(b.args)[p];
-    comm_f32_mfma_body(a, blockIdx.x - b.start[p]);
-}
-__global__ void __launch_bounds__(kThreads) k_comm_f32_global_b(Batch b)
-{
-    const int p = batch_find(b.start, b.nprob, blockIdx.x);
-    const CommArgs a = static_cast<const CommArgs *>(b.args)[p];
-    const int l = blockIdx.x - b.start[p], gx = b.gx[p];
-    comm_f32_global_body(a, l % gx, l / gx);
-}
-__global__ void __launch_bounds__(kThreads) k_rownorm_f32_b(Batch b)
-{
-    const int p = batch_find(b.start, b.nprob, blockIdx.x);
-    const CommArgs a = static_cast<const CommArgs *>(b.args)[p];
-    rownorm_f32_body(a, blockIdx.x - b.start[p]);
-}
-
 // ------------------------------------------------------------------ classification and compaction
 //
 // One workgroup of 1024 threads walks the block in chunks of 1024 candidates.
@@ -513,92 +324,32 @@ hipError_t launch_comm_f32(const float *Vs, int d, int64_t p0, int cnt, const De
 {
     if (cnt <= 0)
         return hipSuccess;
-    const int dp = (d + 15) & ~15;
-    const size_t lds = (size_t)6 * dp * (dp + 1) * sizeof(float);
-    static int max_lds = -1;
-    static size_t granted = 65536;
-    if (max_lds < 0) {
-        int dev = 0, v = 65536;
-        if (hipGetDevice(&dev) == hipSuccess &&
-            hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess)
-            max_lds = v;
-        else
-            max_lds = 65536;
-    }
-    if (lds > granted && lds + 1024 <= (size_t)max_lds) {
-        // raise the dynamic LDS limit of this kernel to what this launch needs
-        if (hipFuncSetAttribute((const void *)k_comm_f32_mfma, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) ==
-            hipSuccess)
-            granted = lds;
-        else
-            (void)hipGetLastError();  // clear the failed request; the fallback kernel is used
-    }
     CommArgs a{Vs, d, p0, nullptr, dp0, nullptr, cnt, st, Hs, hs2};
-    if (d <= 16) {
+    if (d <= 16)
         hipLaunchKernelGGL(k_comm_f32_reg16, dim3((unsigned)((cnt + 3) / 4)), dim3(kThreads), 0, s, a);
-        return hipGetLastError();
-    }
-    if (d <= 32) {
+    else if (d <= 32)
         hipLaunchKernelGGL(k_comm_f32_reg<2>, dim3(cnt), dim3(kThreads), (size_t)2 * 32 * 33 * sizeof(float), s, a);
-        return hipGetLastError();
-    }
-    if (d <= 64) {
+    else if (d <= 64)
         hipLaunchKernelGGL(k_comm_f32_reg<4>, dim3(cnt), dim3(kThreads), (size_t)2 * 64 * 65 * sizeof(float), s, a);
-        return hipGetLastError();
-    }
-    if (lds <= granted) {
-        hipLaunchKernelGGL(k_comm_f32_mfma, dim3(cnt), dim3(kThreads), lds, s, a);
-    } else {
-        const int64_t D = (int64_t)d * d;
-        hipLaunchKernelGGL(k_comm_f32_global, dim3((unsigned)((D + kThreads - 1) / kThreads), cnt), dim3(kThreads), 0,
-                           s, a);
-        hipLaunchKernelGGL(k_rownorm_f32, dim3(cnt), dim3(kThreads), 0, s, a);
-    }
+    else
+        return launch_comm_pairs(a, false, s);
     return hipGetLastError();
 }
 
-bool comm_f32_fits_lds(int d)
-{
-    const int dp = (d + 15) & ~15;
-    int dev = 0, v = 65536;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
-        v = 65536;
-    return (size_t)6 * dp * (dp + 1) * sizeof(float) + 1024 <= (size_t)v;
-}
+bool comm_f32_fits_lds(int d) { return d <= 64; }
 
 hipError_t launch_comm_f32_batched(const Batch &b, bool lds_variant, int dmax, hipStream_t s)
 {
     if (b.total <= 0)
         return hipSuccess;
-    if (lds_variant && dmax <= 32) {
+    if (!lds_variant)
+        return launch_comm_pairs_batched(b, false, s);
+    if (dmax <= 32)
         hipLaunchKernelGGL(k_comm_f32_reg_b<2>, dim3(b.total), dim3(kThreads), (size_t)2 * 32 * 33 * sizeof(float), s,
                            b);
-    } else if (lds_variant && dmax <= 64) {
+    else
         hipLaunchKernelGGL(k_comm_f32_reg_b<4>, dim3(b.total), dim3(kThreads), (size_t)2 * 64 * 65 * sizeof(float), s,
                            b);
-    } else if (lds_variant) {
-        const int dp = (dmax + 15) & ~15;
-        const size_t lds = (size_t)6 * dp * (dp + 1) * sizeof(float);
-        static size_t granted = 65536;
-        if (lds > granted) {
-            if (hipFuncSetAttribute((const void *)k_comm_f32_mfma_b, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    (int)lds) != hipSuccess)
-                return hipGetLastError();
-            granted = lds;
-        }
-        hipLaunchKernelGGL(k_comm_f32_mfma_b, dim3(b.total), dim3(kThreads), lds, s, b);
-    } else {
-        hipLaunchKernelGGL(k_comm_f32_global_b, dim3(b.total), dim3(kThreads), 0, s, b);
-    }
-    return hipGetLastError();
-}
-
-hipError_t launch_rownorm_f32_batched(const Batch &b, hipStream_t s)
-{
-    if (b.total <= 0)
-        return hipSuccess;
-    hipLaunchKernelGGL(k_rownorm_f32_b, dim3(b.total), dim3(kThreads), 0, s, b);
     return hipGetLastError();
 }
 

@@ -280,13 +280,16 @@ hipError_t launch_gemm_dot_batched(const Batch &b, bool f32, hipStream_t s);
 hipError_t launch_gemm_sub_batched(const Batch &b, bool f32, hipStream_t s);
 hipError_t launch_norm_final_batched(const Batch &b, hipStream_t s);
 // Grouped versions of the other stage kernels (one workgroup per candidate for the
-// LDS brackets, per (element tile, candidate) for the global ones, per problem for
-// classification and acceptance).
+// brackets, per problem for classification and acceptance).  lds_variant: every
+// problem of the group has d <= 64 (largest dmax); otherwise the tile-pair kernel.
 hipError_t launch_comm_f64_batched(const Batch &b, bool lds_variant, int dmax, hipStream_t s);
 hipError_t launch_comm_f32_batched(const Batch &b, bool lds_variant, int dmax, hipStream_t s);
-hipError_t launch_rownorm_f32_batched(const Batch &b, hipStream_t s);
 hipError_t launch_classify_batched(const Batch &b, hipStream_t s);
 hipError_t launch_accept_batched(const Batch &b, int64_t lds_doubles, hipStream_t s);
+// Bracket of d > 64 by 16 x 16 tile pairs on the matrix cores (kernels_comm.hip), one
+// workgroup per candidate; FP32 rows also get their squared norms (a.hs2).
+hipError_t launch_comm_pairs(const CommArgs &a, bool f64, hipStream_t s);
+hipError_t launch_comm_pairs_batched(const Batch &b, bool f64, hipStream_t s);
 bool comm_f64_fits_lds(int d);
 bool comm_f32_fits_lds(int d);
 // DevState copies of several problems into one array (for one read-back).

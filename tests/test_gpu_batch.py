@@ -48,7 +48,7 @@ def test_batch64(precision, decide):
         v = b.basis(i)
         if p.name.startswith("pair"):
             assert pins.su_span_distance(v) <= SPAN_TOL, p.name
-        elif p.name.startswith("pauli") or (p.name.startswith("ising") and p.d <= 32):
+        elif p.name.startswith("pauli") or p.name.startswith("ising"):
             if p.name.startswith("pauli"):
                 n = 4 + (i - 9) % 3
                 k = 3 + ((i - 9) // 3) % 4
