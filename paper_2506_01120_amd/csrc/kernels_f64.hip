@@ -575,53 +575,38 @@ __global__ void __launch_bounds__(kThreads) k_sub_partial_f64(const double *__re
         part[((int64_t)ks * cnt + c) * D + j] = acc;
 }
 
-// R = H - sum_ks part, written over H_row(r); per-(row, tile) squared norms of R and H.
+// R = H - sum_ks part, written over H_row(r), and the squared norms of R and H into
+// rho2[r], h2[r]: one workgroup per row (these passes have at most a few dozen rows),
+// partial sums added in a fixed order.
 __global__ void __launch_bounds__(kThreads) k_sub_reduce_f64(double *__restrict__ H, const double *__restrict__ part,
                                                              const int *__restrict__ rows,
                                                              const int *__restrict__ nrows, int cnt, int64_t D,
                                                              int ks_total, const DevState *__restrict__ st,
-                                                             double *__restrict__ normpart)
+                                                             double *__restrict__ rho2, double *__restrict__ h2)
 {
     __shared__ double red[8];
-    const int c = blockIdx.y;
+    const int c = blockIdx.x;
     const int nr = nrows ? *nrows : cnt;
     if (c >= nr || aborted(st))
         return;
     const int hr = rows ? rows[c] : c;
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    double r2 = 0.0, h2 = 0.0;
-    if (j < D) {
+    double r2 = 0.0, hh = 0.0;
+    for (int64_t j = threadIdx.x; j < D; j += blockDim.x) {
         const double h = H[(int64_t)hr * D + j];
         double s = 0.0;
         for (int ks = 0; ks < ks_total; ++ks)
             s += part[((int64_t)ks * cnt + c) * D + j];
         const double r = h - s;
         H[(int64_t)hr * D + j] = r;
-        r2 = r * r;
-        h2 = h * h;
+        r2 += r * r;
+        hh += h * h;
     }
     r2 = block_sum(r2, red);
-    h2 = block_sum(h2, red);
+    hh = block_sum(hh, red);
     if (threadIdx.x == 0) {
-        normpart[((int64_t)c * gridDim.x + blockIdx.x) * 2] = r2;
-        normpart[((int64_t)c * gridDim.x + blockIdx.x) * 2 + 1] = h2;
+        rho2[c] = r2;
+        h2[c] = hh;
     }
-}
-
-__global__ void k_norm_final(const double *__restrict__ normpart, const int *__restrict__ nrows, int cnt, int tiles,
-                             const DevState *__restrict__ st, double *__restrict__ rho2, double *__restrict__ h2)
-{
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    const int nr = nrows ? *nrows : cnt;
-    if (c >= nr || aborted(st))
-        return;
-    double a = 0.0, b = 0.0;
-    for (int t = 0; t < tiles; ++t) {
-        a += normpart[((int64_t)c * tiles + t) * 2];
-        b += normpart[((int64_t)c * tiles + t) * 2 + 1];
-    }
-    rho2[c] = a;
-    h2[c] = b;
 }
 
 int split_k(int64_t D, int cnt, int64_t n_hi)
@@ -1811,8 +1796,7 @@ size_t proj_scratch_doubles(int64_t D, int cnt_max, int64_t cap)
         const int ks = split_k(D, cnt, cap);
         best = std::max(best, (size_t)ks * cnt * D);
     }
-    const int64_t tiles = (D + kThreads - 1) / kThreads;
-    return best + (size_t)cnt_max * tiles * 2;  // + norm partials
+    return best;
 }
 
 int project_split_k(int64_t D, int cnt, int64_t n_hi) { return split_k(D, cnt, std::max<int64_t>(n_hi, 1)); }
@@ -1867,12 +1851,8 @@ hipError_t launch_reduce_f64(double *H, const int *rows, const int *nrows, doubl
         return hipSuccess;
     const int64_t n_hi = std::max<int64_t>(sh.n_hi, 1);
     const int ks = split_k(sh.D, cnt, n_hi);
-    const int tiles = (int)((sh.D + kThreads - 1) / kThreads);
-    double *normpart = part + (size_t)ks * cnt * sh.D;
-    hipLaunchKernelGGL(k_sub_reduce_f64, dim3(tiles, cnt), dim3(kThreads), 0, s, H, part, rows, nrows, cnt, sh.D, ks,
-                       st, normpart);
-    hipLaunchKernelGGL(k_norm_final, dim3((cnt + kThreads - 1) / kThreads), dim3(kThreads), 0, s, normpart, nrows, cnt,
-                       tiles, st, rho2, h2);
+    hipLaunchKernelGGL(k_sub_reduce_f64, dim3(cnt), dim3(kThreads), 0, s, H, part, rows, nrows, cnt, sh.D, ks, st,
+                       rho2, h2);
     return hipGetLastError();
 }
 
