@@ -1112,6 +1112,8 @@ __device__ __forceinline__ void accept_body(const AcceptArgs &a)
     __shared__ double rr_s;
     __shared__ unsigned long long s_cnt[4];  // zero, screen_rej, fp64_rej, nonfinite
     __shared__ double s_max[2];              // max rejected FP64 residual, max screen-rejected residual
+    __shared__ unsigned long long wa_cnt[16][4];  // phase A per-wave counts and maxima
+    __shared__ double wa_max[16][2];
     __shared__ double gacc[1024];            // per-group partial sums of the in-block subtraction (G * D <= 1024)
     DevState *st = a.st;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
@@ -1120,12 +1122,18 @@ __device__ __forceinline__ void accept_body(const AcceptArgs &a)
     double *R = dyn + a.cnt;
     double *cache = R + D;
     const int64_t slots = a.lds_doubles > a.cnt + D ? (a.lds_doubles - a.cnt - D) / D : 0;
+    // The state as this launch finds it, read once (all loads in flight together): the
+    // statistics are then written back as plain stores of this copy plus the launch's
+    // counts, instead of read-modify-write chains on global memory.  Nothing else writes
+    // the state while the launch runs.
+    __shared__ DevState s0;
     if (threadIdx.x == 0) {
-        sN = st->N;
+        s0 = *st;
+        ns = a.nsurv ? *a.nsurv : 0;
+        sN = s0.N;
+        stop = s0.done | s0.numeric_error | s0.full;
         if (a.elem_src || a.track_new)
             st->raw_lo = sN;  // the rows appended by this launch start here
-        stop = aborted(st);
-        ns = a.nsurv ? *a.nsurv : 0;
         for (int i = 0; i < 4; ++i)
             s_cnt[i] = 0;
         s_max[0] = s_max[1] = 0.0;
@@ -1161,24 +1169,32 @@ __device__ __forceinline__ void accept_body(const AcceptArgs &a)
             m0 = fmax(m0, __shfl_down(m0, off, 64));
             m1 = fmax(m1, __shfl_down(m1, off, 64));
         }
+        // per-wave slots, combined by thread 0 (atomics from every wave on the same six
+        // LDS words serialise)
         if (lane == 0) {
-            atomicAdd(&s_cnt[0], k0);
-            atomicAdd(&s_cnt[1], k1);
-            atomicAdd(&s_cnt[2], k2);
-            atomicAdd(&s_cnt[3], k3);
-            atomic_max_pos(&s_max[0], m0);
-            atomic_max_pos(&s_max[1], m1);
+            wa_cnt[w][0] = k0;
+            wa_cnt[w][1] = k1;
+            wa_cnt[w][2] = k2;
+            wa_cnt[w][3] = k3;
+            wa_max[w][0] = m0;
+            wa_max[w][1] = m1;
         }
     }
     __syncthreads();
     if (threadIdx.x == 0) {
+        for (int q = 0; q < nw; ++q) {
+            for (int i = 0; i < 4; ++i)
+                s_cnt[i] += wa_cnt[q][i];
+            s_max[0] = fmax(s_max[0], wa_max[q][0]);
+            s_max[1] = fmax(s_max[1], wa_max[q][1]);
+        }
         if (a.mode == 1) {
-            st->n_cand += a.cnt;
-            st->n_zero += s_cnt[0];
-            st->n_screen_rej += s_cnt[1];
-            st->n_fp64 += s_cnt[2];
-            st->max_rej = fmax(st->max_rej, s_max[0]);
-            st->max_screen_rej = fmax(st->max_screen_rej, s_max[1]);
+            st->n_cand = (s0.n_cand += a.cnt);
+            st->n_zero = (s0.n_zero += (int64_t)s_cnt[0]);
+            st->n_screen_rej = (s0.n_screen_rej += (int64_t)s_cnt[1]);
+            st->n_fp64 = (s0.n_fp64 += (int64_t)s_cnt[2]);
+            st->max_rej = (s0.max_rej = fmax(s0.max_rej, s_max[0]));
+            st->max_screen_rej = (s0.max_screen_rej = fmax(s0.max_screen_rej, s_max[1]));
         }
         if (s_cnt[3])
             st->numeric_error = 1;
@@ -1305,7 +1321,7 @@ __device__ __forceinline__ void accept_body(const AcceptArgs &a)
             l_acc += b.u;
             l_maxrej = fmax(l_maxrej, bstat[0]);
             l_minacc = fmin(l_minacc, bstat[1]);
-            st->n_bqr += b.u;
+            st->n_bqr = (s0.n_bqr += b.u);
             sN = N0 + b.u;
             if (a.early_exit && sN >= a.ambient)
                 st->done = 1;
@@ -1528,15 +1544,15 @@ __device__ __forceinline__ void accept_body(const AcceptArgs &a)
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        st->n_rows += nsv;
-        st->n_fp64 += l_fp64;
-        st->n_zero += l_zero;
-        st->n_acc += l_acc;
-        st->n_gen_acc += l_gen;
-        st->max_rej = fmax(st->max_rej, l_maxrej);
-        st->min_acc = fmin(st->min_acc, l_minacc);
-        st->scr_max_dep = fmax(st->scr_max_dep, l_sdep);
-        st->scr_min_indep = fmin(st->scr_min_indep, l_sind);
+        st->n_rows = s0.n_rows + nsv;
+        st->n_fp64 = s0.n_fp64 + l_fp64;
+        st->n_zero = s0.n_zero + l_zero;
+        st->n_acc = s0.n_acc + l_acc;
+        st->n_gen_acc = s0.n_gen_acc + l_gen;
+        st->max_rej = fmax(s0.max_rej, l_maxrej);
+        st->min_acc = fmin(s0.min_acc, l_minacc);
+        st->scr_max_dep = fmax(s0.scr_max_dep, l_sdep);
+        st->scr_min_indep = fmin(s0.scr_min_indep, l_sind);
         st->N = sN;
     }
 }
