@@ -104,7 +104,21 @@ def roofline(stats, precision: str):
         achieved, peak, unit, bound = fl[dom] / t / 1e12, peak_tf, "TFLOP/s", "mfma"
     else:
         achieved, peak, unit, bound = by[dom] / t / 1e9, PEAK["hbm_GBps"], "GB/s", "hbm"
-    breakdown = {k: {"ms": round(ms[k], 3), "launches": n[k], "avg_us": round(1e3 * ms[k] / n[k], 3) if n[k] else 0}
+    def cls_roof(k):
+        # each class against its own bound: the matrix-core peak of the arithmetic it runs in
+        # (the screen's GEMMs in the screen precision, the screened bracket in FP32, everything
+        # else in FP64) when it works at or above that ridge intensity, HBM otherwise
+        tk = ms[k] / 1e3
+        if tk <= 0:
+            return {}
+        cls_prec = precision if k in ("dot", "sub") else ("fp32" if k == "comm" and precision != "fp64" else "fp64")
+        ptf = PEAK[cls_prec + "_TF"] if cls_prec != "bf16x3" else PEAK["bf16_TF"]
+        if fl[k] > 0 and (not by[k] or fl[k] / by[k] >= ptf * 1e12 / (PEAK["hbm_GBps"] * 1e9)):
+            return {"tflops": round(fl[k] / tk / 1e12, 3), "frac": round(fl[k] / tk / 1e12 / ptf, 4)}
+        return {"gbps": round(by[k] / tk / 1e9, 2), "frac": round(by[k] / tk / 1e9 / PEAK["hbm_GBps"], 5)}
+
+    breakdown = {k: {"ms": round(ms[k], 3), "launches": n[k], "avg_us": round(1e3 * ms[k] / n[k], 3) if n[k] else 0,
+                     **cls_roof(k)}
                  for k in names if n[k]}
     return {"kernel": dom, "bound": bound, "achieved": round(achieved, 4), "peak": peak, "unit": unit,
             "frac": round(achieved / peak, 5), "traffic": None,
