@@ -680,7 +680,6 @@ __device__ inline double lane_bcast(double x, int src)
     const int hi = __builtin_amdgcn_readlane((int)(b >> 32), s);
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
-__device__ inline int lane_bcast_int(int x, int src) { return __builtin_amdgcn_readlane(x, __builtin_amdgcn_readfirstlane(src)); }
 
 // Row stride of the small Gram matrix in LDS: odd, so that a column read by
 // 64 lanes spreads over the banks, and at least 17.
