@@ -1643,15 +1643,16 @@ struct lie_closure_batch {
         int kid;
         double flops;
         int64_t lds_doubles;
+        bool vec;  // projection GEMMs: every problem's rows take 16-byte loads
     };
     std::vector<Rec> recs;
 
     template <typename A>
-    lie_status record(Kind kind, const Group<A> &g, bool lds, int dmax, int kid, double flops)
+    lie_status record(Kind kind, const Group<A> &g, bool lds, int dmax, int kid, double flops, bool vec = false)
     {
         if (g.empty())
             return LIE_OK;
-        Rec r{kind, {}, lds, dmax, kid, flops, 0};
+        Rec r{kind, {}, lds, dmax, kid, flops, 0, vec};
         if constexpr (std::is_same<A, lie::AcceptArgs>::value)
             r.lds_doubles = g.args.front().lds_doubles;
         lie_status s = make(g, &r.b);
@@ -1695,9 +1696,11 @@ struct lie_closure_batch {
         Group<lie::GemmArgs> dot, sub;
         Group<lie::NormArgs> nrm;
         double fl = 0;
+        bool vec = true;
         const int bm = lie::gemm_group_m(false), bn = lie::gemm_group_n(false);
         for (const Item &it : items) {
             lie_closure *h = it.h;
+            vec = vec && h->D % 2 == 0;
             const int64_t nh = std::min(std::max<int64_t>(it.n_hi, 1), h->cap);
             lie::GemmArgs g{};
             g.H = h->H64;
@@ -1722,9 +1725,9 @@ struct lie_closure_batch {
             if (!verify)
                 fl += 2.0 * (double)h->b_nlo * (double)h->D * it.cnt;
         }
-        lie_status s = record(DOT_F64, dot, false, 0, verify ? LIE_K_VERIFY : LIE_K_DOT, fl);
+        lie_status s = record(DOT_F64, dot, false, 0, verify ? LIE_K_VERIFY : LIE_K_DOT, fl, vec);
         if (s == LIE_OK)
-            s = record(SUB_F64, sub, false, 0, verify ? LIE_K_VERIFY : LIE_K_SUB, fl);
+            s = record(SUB_F64, sub, false, 0, verify ? LIE_K_VERIFY : LIE_K_SUB, fl, vec);
         if (s == LIE_OK)
             s = record(NORM, nrm, false, 0, verify ? LIE_K_VERIFY : LIE_K_REDUCE, 0);
         return s;
@@ -1810,6 +1813,7 @@ struct lie_closure_batch {
         Group<lie::NormArgs> nrm;
         int dmax = 1;
         double flc = 0, flp = 0;
+        bool vec = true;
         const int bm = lie::gemm_group_m(true), bn = lie::gemm_group_n(true);
         for (const Item &it : items) {
             lie_closure *h = it.h;
@@ -1820,6 +1824,7 @@ struct lie_closure_batch {
             } else {
                 glob.add(a, it.cnt, 1);  // one workgroup per candidate (tile-pair kernel, row norms included)
             }
+            vec = vec && h->D % 4 == 0;
             const int64_t nh = std::min(std::max<int64_t>(it.n_hi, 1), h->cap);
             lie::GemmArgs g{};
             g.H = h->Hs;
@@ -1844,8 +1849,8 @@ struct lie_closure_batch {
         lie_status s = LIE_OK;
         if ((s = record(COMM_F32, lds, true, dmax, LIE_K_COMM, flc)) != LIE_OK ||
             (s = record(COMM_F32, glob, false, 0, LIE_K_COMM, lds.empty() ? flc : 0)) != LIE_OK ||
-            (s = record(bf_items ? DOT_BF : DOT_F32, dot, false, 0, LIE_K_DOT, flp)) != LIE_OK ||
-            (s = record(bf_items ? SUB_BF : SUB_F32, sub, false, 0, LIE_K_SUB, flp)) != LIE_OK ||
+            (s = record(bf_items ? DOT_BF : DOT_F32, dot, false, 0, LIE_K_DOT, flp, vec)) != LIE_OK ||
+            (s = record(bf_items ? SUB_BF : SUB_F32, sub, false, 0, LIE_K_SUB, flp, vec)) != LIE_OK ||
             (s = record(NORM, nrm, false, 0, LIE_K_REDUCE, 0)) != LIE_OK)
             return s;
         if ((s = group_classify(items, true)) != LIE_OK)
@@ -1866,12 +1871,12 @@ struct lie_closure_batch {
         switch (r.kind) {
         case COMM_F64: return status_of(lie::launch_comm_f64_batched(r.b, r.lds, r.dmax, stream));
         case COMM_F32: return status_of(lie::launch_comm_f32_batched(r.b, r.lds, r.dmax, stream));
-        case DOT_F64: return status_of(lie::launch_gemm_dot_batched(r.b, false, stream));
-        case DOT_F32: return status_of(lie::launch_gemm_dot_batched(r.b, true, stream));
+        case DOT_F64: return status_of(lie::launch_gemm_dot_batched(r.b, false, r.vec, stream));
+        case DOT_F32: return status_of(lie::launch_gemm_dot_batched(r.b, true, r.vec, stream));
         case DOT_BF: return status_of(lie::launch_gemm_dot_bf16x3_batched(r.b, stream));
         case SUB_BF: return status_of(lie::launch_gemm_sub_bf16x3_batched(r.b, stream));
-        case SUB_F64: return status_of(lie::launch_gemm_sub_batched(r.b, false, stream));
-        case SUB_F32: return status_of(lie::launch_gemm_sub_batched(r.b, true, stream));
+        case SUB_F64: return status_of(lie::launch_gemm_sub_batched(r.b, false, r.vec, stream));
+        case SUB_F32: return status_of(lie::launch_gemm_sub_batched(r.b, true, r.vec, stream));
         case NORM: return status_of(lie::launch_norm_final_batched(r.b, stream));
         case CLASSIFY: return status_of(lie::launch_classify_batched(r.b, stream));
         case ACCEPT: return status_of(lie::launch_accept_batched(r.b, r.lds_doubles, stream));

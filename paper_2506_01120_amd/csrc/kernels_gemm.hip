@@ -69,7 +69,16 @@ constexpr int kMaxSlices = 16;  // K slices of a split pass
 
 __device__ inline bool aborted(const DevState *st) { return st && (st->done | st->numeric_error | st->full); }
 
+// Operand loads are unconditional: an element outside the operand reads a valid
+// address (row rows-1 or column 0), and the LDS store replaces it by zero (each item
+// keeps the count of its leading in-range values).  With no branch and no use of the
+// value at load time, every load of a chunk is in flight at once.  VL (a template
+// parameter, so the compiler cannot fold the two load forms into one of 4-byte loads):
+// the rows are a multiple of 16 bytes long, so a 16-byte load at an in-range k (a
+// multiple of VEC) stays inside the row.
+
 // Tile loader of a K-contiguous operand: rows [r0, r0+BR) x k [k0, k0+KC) into LDS as S[k][row].
+// begin() fixes the rows (row pointers through rowmap, computed once per tile).
 template <typename T, int BR>
 struct KContigLoader {
     static constexpr int VEC = 16 / sizeof(T);           // elements per 16-byte load
@@ -77,41 +86,54 @@ struct KContigLoader {
     static constexpr int TOTAL = BR * PER_ROW;           // vectors per tile
     static constexpr int PER_THREAD = (TOTAL + 255) / 256;
     T v[PER_THREAD][VEC];
+    int nv[PER_THREAD];        // leading in-range values of the item
+    const T *rp[PER_THREAD];   // row start (a valid row for out-of-range items)
+    bool rv[PER_THREAD];       // the item's row is in range
 
     template <typename RowFn>
-    __device__ void load(const T *__restrict__ base, int64_t ld, int64_t r0, int64_t rows, int64_t k0, int64_t K,
-                         bool vec_ok, RowFn rowmap)
+    __device__ void begin(const T *__restrict__ base, int64_t ld, int64_t r0, int64_t rows, RowFn rowmap)
     {
 #pragma unroll
         for (int i = 0; i < PER_THREAD; ++i) {
             const int q = threadIdx.x + 256 * i;
-            const int r = q / PER_ROW, kv = (q % PER_ROW) * VEC;
-            const int64_t row = r0 + r, k = k0 + kv;
-            if (q < TOTAL && row < rows) {
-                const T *p = base + (int64_t)rowmap(row) * ld + k;
-                if (vec_ok && k + VEC <= K) {
-                    if constexpr (sizeof(T) == 4) {
-                        const float4 t = *reinterpret_cast<const float4 *>(p);
-                        v[i][0] = t.x;
-                        v[i][1] = t.y;
-                        v[i][2] = t.z;
-                        v[i][3] = t.w;
-                    } else {
-                        const double2 t = *reinterpret_cast<const double2 *>(p);
-                        v[i][0] = t.x;
-                        v[i][1] = t.y;
-                    }
-                } else {
+            const int64_t row = r0 + q / PER_ROW;
+            rv[i] = q < TOTAL && row < rows;
+            rp[i] = base + (int64_t)rowmap(rv[i] ? row : rows - 1) * ld;
+        }
+    }
+    // chunk k0 of the rows of `geo`, offset by `off` elements (a slice of the operand)
+    template <bool VL>
+    __device__ void load_from(const KContigLoader &geo, int64_t off, int64_t k0, int64_t K)
+    {
 #pragma unroll
-                    for (int u = 0; u < VEC; ++u)
-                        v[i][u] = (k + u < K) ? p[u] : T(0);
+        for (int i = 0; i < PER_THREAD; ++i) {
+            const int q = threadIdx.x + 256 * i;
+            const int64_t k = k0 + (q % PER_ROW) * VEC;
+            nv[i] = geo.rv[i] ? (int)min<int64_t>(max<int64_t>(K - k, 0), VEC) : 0;
+            const T *p = geo.rp[i] + off;
+            if constexpr (VL) {
+                if constexpr (sizeof(T) == 4) {
+                    const float4 t = *reinterpret_cast<const float4 *>(p + (k < K ? k : 0));
+                    v[i][0] = t.x;
+                    v[i][1] = t.y;
+                    v[i][2] = t.z;
+                    v[i][3] = t.w;
+                } else {
+                    const double2 t = *reinterpret_cast<const double2 *>(p + (k < K ? k : 0));
+                    v[i][0] = t.x;
+                    v[i][1] = t.y;
                 }
             } else {
 #pragma unroll
                 for (int u = 0; u < VEC; ++u)
-                    v[i][u] = T(0);
+                    v[i][u] = p[k + u < K ? k + u : 0];
             }
         }
+    }
+    template <bool VL>
+    __device__ void load(int64_t k0, int64_t K)
+    {
+        load_from<VL>(*this, 0, k0, K);
     }
     template <int LDW>
     __device__ void store(T (*S)[LDW]) const
@@ -123,16 +145,16 @@ struct KContigLoader {
                 const int r = q / PER_ROW, kv = (q % PER_ROW) * VEC;
 #pragma unroll
                 for (int u = 0; u < VEC; ++u)
-                    S[kv + u][r] = v[i][u];
+                    S[kv + u][r] = u < nv[i] ? v[i][u] : T(0);
             }
         }
     }
 };
 
-// Tile loader of a row-major K x N operand (rows k, contiguous n): k [k0, k0+KC) x n [n0, n0+BN) as S[k][n].
 // Loader of a K-contiguous operand held as `cs` <= CS slices whose sum is the operand
 // (coefficients of a split pass): all slices are loaded at once, so their loads are in
-// flight together, and added in slice order when the tile is stored.
+// flight together, and added in slice order when the tile is stored.  The slices share
+// the row geometry of part[0].
 template <typename T, int BR, int CS>
 struct SlicedLoader {
     KContigLoader<T, BR> part[CS];
@@ -140,17 +162,22 @@ struct SlicedLoader {
     int64_t stride = 0;
 
     template <typename RowFn>
-    __device__ void load(const T *__restrict__ base, int64_t ld, int64_t r0, int64_t rows, int64_t k0, int64_t K,
-                         bool vec_ok, RowFn rowmap)
+    __device__ void begin(const T *__restrict__ base, int64_t ld, int64_t r0, int64_t rows, RowFn rowmap)
+    {
+        part[0].begin(base, ld, r0, rows, rowmap);
+    }
+    template <bool VL>
+    __device__ void load(int64_t k0, int64_t K)
     {
 #pragma unroll
         for (int q = 0; q < CS; ++q)
             if (q < cs)
-                part[q].load(base + (int64_t)q * stride, ld, r0, rows, k0, K, vec_ok, rowmap);
+                part[q].template load_from<VL>(part[0], (int64_t)q * stride, k0, K);
     }
     template <int LDW>
     __device__ void store(T (*S)[LDW])
     {
+        // out-of-range values of every slice sit at the same positions; part[0] masks the sum
 #pragma unroll
         for (int q = 1; q < CS; ++q)
             if (q < cs)
@@ -163,6 +190,8 @@ struct SlicedLoader {
     }
 };
 
+// Tile loader of a row-major K x N operand (rows k, contiguous n): k [k0, k0+KC) x n [n0, n0+BN) as S[k][n].
+// begin() fixes the columns.
 template <typename T, int BN>
 struct KRowLoader {
     static constexpr int VEC = 16 / sizeof(T);
@@ -170,38 +199,46 @@ struct KRowLoader {
     static constexpr int TOTAL = KC * PER_ROW;
     static constexpr int PER_THREAD = (TOTAL + 255) / 256;
     T v[PER_THREAD][VEC];
+    int nv[PER_THREAD];        // leading in-range values of the item
+    const T *cp[PER_THREAD];   // column start in row 0 (a valid column for out-of-range items)
+    int cv[PER_THREAD];        // in-range columns of the item
 
-    __device__ void load(const T *__restrict__ base, int64_t ld, int64_t k0, int64_t K, int64_t n0, int64_t Ncols,
-                         bool vec_ok)
+    __device__ void begin(const T *__restrict__ base, int64_t n0, int64_t Ncols)
     {
 #pragma unroll
         for (int i = 0; i < PER_THREAD; ++i) {
             const int q = threadIdx.x + 256 * i;
-            const int kk = q / PER_ROW, nv = (q % PER_ROW) * VEC;
-            const int64_t k = k0 + kk, n = n0 + nv;
-            if (q < TOTAL && k < K) {
-                const T *p = base + k * ld + n;
-                if (vec_ok && n + VEC <= Ncols) {
-                    if constexpr (sizeof(T) == 4) {
-                        const float4 t = *reinterpret_cast<const float4 *>(p);
-                        v[i][0] = t.x;
-                        v[i][1] = t.y;
-                        v[i][2] = t.z;
-                        v[i][3] = t.w;
-                    } else {
-                        const double2 t = *reinterpret_cast<const double2 *>(p);
-                        v[i][0] = t.x;
-                        v[i][1] = t.y;
-                    }
-                } else {
+            const int64_t n = n0 + (q % PER_ROW) * VEC;
+            const bool ok = q < TOTAL && n < Ncols;
+            cv[i] = ok ? (int)min<int64_t>(Ncols - n, VEC) : 0;
+            cp[i] = base + (ok ? n : 0);
+        }
+    }
+    template <bool VL>
+    __device__ void load(int64_t ld, int64_t k0, int64_t K)
+    {
 #pragma unroll
-                    for (int u = 0; u < VEC; ++u)
-                        v[i][u] = (n + u < Ncols) ? p[u] : T(0);
+        for (int i = 0; i < PER_THREAD; ++i) {
+            const int q = threadIdx.x + 256 * i;
+            const int64_t k = k0 + q / PER_ROW;
+            nv[i] = k < K ? cv[i] : 0;
+            const T *p = cp[i] + (k < K ? k : 0) * ld;
+            if constexpr (VL) {
+                if constexpr (sizeof(T) == 4) {
+                    const float4 t = *reinterpret_cast<const float4 *>(p);
+                    v[i][0] = t.x;
+                    v[i][1] = t.y;
+                    v[i][2] = t.z;
+                    v[i][3] = t.w;
+                } else {
+                    const double2 t = *reinterpret_cast<const double2 *>(p);
+                    v[i][0] = t.x;
+                    v[i][1] = t.y;
                 }
             } else {
 #pragma unroll
                 for (int u = 0; u < VEC; ++u)
-                    v[i][u] = T(0);
+                    v[i][u] = p[u < cv[i] ? u : 0];
             }
         }
     }
@@ -212,16 +249,14 @@ struct KRowLoader {
         for (int i = 0; i < PER_THREAD; ++i) {
             const int q = threadIdx.x + 256 * i;
             if (q < TOTAL) {
-                const int kk = q / PER_ROW, nv = (q % PER_ROW) * VEC;
+                const int kk = q / PER_ROW, nv0 = (q % PER_ROW) * VEC;
 #pragma unroll
                 for (int u = 0; u < VEC; ++u)
-                    S[kk][nv + u] = v[i][u];
+                    S[kk][nv0 + u] = u < nv[i] ? v[i][u] : T(0);
             }
         }
     }
 };
-
-
 
 // K chunks [lo, hi) of slice kz out of ks (every chunk in exactly one slice).
 __device__ inline void slice_range(int nchunks, int kz, int ks, int &lo, int &hi)
@@ -232,7 +267,8 @@ __device__ inline void slice_range(int nchunks, int kz, int ks, int &lo, int &hi
 }
 
 // ---------------------------------------------------------------- coefficients
-template <typename T, int SM, int SN>
+// VD: rows of D elements take 16-byte loads (D a multiple of 16 bytes)
+template <typename T, int SM, int SN, bool VD>
 __device__ void gemm_dot_body(const GemmArgs &g, int bx0, int by, int gxs, int kz = 0)
 {
     using M = Mma<T>;
@@ -252,9 +288,9 @@ __device__ void gemm_dot_body(const GemmArgs &g, int bx0, int by, int gxs, int k
     const int *rows = g.rows;
     auto hmap = [rows](int64_t r) -> int64_t { return rows ? rows[r] : r; };
     auto ident = [](int64_t r) -> int64_t { return r; };
-    const bool vec_ok = (g.D % (16 / sizeof(T))) == 0;
     KContigLoader<T, BM> la;
     KContigLoader<T, BN> lb;
+    la.begin(H, g.D, m0, Mrows, hmap);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int wm = w >> 1, wn = w & 1;
     for (int64_t n0 = (int64_t)bx0 * BN; n0 < N; n0 += (int64_t)gxs * BN) {
@@ -266,19 +302,22 @@ __device__ void gemm_dot_body(const GemmArgs &g, int bx0, int by, int gxs, int k
                 acc[i][j] = M::zero();
         int clo = 0, chi = 0;
         slice_range((int)((g.D + KC - 1) / KC), kz, g.ksplit > 1 ? g.ksplit : 1, clo, chi);
+        lb.begin(V, g.D, n0, N, ident);
         if (clo < chi) {
-            la.load(H, g.D, m0, Mrows, (int64_t)clo * KC, g.D, vec_ok, hmap);
-            lb.load(V, g.D, n0, N, (int64_t)clo * KC, g.D, vec_ok, ident);
+            la.template load<VD>((int64_t)clo * KC, g.D);
+            lb.template load<VD>((int64_t)clo * KC, g.D);
             la.store(As[0]);
             lb.store(Bs[0]);
         }
         __syncthreads();
         for (int c = clo; c < chi; ++c) {
             const int buf = (c - clo) & 1;
-            if (c + 1 < chi) {
-                la.load(H, g.D, m0, Mrows, (int64_t)(c + 1) * KC, g.D, vec_ok, hmap);
-                lb.load(V, g.D, n0, N, (int64_t)(c + 1) * KC, g.D, vec_ok, ident);
-            }
+            // the next chunk (the last one again at the end: a redundant fetch keeps the loop
+            // free of load branches); scheduling barriers keep fetch, multiply, store in order
+            const int64_t kn = (int64_t)min(c + 1, chi - 1) * KC;
+            la.template load<VD>(kn, g.D);
+            lb.template load<VD>(kn, g.D);
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int kk = 0; kk < KC; kk += M::KS) {
                 T a[SM], b[SN];
@@ -294,10 +333,9 @@ __device__ void gemm_dot_body(const GemmArgs &g, int bx0, int by, int gxs, int k
                     for (int j = 0; j < SN; ++j)
                         acc[i][j] = M::mma(a[i], b[j], acc[i][j]);
             }
-            if (c + 1 < chi) {
-                la.store(As[buf ^ 1]);
-                lb.store(Bs[buf ^ 1]);
-            }
+            __builtin_amdgcn_sched_barrier(0);
+            la.store(As[buf ^ 1]);
+            lb.store(Bs[buf ^ 1]);
             __syncthreads();
         }
         T *C = static_cast<T *>(g.C) + (int64_t)kz * g.cslice;
@@ -316,7 +354,9 @@ __device__ void gemm_dot_body(const GemmArgs &g, int bx0, int by, int gxs, int k
 }
 
 // ---------------------------------------------------------------- residual + norms
-template <typename T, int SM, int SN, int CS = 1>
+// VD as in the coefficient GEMM (basis rows); the coefficient rows (ldc a multiple of 4)
+// always take 16-byte loads.
+template <typename T, int SM, int SN, bool VD, int CS = 1>
 __device__ void gemm_sub_body(const GemmArgs &g, int bx, int by, int ntiles, int kz = 0)
 {
     using M = Mma<T>;
@@ -340,9 +380,8 @@ __device__ void gemm_sub_body(const GemmArgs &g, int bx, int by, int ntiles, int
     KRowLoader<T, BN> lb;        // V rows
     la.cs = CS > 1 ? min(max(g.cslices, 1), CS) : 1;
     la.stride = g.cslice;
-    const bool vec_c = (g.ldc % (16 / sizeof(T))) == 0;
-    const bool vec_v = (g.D % (16 / sizeof(T))) == 0;
-    auto load_c = [&](int64_t k0) { la.load(Cc, g.ldc, m0, Mrows, k0, N, vec_c, ident); };
+    la.begin(Cc, g.ldc, m0, Mrows, ident);
+    lb.begin(V, j0, g.D);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int wm = w >> 1, wn = w & 1;
     typename M::Acc acc[SM][SN];
@@ -354,18 +393,18 @@ __device__ void gemm_sub_body(const GemmArgs &g, int bx, int by, int ntiles, int
     int clo = 0, chi = 0;
     slice_range((int)((N + KC - 1) / KC), kz, g.ksplit > 1 ? g.ksplit : 1, clo, chi);
     if (clo < chi) {
-        load_c((int64_t)clo * KC);
-        lb.load(V, g.D, (int64_t)clo * KC, N, j0, g.D, vec_v);
+        la.template load<true>((int64_t)clo * KC, N);
+        lb.template load<VD>(g.D, (int64_t)clo * KC, N);
         la.store(As[0]);
         lb.store(Bs[0]);
     }
     __syncthreads();
     for (int c = clo; c < chi; ++c) {
         const int buf = (c - clo) & 1;
-        if (c + 1 < chi) {
-            load_c((int64_t)(c + 1) * KC);
-            lb.load(V, g.D, (int64_t)(c + 1) * KC, N, j0, g.D, vec_v);
-        }
+        const int64_t kn = (int64_t)min(c + 1, chi - 1) * KC;  // as in the coefficient GEMM
+        la.template load<true>(kn, N);
+        lb.template load<VD>(g.D, kn, N);
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int kk = 0; kk < KC; kk += M::KS) {
             T a[SM], b[SN];
@@ -381,10 +420,9 @@ __device__ void gemm_sub_body(const GemmArgs &g, int bx, int by, int ntiles, int
                 for (int j = 0; j < SN; ++j)
                     acc[i][j] = M::mma(a[i], b[j], acc[i][j]);
         }
-        if (c + 1 < chi) {
-            la.store(As[buf ^ 1]);
-            lb.store(Bs[buf ^ 1]);
-        }
+        __builtin_amdgcn_sched_barrier(0);
+        la.store(As[buf ^ 1]);
+        lb.store(Bs[buf ^ 1]);
         __syncthreads();
     }
     if (g.ksplit > 1) {
@@ -403,40 +441,62 @@ __device__ void gemm_sub_body(const GemmArgs &g, int bx, int by, int ntiles, int
                 }
         return;
     }
-    // epilogue: R = H - acc, squared norms of R and H summed over this wave's columns
+    // epilogue: R = H - acc, squared norms of R and H summed over this wave's columns.
+    // The H values are loaded in groups of RG output rows, every load of a group issued
+    // before any is used (out-of-range ones read a valid address and are ignored), so a
+    // group costs one memory latency, not one per value.  The group sizes keep the
+    // registers, and so the waves per SIMD, of the K loop (FP32: 2 of 16 rows; FP64: all 4).
     T *H = const_cast<T *>(static_cast<const T *>(g.H));
     const int *rows = g.rows;
+    constexpr int RG = M::NR <= 4 ? M::NR : 2;
 #pragma unroll
     for (int i = 0; i < SM; ++i)
 #pragma unroll
-        for (int r = 0; r < M::NR; ++r) {
-            const int ml = wm * SM * M::E + i * M::E + M::out_row(lane, r);
-            const int m = m0 + ml;
-            double rs = 0.0, hsq = 0.0;
-            if (m < Mrows) {
-                const int64_t hr = rows ? rows[m] : m;
+        for (int r0 = 0; r0 < M::NR; r0 += RG) {
+            int hrow[RG];
+            T hv[RG][SN];
+#pragma unroll
+            for (int q = 0; q < RG; ++q) {
+                const int m = m0 + wm * SM * M::E + i * M::E + M::out_row(lane, r0 + q);
+                const int mc = m < Mrows ? m : Mrows - 1;
+                hrow[q] = rows ? rows[mc] : mc;
+            }
+#pragma unroll
+            for (int q = 0; q < RG; ++q)
 #pragma unroll
                 for (int j = 0; j < SN; ++j) {
                     const int64_t col = j0 + wn * SN * M::E + j * M::E + M::out_col(lane);
-                    if (col < g.D) {
-                        T *hp = H + hr * g.D + col;
-                        const T h = *hp;
-                        const T res = h - acc[i][j][r];
-                        if (g.write_r)
-                            *hp = res;
-                        rs += (double)res * (double)res;
-                        hsq += (double)h * (double)h;
+                    hv[q][j] = H[(int64_t)hrow[q] * g.D + (col < g.D ? col : 0)];
+                }
+#pragma unroll
+            for (int q = 0; q < RG; ++q) {
+                const int r = r0 + q;
+                const int ml = wm * SM * M::E + i * M::E + M::out_row(lane, r);
+                const int m = m0 + ml;
+                double rs = 0.0, hsq = 0.0;
+                if (m < Mrows) {
+#pragma unroll
+                    for (int j = 0; j < SN; ++j) {
+                        const int64_t col = j0 + wn * SN * M::E + j * M::E + M::out_col(lane);
+                        if (col < g.D) {
+                            const T h = hv[q][j];
+                            const T res = h - acc[i][j][r];
+                            if (g.write_r)
+                                H[(int64_t)hrow[q] * g.D + col] = res;
+                            rs += (double)res * (double)res;
+                            hsq += (double)h * (double)h;
+                        }
                     }
                 }
-            }
-            // sum over the lanes that hold the same output row
-            for (int off = M::E / 2; off > 0; off >>= 1) {
-                rs += __shfl_xor(rs, off, 64);
-                hsq += __shfl_xor(hsq, off, 64);
-            }
-            if (M::out_col(lane) == 0) {
-                red[ml][wn][0] = rs;
-                red[ml][wn][1] = hsq;
+                // sum over the lanes that hold the same output row
+                for (int off = M::E / 2; off > 0; off >>= 1) {
+                    rs += __shfl_xor(rs, off, 64);
+                    hsq += __shfl_xor(hsq, off, 64);
+                }
+                if (M::out_col(lane) == 0) {
+                    red[ml][wn][0] = rs;
+                    red[ml][wn][1] = hsq;
+                }
             }
         }
     __syncthreads();
@@ -450,16 +510,16 @@ __device__ void gemm_sub_body(const GemmArgs &g, int bx, int by, int ntiles, int
     }
 }
 
-template <typename T, int SM, int SN>
+template <typename T, int SM, int SN, bool VD>
 __global__ void __launch_bounds__(256) k_gemm_dot(GemmArgs g)
 {
-    gemm_dot_body<T, SM, SN>(g, blockIdx.x, blockIdx.y, gridDim.x, blockIdx.z);
+    gemm_dot_body<T, SM, SN, VD>(g, blockIdx.x, blockIdx.y, gridDim.x, blockIdx.z);
 }
 
-template <typename T, int SM, int SN, int CS = 1>
+template <typename T, int SM, int SN, bool VD, int CS = 1>
 __global__ void __launch_bounds__(256) k_gemm_sub(GemmArgs g)
 {
-    gemm_sub_body<T, SM, SN, CS>(g, blockIdx.x, blockIdx.y, gridDim.x, blockIdx.z);
+    gemm_sub_body<T, SM, SN, VD, CS>(g, blockIdx.x, blockIdx.y, gridDim.x, blockIdx.z);
 }
 
 // Finishing step of a split residual pass, one workgroup per row m: R = H - sum_z P_z
@@ -507,22 +567,22 @@ __global__ void __launch_bounds__(256) k_gemm_sub_finish(GemmArgs g, double *rho
     }
 }
 
-template <typename T, int SM, int SN>
+template <typename T, int SM, int SN, bool VD>
 __global__ void __launch_bounds__(256) k_gemm_dot_b(Batch b)
 {
     const int p = batch_find(b.start, b.nprob, blockIdx.x);
     const GemmArgs g = static_cast<const GemmArgs *>(b.args)[p];
     const int l = blockIdx.x - b.start[p], gx = b.gx[p];
-    gemm_dot_body<T, SM, SN>(g, l % gx, l / gx, gx);
+    gemm_dot_body<T, SM, SN, VD>(g, l % gx, l / gx, gx);
 }
 
-template <typename T, int SM, int SN>
+template <typename T, int SM, int SN, bool VD>
 __global__ void __launch_bounds__(256) k_gemm_sub_b(Batch b)
 {
     const int p = batch_find(b.start, b.nprob, blockIdx.x);
     const GemmArgs g = static_cast<const GemmArgs *>(b.args)[p];
     const int l = blockIdx.x - b.start[p], gx = b.gx[p];
-    gemm_sub_body<T, SM, SN>(g, l % gx, l / gx, gx);
+    gemm_sub_body<T, SM, SN, VD>(g, l % gx, l / gx, gx);
 }
 
 __device__ void norm_final_body(const NormArgs &a, int bx)
@@ -550,14 +610,23 @@ __global__ void __launch_bounds__(256) k_norm_final_b(Batch b)
     norm_final_body(a, blockIdx.x - b.start[p]);
 }
 
+// 16-byte loads of rows of D elements (buffers are 256-byte aligned, rows a multiple of 16 bytes)
+template <typename T>
+bool rows_vec(int64_t D)
+{
+    return D % (16 / (int64_t)sizeof(T)) == 0;
+}
+
 template <typename T, int SM, int SN>
 hipError_t dot_impl(const GemmArgs &g, int64_t n_hi, hipStream_t s)
 {
     constexpr int E = Mma<T>::E;
     constexpr int BM = 2 * SM * E, BN = 2 * SN * E;
-    hipLaunchKernelGGL((k_gemm_dot<T, SM, SN>),
-                       dim3((unsigned)((n_hi + BN - 1) / BN), (g.cnt + BM - 1) / BM, std::max(g.ksplit, 1)), dim3(256),
-                       0, s, g);
+    const dim3 grid((unsigned)((n_hi + BN - 1) / BN), (g.cnt + BM - 1) / BM, std::max(g.ksplit, 1));
+    if (rows_vec<T>(g.D))
+        hipLaunchKernelGGL((k_gemm_dot<T, SM, SN, true>), grid, dim3(256), 0, s, g);
+    else
+        hipLaunchKernelGGL((k_gemm_dot<T, SM, SN, false>), grid, dim3(256), 0, s, g);
     return hipGetLastError();
 }
 
@@ -568,10 +637,17 @@ hipError_t sub_impl(const GemmArgs &g, hipStream_t s)
     constexpr int BM = 2 * SM * E, BN = 2 * SN * E;
     const int tiles = (int)((g.D + BN - 1) / BN);
     const dim3 grid(tiles, (g.cnt + BM - 1) / BM, std::max(g.ksplit, 1));
-    if (g.cslices > 1)
-        hipLaunchKernelGGL((k_gemm_sub<T, SM, SN, kMaxSlices>), grid, dim3(256), 0, s, g);
+    if (g.ldc % 4 != 0)
+        return hipErrorInvalidValue;  // the coefficient rows are read with 16-byte loads
+    const bool v = rows_vec<T>(g.D);
+    if (g.cslices > 1 && v)
+        hipLaunchKernelGGL((k_gemm_sub<T, SM, SN, true, kMaxSlices>), grid, dim3(256), 0, s, g);
+    else if (g.cslices > 1)
+        hipLaunchKernelGGL((k_gemm_sub<T, SM, SN, false, kMaxSlices>), grid, dim3(256), 0, s, g);
+    else if (v)
+        hipLaunchKernelGGL((k_gemm_sub<T, SM, SN, true>), grid, dim3(256), 0, s, g);
     else
-        hipLaunchKernelGGL((k_gemm_sub<T, SM, SN>), grid, dim3(256), 0, s, g);
+        hipLaunchKernelGGL((k_gemm_sub<T, SM, SN, false>), grid, dim3(256), 0, s, g);
     return hipGetLastError();
 }
 
@@ -736,25 +812,33 @@ hipError_t launch_norm_final(const double *normpart, const int *nrows, int cnt, 
 int gemm_group_m(bool) { return 64; }
 int gemm_group_n(bool) { return 64; }
 
-hipError_t launch_gemm_dot_batched(const Batch &b, bool f32, hipStream_t s)
+hipError_t launch_gemm_dot_batched(const Batch &b, bool f32, bool vec, hipStream_t s)
 {
     if (b.total <= 0)
         return hipSuccess;
-    if (f32)
-        hipLaunchKernelGGL((k_gemm_dot_b<float, 1, 1>), dim3(b.total), dim3(256), 0, s, b);
+    if (f32 && vec)
+        hipLaunchKernelGGL((k_gemm_dot_b<float, 1, 1, true>), dim3(b.total), dim3(256), 0, s, b);
+    else if (f32)
+        hipLaunchKernelGGL((k_gemm_dot_b<float, 1, 1, false>), dim3(b.total), dim3(256), 0, s, b);
+    else if (vec)
+        hipLaunchKernelGGL((k_gemm_dot_b<double, 2, 2, true>), dim3(b.total), dim3(256), 0, s, b);
     else
-        hipLaunchKernelGGL((k_gemm_dot_b<double, 2, 2>), dim3(b.total), dim3(256), 0, s, b);
+        hipLaunchKernelGGL((k_gemm_dot_b<double, 2, 2, false>), dim3(b.total), dim3(256), 0, s, b);
     return hipGetLastError();
 }
 
-hipError_t launch_gemm_sub_batched(const Batch &b, bool f32, hipStream_t s)
+hipError_t launch_gemm_sub_batched(const Batch &b, bool f32, bool vec, hipStream_t s)
 {
     if (b.total <= 0)
         return hipSuccess;
-    if (f32)
-        hipLaunchKernelGGL((k_gemm_sub_b<float, 1, 1>), dim3(b.total), dim3(256), 0, s, b);
+    if (f32 && vec)
+        hipLaunchKernelGGL((k_gemm_sub_b<float, 1, 1, true>), dim3(b.total), dim3(256), 0, s, b);
+    else if (f32)
+        hipLaunchKernelGGL((k_gemm_sub_b<float, 1, 1, false>), dim3(b.total), dim3(256), 0, s, b);
+    else if (vec)
+        hipLaunchKernelGGL((k_gemm_sub_b<double, 2, 2, true>), dim3(b.total), dim3(256), 0, s, b);
     else
-        hipLaunchKernelGGL((k_gemm_sub_b<double, 2, 2>), dim3(b.total), dim3(256), 0, s, b);
+        hipLaunchKernelGGL((k_gemm_sub_b<double, 2, 2, false>), dim3(b.total), dim3(256), 0, s, b);
     return hipGetLastError();
 }
 

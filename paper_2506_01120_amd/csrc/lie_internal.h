@@ -276,8 +276,9 @@ hipError_t launch_norm_final(const double *normpart, const int *nrows, int cnt, 
 // Geometry of the grouped GEMM launches (fixed tiles: FP32 64x64, FP64 64x64).
 int gemm_group_m(bool f32);   // rows per workgroup
 int gemm_group_n(bool f32);   // columns per workgroup
-hipError_t launch_gemm_dot_batched(const Batch &b, bool f32, hipStream_t s);
-hipError_t launch_gemm_sub_batched(const Batch &b, bool f32, hipStream_t s);
+// vec: every problem's D is a multiple of 16 bytes of elements (16-byte row loads)
+hipError_t launch_gemm_dot_batched(const Batch &b, bool f32, bool vec, hipStream_t s);
+hipError_t launch_gemm_sub_batched(const Batch &b, bool f32, bool vec, hipStream_t s);
 hipError_t launch_norm_final_batched(const Batch &b, hipStream_t s);
 // Grouped versions of the other stage kernels (one workgroup per candidate for the
 // brackets, per problem for classification and acceptance).  lds_variant: every
