@@ -1,4 +1,5 @@
-// Bracket of large operators (d > 64) on the matrix cores, FP64 and FP32.
+// Brackets on the matrix cores, FP64 and FP32: large operators (d > 64) as mirrored
+// tile pairs, and 16 < d <= 32 with the left operand shared by consecutive candidates.
 //
 // With A = sqrt(d/2)(Ar + i Ai) read from the packed array (entry (i, k) of Ar and Ai
 // both come from p[i][k] and p[k][i]), the bracket is [A, B] = (d/2)(P - P^H) with
@@ -185,6 +186,154 @@ __global__ void __launch_bounds__(kThreads) k_comm_pairs_b(Batch b)
     comm_pairs_body<T>(a, blockIdx.x - b.start[p]);
 }
 
+// ---- 16 < d <= 32, candidates grouped by their left operand.
+//
+// Consecutive pair indices p = l(l-1)/2 + m run over m = 0 .. l-1 with l fixed, so
+// consecutive candidates of a block share their left operand V_l.  A workgroup takes
+// up to kMaxGroup consecutive candidates: the MFMA fragments of A (its row block, every
+// k-step) are gathered once per distinct l and stay in registers; per candidate only
+// B is staged in LDS (coalesced, row stride 33), and the next candidate's B is fetched
+// while this one is multiplied.  Wave w computes the 16 x 16 tile (I, J) = (w % 2, w / 2)
+// of P = (Ar + i Ai)(Br + i Bi) (operands zero-padded to 32), P goes to LDS, and the
+// packed bracket sqrt(d/2)(P - P^H) (diagonal sqrt(d) Im P_ii) and its squared norm are
+// written out as in the other bracket kernels.
+constexpr int kMaxGroup = 16;
+constexpr int kLo = 33;  // LDS row stride of the staged operand and of P
+
+// (x, y) = (S[i][k], S[k][i]) of an operand staged in LDS; an index outside d x d reads
+// entry (0, 0), dropped by frag().
+template <typename T>
+__device__ inline Raw<T> raw_lds(const T *S, int d, int i, int k)
+{
+    const bool in = i < d && k < d;
+    const int ic = in ? i : 0, kc = in ? k : 0;
+    return Raw<T>{S[ic * kLo + kc], S[kc * kLo + ic]};
+}
+
+template <typename T>
+__device__ void comm_grouped_body(const CommArgs &A, int c0, int G)
+{
+    using M = PairMma<T>;
+    using Acc = typename M::Acc;
+    __shared__ T Sa[32 * kLo], Sb[32 * kLo], Pr[32 * kLo], Pi[32 * kLo];
+    __shared__ double red[kMaxGroup][4];
+    const DevState *st = A.st;
+    const int cnt = A.ncnt ? *A.ncnt : A.cnt;
+    const int ng = min(G, cnt - c0);
+    if (ng <= 0 || (st && (st->done | st->numeric_error | st->full)))
+        return;
+    const T *V = static_cast<const T *>(A.V);
+    const int d = A.d;
+    const int D = d * d;  // <= 1024: at most 4 elements per thread
+    const int64_t pbase = A.pair_list ? 0 : (A.dp0 ? *A.dp0 : A.p0);
+    auto pair_of = [&](int c) -> int64_t { return A.pair_list ? A.pair_list[c] : pbase + c; };
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int I = w & 1, J = w >> 1;
+    const int lr = lane & 15, lk = lane >> 4;
+    const T so = (T)sqrt(0.5 * d), sd = (T)sqrt((double)d);
+    // element e = tid + kThreads j of an operand row: its (row, column) and whether it exists
+    int eo[4];
+    bool ev[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int e = tid + kThreads * j;
+        ev[j] = e < D;
+        eo[j] = ev[j] ? (e / d) * kLo + e % d : 0;
+    }
+    int64_t l, m;
+    decode_pair(pair_of(c0), l, m);
+    T bnext[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+        bnext[j] = V[m * D + (ev[j] ? tid + kThreads * j : 0)];
+    int64_t lcur = -1;
+    T ar[8], ai[8];  // A fragments of row block I, k-steps 0..7
+    for (int g = 0; g < ng; ++g) {
+        const bool newa = l != lcur;  // uniform
+        if (newa) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (ev[j])
+                    Sa[eo[j]] = V[l * D + tid + kThreads * j];
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if (ev[j])
+                Sb[eo[j]] = bnext[j];
+        __syncthreads();  // Sa (when new) and Sb staged; P of the previous candidate read out
+        if (newa) {
+#pragma unroll
+            for (int s = 0; s < 8; ++s) {
+                const int k = 4 * s + lk;
+                frag(raw_lds(Sa, d, 16 * I + lr, k), d, 16 * I + lr, k, ar[s], ai[s]);
+            }
+            lcur = l;
+        }
+        int64_t ln = l, mn = m;
+        if (g + 1 < ng) {
+            decode_pair(pair_of(c0 + g + 1), ln, mn);
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                bnext[j] = V[mn * D + (ev[j] ? tid + kThreads * j : 0)];
+        }
+        Acc pr, pi;
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            pr[r] = pi[r] = T(0);
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+            const int k = 4 * s + lk;
+            T br, bi;
+            frag(raw_lds(Sb, d, k, 16 * J + lr), d, k, 16 * J + lr, br, bi);
+            pr = M::mma(ar[s], br, pr);
+            pr = M::mma(-ai[s], bi, pr);
+            pi = M::mma(ar[s], bi, pi);
+            pi = M::mma(ai[s], br, pi);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int row = 16 * I + M::row(lane, r);
+            Pr[row * kLo + 16 * J + lr] = pr[r];
+            Pi[row * kLo + 16 * J + lr] = pi[r];
+        }
+        __syncthreads();  // P complete; Sb and Sa reads done
+        T *out = static_cast<T *>(A.H) + (int64_t)(c0 + g) * D;
+        double sq = 0.0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int e = tid + kThreads * j;
+            if (e < D) {
+                const int i = e / d, jj = e % d;
+                T v;
+                if (i < jj)
+                    v = so * (Pr[i * kLo + jj] - Pr[jj * kLo + i]);
+                else if (i > jj)
+                    v = so * (Pi[jj * kLo + i] + Pi[i * kLo + jj]);
+                else
+                    v = sd * Pi[i * kLo + i];
+                out[e] = v;
+                sq += (double)v * (double)v;
+            }
+        }
+        for (int off = 32; off > 0; off >>= 1)
+            sq += __shfl_down(sq, off, 64);
+        if (lane == 0)
+            red[g][w] = sq;
+        l = ln;
+        m = mn;
+    }
+    __syncthreads();
+    if (A.hs2 && tid < ng)
+        A.hs2[c0 + tid] = red[tid][0] + red[tid][1] + red[tid][2] + red[tid][3];
+}
+
+// FP32: at most 128 registers, four workgroups per CU (FP64 would spill there)
+template <typename T>
+__global__ void __launch_bounds__(kThreads, sizeof(T) == 4 ? 4 : 3) k_comm_grouped(CommArgs a, int G)
+{
+    comm_grouped_body<T>(a, blockIdx.x * G, G);
+}
+
 }  // namespace
 
 hipError_t launch_comm_pairs(const CommArgs &a, bool f64, hipStream_t s)
@@ -195,6 +344,23 @@ hipError_t launch_comm_pairs(const CommArgs &a, bool f64, hipStream_t s)
         hipLaunchKernelGGL(k_comm_pairs<double>, dim3(a.cnt), dim3(kThreads), 0, s, a);
     else
         hipLaunchKernelGGL(k_comm_pairs<float>, dim3(a.cnt), dim3(kThreads), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_comm_grouped(const CommArgs &a, bool f64, hipStream_t s)
+{
+    if (a.cnt <= 0)
+        return hipSuccess;
+    if (a.d <= 16 || a.d > 32)
+        return hipErrorInvalidValue;
+    // candidates per workgroup: the sharing grows with the group, but a group runs its
+    // candidates one after the other, so keep at least about 1024 workgroups in flight
+    const int G = std::max(1, std::min(kMaxGroup, a.cnt / 1024));
+    const unsigned grid = (unsigned)((a.cnt + G - 1) / G);
+    if (f64)
+        hipLaunchKernelGGL(k_comm_grouped<double>, dim3(grid), dim3(kThreads), 0, s, a, G);
+    else
+        hipLaunchKernelGGL(k_comm_grouped<float>, dim3(grid), dim3(kThreads), 0, s, a, G);
     return hipGetLastError();
 }
 

@@ -1694,10 +1694,8 @@ hipError_t launch_comm_f64(const double *V, int d, int64_t p0, const int64_t *pa
         hipLaunchKernelGGL(k_comm_f64_mfma16, dim3((unsigned)((cnt + 3) / 4)), dim3(kThreads), 0, s, a);
         return hipGetLastError();
     }
-    if (d <= 32) {
-        hipLaunchKernelGGL(k_comm_f64_mfma<2>, dim3(cnt), dim3(kThreads), (size_t)2 * 32 * 33 * sizeof(double), s, a);
-        return hipGetLastError();
-    }
+    if (d <= 32)
+        return launch_comm_grouped(a, true, s);
     if (d <= 64) {
         static bool granted64 = false;
         const size_t l64 = (size_t)2 * 64 * 65 * sizeof(double);

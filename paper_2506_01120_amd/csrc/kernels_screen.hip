@@ -328,7 +328,7 @@ hipError_t launch_comm_f32(const float *Vs, int d, int64_t p0, int cnt, const De
     if (d <= 16)
         hipLaunchKernelGGL(k_comm_f32_reg16, dim3((unsigned)((cnt + 3) / 4)), dim3(kThreads), 0, s, a);
     else if (d <= 32)
-        hipLaunchKernelGGL(k_comm_f32_reg<2>, dim3(cnt), dim3(kThreads), (size_t)2 * 32 * 33 * sizeof(float), s, a);
+        return launch_comm_grouped(a, false, s);
     else if (d <= 64)
         hipLaunchKernelGGL(k_comm_f32_reg<4>, dim3(cnt), dim3(kThreads), (size_t)2 * 64 * 65 * sizeof(float), s, a);
     else

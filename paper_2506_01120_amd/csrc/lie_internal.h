@@ -290,6 +290,8 @@ hipError_t launch_accept_batched(const Batch &b, int64_t lds_doubles, hipStream_
 // Bracket of d > 64 by 16 x 16 tile pairs on the matrix cores (kernels_comm.hip), one
 // workgroup per candidate; FP32 rows also get their squared norms (a.hs2).
 hipError_t launch_comm_pairs(const CommArgs &a, bool f64, hipStream_t s);
+// 16 < d <= 32: consecutive candidates grouped by their shared left operand (FP64 or FP32)
+hipError_t launch_comm_grouped(const CommArgs &a, bool f64, hipStream_t s);
 hipError_t launch_comm_pairs_batched(const Batch &b, bool f64, hipStream_t s);
 bool comm_f64_fits_lds(int d);
 bool comm_f32_fits_lds(int d);
