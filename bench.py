@@ -208,6 +208,9 @@ def main():
     ap.add_argument("--autotune", action="store_true",
                     help="pick the saturated block size and GEMM tiles by timing them at init (before timing)")
     ap.add_argument("--tune-cache", default=None, help="text cache of autotuner choices")
+    ap.add_argument("--gemm-tile", type=int, default=0,
+                    help="screening GEMM workgroup tile of saturated blocks (1: 64x64, 2: 128x128); "
+                         "0: autotuned or heuristic")
     ap.add_argument("--method", default="orthonormalization",
                     choices=["orthonormalization", "rank_svd", "matrix_inversion"],
                     help="rank_svd: the standard algorithm with an SVD rank test (comparison baseline); "
@@ -244,7 +247,7 @@ def main():
                 p.tol = tol
     cfg = dict(precision=args.precision, decide=args.decide, block=args.block, early_exit=args.early_exit,
                autotune=args.autotune, tune_cache=args.tune_cache, raw_basis=args.raw_basis, method=args.method,
-               representation=args.representation)
+               representation=args.representation, gemm_tile=args.gemm_tile)
     if args.raw_basis and args.workload == "batch64":
         raise SystemExit("--raw-basis is for single problems")
 

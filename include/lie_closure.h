@@ -122,7 +122,11 @@ typedef struct lie_closure_config {
     int32_t method;        /* lie_method: LIE_METHOD_ORTHONORMALIZATION (default) or the comparison
                               baseline LIE_METHOD_RANK_SVD */
     int32_t representation;/* lie_representation: LIE_REP_DENSE (default) or LIE_REP_PAULI */
-    int32_t reserved[3];   /* must be zero */
+    int32_t gemm_tile;     /* screened precisions, adaptive blocks, single problems: workgroup tile of both
+                              screening GEMMs of full saturated blocks; 0 = the autotuner's choice
+                              (autotune = 1) or the shape heuristic, 1 = 64 x 64, 2 = 128 x 128.  Any
+                              other value, or a nonzero value in FP64, fails with LIE_ERR_ARG */
+    int32_t reserved[2];   /* must be zero */
 } lie_closure_config;
 
 /* Kernel classes reported by the per-kernel counters of lie_closure_stats. */

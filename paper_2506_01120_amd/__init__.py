@@ -26,7 +26,8 @@ def make_config(*, precision: str = "fp64", decide: str = "screen", block: int =
                 tau_rej: float = 0.0, max_dim: int = 0, stream=None, device: int | None = None,
                 use_graphs: bool = True, profile: bool = False, autotune: bool = False,
                 tune_cache: str | None = None, raw_basis: bool = False,
-                method: str = "orthonormalization", representation: str = "dense") -> _lib.Config:
+                method: str = "orthonormalization", representation: str = "dense",
+                gemm_tile: int = 0) -> _lib.Config:
     cfg = _lib.Config()
     _lib.check(_lib.load().lie_closure_config_default(ctypes.byref(cfg)))
     cfg.precision = _lib.PRECISIONS[precision]
@@ -42,6 +43,7 @@ def make_config(*, precision: str = "fp64", decide: str = "screen", block: int =
     cfg.raw_basis = 1 if raw_basis else 0
     cfg.method = {"orthonormalization": 0, "rank_svd": 1, "matrix_inversion": 2}[method]
     cfg.representation = {"dense": 0, "pauli": 1}[representation]
+    cfg.gemm_tile = int(gemm_tile)
     # the bytes object must outlive the init call that reads it; the Config keeps it
     cfg._tune_cache_bytes = None if tune_cache is None else os.fsencode(tune_cache)
     cfg.tune_cache = cfg._tune_cache_bytes

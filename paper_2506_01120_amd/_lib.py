@@ -55,7 +55,8 @@ class Config(ctypes.Structure):
         ("raw_basis", ctypes.c_int32),
         ("method", ctypes.c_int32),
         ("representation", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 3),
+        ("gemm_tile", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 2),
     ]
 
 

@@ -941,6 +941,9 @@ lie_status resolve_config(const lie_closure_config *in, lie_closure_config *out)
     for (int r : out->reserved)
         if (r != 0)
             return fail(LIE_ERR_ARG, "config.reserved must be zero");
+    if (out->gemm_tile < 0 || out->gemm_tile > 2 || (out->gemm_tile != 0 && out->precision == LIE_PREC_FP64))
+        return fail(LIE_ERR_ARG, "config.gemm_tile %d: screened precisions take 1 or 2, FP64 takes 0",
+                    out->gemm_tile);
     if (out->autotune != 0 && out->autotune != 1)
         return fail(LIE_ERR_ARG, "config.autotune must be 0 or 1");
     out->tune_cache = nullptr;  // read at init only (see lie_closure_init), never kept
@@ -1093,6 +1096,8 @@ lie_status lie_closure_init(lie_closure **out, const double *generators, int32_t
             h->block_growth = std::min(h->block_growth, h->block_sat);
             h->autotuned = cached ? 2 : 1;
         }
+        if (h->block == 0 && cfg.gemm_tile > 0)
+            h->tile_dot = h->tile_sub = cfg.gemm_tile;  // an explicit tile replaces the timed or heuristic one
     }
     const int b = h->block > 0 ? h->block : std::max(h->block_growth, h->block_sat);
     h->bmax = b;

@@ -132,6 +132,11 @@ def test_config_validation(lib):
     cfg = make_config()
     cfg.autotune = 2
     assert _init(lib, g, 3, 4, 1e-10, cfg)[0] == -1
+    # screening GEMM tiles: 1-2 for the screened precisions, none for FP64
+    for prec, tile in (("fp64", 1), ("fp32", 3), ("fp32", -1), ("bf16x3", 3)):
+        cfg = make_config(precision=prec)
+        cfg.gemm_tile = tile
+        assert _init(lib, g, 3, 4, 1e-10, cfg)[0] == -1
 
 
 def test_null_handle_calls(lib):

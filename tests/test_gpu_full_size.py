@@ -50,6 +50,14 @@ def test_su32_full_certification(precision, decide):
     check(dim, v, st, orth, 32, True, SPAN_TOL_FP64 if precision == "fp64" else SPAN_TOL_MIXED, 1e-10)
 
 
+@pytest.mark.parametrize("tile", [1, 2])
+def test_su32_bf16_tiles(tile):
+    """d = 32 (seed 3), tol 1e-8, split-BF16 screen with each workgroup tile of the screening GEMMs."""
+    dim, v, st, orth = closure(32, 3, 1e-8, precision="bf16x3", decide="screen", gemm_tile=tile)
+    check(dim, v, st, orth, 32, True, SPAN_TOL_MIXED, 1e-10)
+    assert st["tile_dot"] == tile and st["tile_sub"] == tile
+
+
 @pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
 def test_su64_early_exit(precision):
     """d = 64 (seed 5), tol 1e-8, stopped at the ambient bound 4095."""

@@ -191,6 +191,15 @@ def test_screened_small(case, precision, decide):
     assert_parity_mixed(gens, tol, precision=precision, decide=decide, block=block)
 
 
+@pytest.mark.parametrize("precision,tile", [("fp32", 1), ("fp32", 2), ("bf16x3", 1), ("bf16x3", 2)])
+def test_screen_gemm_tiles(precision, tile):
+    """su(16) (seed 2, tol 1e-10, adaptive blocks) with each workgroup tile of the screening GEMMs
+    forced on the saturated blocks, against the reference."""
+    _, _, st = assert_parity_mixed(W.rand_pair(16, seed=2), 1e-10, expected=255, precision=precision,
+                                   decide="screen", gemm_tile=tile)
+    assert st["tile_dot"] == tile and st["tile_sub"] == tile
+
+
 @pytest.mark.parametrize("precision,decide", SCREEN_MODES)
 def test_screened_su32_early_exit(precision, decide):
     """d=32 random pair (seed 3), tol 1e-8, early exit at d^2-1 = 1023, against the reference."""
