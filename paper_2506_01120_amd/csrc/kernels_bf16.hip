@@ -26,8 +26,14 @@ namespace {
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
-constexpr int KC = 32;        // K chunk
-constexpr int LDK = KC + 8;   // LDS row stride (bf16 elements), keeps 16-byte alignment
+constexpr int KC = 32;   // K chunk
+constexpr int LDK = KC;  // LDS row: 64 bytes, four 16-byte groups of 8 k, unpadded
+
+// Column of element k of LDS row `row`: the 16-byte group g = k / 8 is stored at position
+// g ^ ((row / 2) % 4).  An MFMA fragment read (lanes 0-7 take rows r..r+7 at one group)
+// then touches eight distinct 16-byte bank groups, and the staging writes, which cover
+// whole consecutive rows, are contiguous -- neither conflicts.
+__device__ inline int swz(int row, int k) { return ((((k >> 3) ^ (row >> 1)) & 3) << 3) | (k & 7); }
 
 __device__ inline bool aborted(const DevState *st) { return st && (st->done | st->numeric_error | st->full); }
 
@@ -80,9 +86,10 @@ struct SplitRowLoader {
         for (int i = 0; i < PER_THREAD; ++i) {
             const int q = threadIdx.x + 256 * i;
             const int r = q / (KC / 4), kv = (q % (KC / 4)) * 4;
+            const int col = swz(r, kv);  // the four values stay inside one 16-byte group
 #pragma unroll
             for (int u = 0; u < 4; ++u)
-                split(u < nv[i] ? v[i][u] : 0.f, Sh[r][kv + u], Sl[r][kv + u]);
+                split(u < nv[i] ? v[i][u] : 0.f, Sh[r][col + u], Sl[r][col + u]);
         }
     }
 };
@@ -130,8 +137,8 @@ struct SplitColLoader {
                 h[u] = hu;
                 l[u] = lu;
             }
-            *reinterpret_cast<bf16x8 *>(&Sh[n][8 * g]) = h;
-            *reinterpret_cast<bf16x8 *>(&Sl[n][8 * g]) = l;
+            *reinterpret_cast<bf16x8 *>(&Sh[n][swz(n, 8 * g)]) = h;
+            *reinterpret_cast<bf16x8 *>(&Sl[n][swz(n, 8 * g)]) = l;
         }
     }
 };
@@ -154,14 +161,14 @@ __device__ inline void mma_chunk(const Tiles<SM, SN> &t, int buf, int wm, int wn
 #pragma unroll
         for (int i = 0; i < SM; ++i) {
             const int row = wm * SM * 32 + i * 32 + (lane & 31);
-            ah[i] = *reinterpret_cast<const bf16x8 *>(&t.Ah[buf][row][kq]);
-            al[i] = *reinterpret_cast<const bf16x8 *>(&t.Al[buf][row][kq]);
+            ah[i] = *reinterpret_cast<const bf16x8 *>(&t.Ah[buf][row][swz(row, kq)]);
+            al[i] = *reinterpret_cast<const bf16x8 *>(&t.Al[buf][row][swz(row, kq)]);
         }
 #pragma unroll
         for (int j = 0; j < SN; ++j) {
             const int col = wn * SN * 32 + j * 32 + (lane & 31);
-            bh[j] = *reinterpret_cast<const bf16x8 *>(&t.Bh[buf][col][kq]);
-            bl[j] = *reinterpret_cast<const bf16x8 *>(&t.Bl[buf][col][kq]);
+            bh[j] = *reinterpret_cast<const bf16x8 *>(&t.Bh[buf][col][swz(col, kq)]);
+            bl[j] = *reinterpret_cast<const bf16x8 *>(&t.Bl[buf][col][swz(col, kq)]);
         }
 #pragma unroll
         for (int i = 0; i < SM; ++i)
@@ -297,7 +304,7 @@ __device__ void bf_sub_body(const GemmArgs &g, int bx, int by, int ntiles)
     const int m0 = by * BM;
     if (m0 >= Mrows)
         return;
-    // the per-row partial sums of the epilogue reuse the tile storage (80 KB at 128 x 128, so two
+    // the per-row partial sums of the epilogue reuse the tile storage (64 KB at 128 x 128, so two
     // workgroups fit a CU's LDS); the K loop ends with a barrier, after which the tiles are dead
     __shared__ __attribute__((aligned(16))) char smem[sizeof(TT)];
     static_assert(sizeof(double) * BM * 4 <= sizeof(TT), "partial sums must fit the tile storage");
