@@ -39,7 +39,7 @@ def gpu_closure(gens, tol, **cfg):
 
 
 def assert_parity(gens, tol, *, early_exit=False, expected=None, **cfg):
-    ref = O.closure(gens, tol, early_exit=early_exit)
+    ref = reference(gens, tol, early_exit)
     dim, v, st, orth = gpu_closure(gens, tol, early_exit=early_exit, **cfg)
     assert dim == ref.dim, (dim, ref.dim)
     if expected is not None:
@@ -189,6 +189,20 @@ def test_screened_small(case, precision, decide):
         "pair5_ragged": (W.rand_pair(5, seed=22), 1e-10, 33),
     }[case]
     assert_parity_mixed(gens, tol, precision=precision, decide=decide, block=block)
+
+
+@pytest.mark.parametrize("d,block,precision", [(17, 4096, "fp64"), (17, 4096, "fp32"), (20, 2048, "fp64")])
+def test_grouped_bracket_ragged(d, block, precision):
+    """16 < d <= 32 with blocks large enough that a workgroup brackets several consecutive
+    candidates sharing their left operand (groups of 4 at 4096, 2 at 2048), odd and even d,
+    full certification, against the reference element by element."""
+    gens = W.rand_pair(d, seed=60 + d)
+    if precision == "fp64":
+        dim, v, _ = assert_parity(gens, 1e-10, block=block, expected=d * d - 1)
+    else:
+        dim, v, _ = assert_parity_mixed(gens, 1e-10, expected=d * d - 1, precision=precision, decide="screen",
+                                        block=block)
+    assert pins.su_span_distance(v) <= SPAN_TOL_MIXED
 
 
 @pytest.mark.parametrize("precision,tile", [("fp32", 1), ("fp32", 2), ("bf16x3", 1), ("bf16x3", 2)])
