@@ -593,9 +593,7 @@ __global__ void __launch_bounds__(kThreads) k_sub_reduce_f64(double *__restrict_
     double r2 = 0.0, hh = 0.0;
     for (int64_t j = threadIdx.x; j < D; j += blockDim.x) {
         const double h = H[(int64_t)hr * D + j];
-        double s = 0.0;
-        for (int ks = 0; ks < ks_total; ++ks)
-            s += part[((int64_t)ks * cnt + c) * D + j];
+        const double s = ordered_strided_sum(part + (int64_t)c * D + j, (int64_t)cnt * D, ks_total);
         const double r = h - s;
         H[(int64_t)hr * D + j] = r;
         r2 += r * r;

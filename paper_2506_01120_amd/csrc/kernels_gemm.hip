@@ -535,9 +535,7 @@ __global__ void __launch_bounds__(256) k_gemm_sub_finish(GemmArgs g, double *rho
     const double *P = static_cast<const double *>(g.P) + (int64_t)m * g.D;
     double rs = 0.0, hs = 0.0;
     for (int64_t j = threadIdx.x; j < g.D; j += blockDim.x) {
-        double acc = 0.0;
-        for (int z = 0; z < g.ksplit; ++z)
-            acc += P[(int64_t)z * g.pslice + j];
+        const double acc = ordered_strided_sum(P + j, g.pslice, g.ksplit);
         const double h = H[j], r = h - acc;
         if (g.write_r)
             H[j] = r;
@@ -591,11 +589,8 @@ __device__ void norm_final_body(const NormArgs &a, int bx)
     const int Mrows = a.nrows ? *a.nrows : a.cnt;
     if (m >= Mrows || aborted(a.st))
         return;
-    double s0 = 0.0, s1 = 0.0;
-    for (int t = 0; t < a.tiles; ++t) {
-        s0 += a.normpart[((int64_t)m * a.tiles + t) * 2];
-        s1 += a.normpart[((int64_t)m * a.tiles + t) * 2 + 1];
-    }
+    const double *np = a.normpart + (int64_t)m * a.tiles * 2;
+    const double s0 = ordered_strided_sum(np, 2, a.tiles), s1 = ordered_strided_sum(np + 1, 2, a.tiles);
     a.rho2[m] = s0;
     if (a.h2)
         a.h2[m] = s1;

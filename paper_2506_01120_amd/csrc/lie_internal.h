@@ -70,6 +70,25 @@ struct Batch {
     int total;         // start[nprob]
 };
 
+// sum over z < n of p[z * stride], added in the order z = 0, 1, ... (a plain loop's
+// rounding), with the loads of each group of eight issued together before any is added:
+// a plain loop waits on each load before the next, one memory latency per term.
+__device__ inline double ordered_strided_sum(const double *p, int64_t stride, int n)
+{
+    double s = 0.0;
+    for (int z0 = 0; z0 < n; z0 += 8) {
+        double v[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            v[q] = p[(int64_t)(z0 + q < n ? z0 + q : z0) * stride];  // a term past n re-reads a valid one
+        __builtin_amdgcn_sched_barrier(0);  // all eight loads in flight before the first add
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            s += z0 + q < n ? v[q] : 0.0;  // adding +0 leaves a sum unchanged
+    }
+    return s;
+}
+
 __device__ inline int batch_find(const int *start, int n, int b)
 {
     int lo = 0, hi = n;  // start[lo] <= b < start[hi]
