@@ -128,7 +128,7 @@ def roofline(stats, precision: str):
 
 # kernel class -> source file of its kernels (the traffic record is void once that file changes)
 KERNEL_SOURCE = {
-    "accept": "kernels_f64.hip",
+    "accept": "kernels_accept.hip",
     "verify": "kernels_gemm.hip",
     "dot": {"fp64": "kernels_gemm.hip", "fp32": "kernels_gemm.hip", "bf16x3": "kernels_bf16.hip"},
     "sub": {"fp64": "kernels_gemm.hip", "fp32": "kernels_gemm.hip", "bf16x3": "kernels_bf16.hip"},

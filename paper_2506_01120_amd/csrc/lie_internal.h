@@ -70,6 +70,24 @@ struct Batch {
     int total;         // start[nprob]
 };
 
+// Workgroup barrier that orders LDS traffic only: it waits for this wave's LDS
+// operations (lgkmcnt = 0) but not for outstanding global loads or stores, so a
+// prefetch or a result store in flight does not stall every barrier.  Use it
+// only where no thread reads global data another thread of the workgroup just wrote.
+// s_waitcnt encoding (gfx9): vmcnt[3:0] | expcnt[6:4] | lgkmcnt[11:8] | vmcnt[5:4] << 14.
+__device__ inline void lds_barrier()
+{
+    __builtin_amdgcn_s_waitcnt(0xC07F);  // vmcnt = 63, expcnt = 7, lgkmcnt = 0
+    __builtin_amdgcn_s_barrier();
+}
+
+__device__ inline double wave_sum(double v)
+{
+    for (int off = 32; off > 0; off >>= 1)
+        v += __shfl_down(v, off, 64);
+    return v;
+}
+
 // sum over z < n of p[z * stride], added in the order z = 0, 1, ... (a plain loop's
 // rounding), with the loads of each group of eight issued together before any is added:
 // a plain loop waits on each load before the next, one memory latency per term.
@@ -211,7 +229,7 @@ hipError_t launch_sub_f64(const double *V, const DevState *st, const double *C, 
 hipError_t launch_reduce_f64(double *H, const int *rows, const int *nrows, double *part, const DevState *st,
                              double *rho2, double *h2, ProjShape sh, hipStream_t s);
 
-// Acceptance of one block (one workgroup): see kernels_f64.hip.
+// Acceptance of one block (one workgroup): see kernels_accept.hip.
 struct AcceptArgs {
     double *V;
     float *Vs;               // FP32 shadow basis (may be null)
