@@ -103,7 +103,7 @@ struct BqrOut {
 // factorisation and the triangular inverse are one-wave recurrences in LDS (lane
 // i owns row i, resp. column i) that need no workgroup barrier.
 __device__ __forceinline__ BqrOut block_qr(const AcceptArgs &a, int nsv, int64_t N0, double *lds, double *cache2, int64_t cslots,
-                           double *stat, const double *hn_rows)
+                           double *stage, int64_t stage_cap, double *stat, const double *hn_rows)
 {
     const int64_t D = a.D;
     const int ld = gram_ld(nsv);
@@ -119,9 +119,9 @@ __device__ __forceinline__ BqrOut block_qr(const AcceptArgs &a, int nsv, int64_t
     __syncthreads();
     auto row = [&](int r) -> const double * { return a.H + (int64_t)hrow[r] * D; };
     // 1. Gram matrix, lower 16 x 16 tiles (I >= J), one tile per wave.  The survivor rows are
-    // staged through LDS in chunks of 64 columns with coalesced loads (the next chunk is
-    // fetched into registers while the current one is multiplied); without room for the
-    // stage the tiles read global memory directly.
+    // staged through LDS (`stage`, stage_cap doubles) in chunks of 64 columns with coalesced
+    // loads (the next chunk is fetched into registers while the current one is multiplied);
+    // without room for the stage the tiles read global memory directly.
     const int T16 = (nsv + 15) / 16;
     const int ntile = T16 * (T16 + 1) / 2;  // <= 10 <= nw
     int tI = 0, tJ = w;
@@ -130,8 +130,7 @@ __device__ __forceinline__ BqrOut block_qr(const AcceptArgs &a, int nsv, int64_t
         ++tI;
     }
     constexpr int KC = 64, KS = KC + 1;
-    if (cslots * D >= (int64_t)nsv * KS) {
-        double *stage = cache2;
+    if (stage_cap >= (int64_t)nsv * KS) {
         const int per = (nsv * KC + blockDim.x - 1) / blockDim.x;  // <= 4
         double nxt[4];
         auto fetch = [&](int64_t k0) {
@@ -666,8 +665,12 @@ __device__ __forceinline__ void accept_body(const AcceptArgs &a)
     // and the next survivor's residual is prefetched into registers
     double *hn_a = cache, *rs_a = hn_a + nsv, *sn_a = rs_a + nsv;
     double *cache2 = sn_a + nsv;
-    const int64_t slots2 = slots > 0 ? std::max<int64_t>(0, (slots * D - 3 * (int64_t)nsv) / D) : 0;
-    const bool meta_in_lds = slots * D >= 3 * (int64_t)nsv;
+    // LDS after R, in doubles (whole cached rows need not fit for the per-survivor scalars
+    // and the block pass's workspace)
+    const int64_t free_d = a.lds_doubles > a.cnt + D ? a.lds_doubles - a.cnt - D : 0;
+    const bool meta_in_lds = free_d >= 3 * (int64_t)nsv;
+    const int64_t rest = meta_in_lds ? free_d - 3 * (int64_t)nsv : 0;
+    const int64_t slots2 = rest / D;
     for (int k = threadIdx.x; k < nsv && meta_in_lds; k += blockDim.x) {
         const int r = sv_of(k);
         const int c = a.surv_cand[r];
@@ -676,21 +679,25 @@ __device__ __forceinline__ void accept_body(const AcceptArgs &a)
         sn_a[k] = a.rho2 ? sqrt(a.rho2[r]) : -1.0;
     }
     __syncthreads();
-    // block Cholesky-QR pass over the survivors (brackets only, at most 64 survivors)
+    // block Cholesky-QR pass over the survivors (brackets only, at most 64 survivors).  Its
+    // workspace goes after the scalars when it fits there; otherwise (large D: R alone takes
+    // most of the LDS) into R, which the pass does not use -- the sequential path after it
+    // refills R -- with the Gram staging behind it.
     const int64_t gram_need = bqr_lds(nsv, nw);
-    const bool gram_ok = a.mode == 1 && nsv >= 2 && nsv <= 64 && nw >= 16 && meta_in_lds &&
-                         slots * D - 3 * (int64_t)nsv >= gram_need;
-    double *gram_base = cache2;
-    if (gram_ok)
+    const bool gram_free = rest >= gram_need, gram_in_r = !gram_free && D >= gram_need;
+    const bool gram_ok = a.mode == 1 && nsv >= 2 && nsv <= 64 && nw >= 16 && meta_in_lds && (gram_free || gram_in_r);
+    double *gram_base = gram_in_r ? R : cache2;
+    if (gram_ok && gram_free)
         cache2 = gram_base + gram_need;
-    const int64_t slots3 =
-        gram_ok ? std::max<int64_t>(0, (slots * D - 3 * (int64_t)nsv - gram_need) / D) : slots2;
+    const int64_t slots3 = gram_ok && gram_free ? (rest - gram_need) / D : slots2;
     double *cbase = meta_in_lds ? cache2 : cache;
     const int64_t cslots = meta_in_lds ? slots3 : slots;
     int r_first = 0;
     if (gram_ok) {
         __shared__ double bstat[2];
-        const BqrOut b = block_qr(a, nsv, N0, gram_base, cache2, cslots, bstat, hn_a);
+        double *stage = gram_in_r ? R + gram_need : cache2;
+        const int64_t stage_cap = gram_in_r ? D - gram_need : cslots * D;
+        const BqrOut b = block_qr(a, nsv, N0, gram_base, cache2, cslots, stage, stage_cap, bstat, hn_a);
         if (threadIdx.x == 0) {
             // rows 0 .. resume-1 are decided: b.u accepted, the rest rejected
             for (int r = 0; r < b.resume; ++r) {
