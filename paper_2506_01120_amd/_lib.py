@@ -154,6 +154,11 @@ def load() -> ctypes.CDLL:
         if not os.path.exists(LIB_PATH):
             raise ImportError(
                 f"{LIB_PATH} is not built; run `python -m paper_2506_01120_amd.build` (hipcc, gfx950) first")
+        # One HIP runtime per process.  PyTorch-ROCm ships its own libamdhip64; if this
+        # library's (from /opt/rocm) were loaded first, torch's would load beside it and torch
+        # would see no device.  With torch loaded first, this library binds to its runtime.
+        import torch  # noqa: F401
+
         _lib = _declare(ctypes.CDLL(LIB_PATH))
     return _lib
 
