@@ -129,15 +129,22 @@ __device__ __forceinline__ BqrOut block_qr(const AcceptArgs &a, int nsv, int64_t
         tJ -= tI + 1;
         ++tI;
     }
-    constexpr int KC = 64, KS = KC + 1;
-    if (stage_cap >= (int64_t)nsv * KS) {
+    if (stage_cap >= (int64_t)nsv * 65) {
+        // chunk width KC = 2^kcs >= 64 columns: as wide as four values per thread and the
+        // stage allow, so few survivors over a long row take few chunks (each chunk costs a
+        // global-load round trip and two barriers)
+        int kcs = 6;
+        while ((nsv << (kcs + 1)) <= 4 * (int)blockDim.x && (int64_t)nsv * ((2 << kcs) + 1) <= stage_cap &&
+               (int64_t)(1 << kcs) < D)
+            ++kcs;
+        const int KC = 1 << kcs, KS = KC + 1;
         const int per = (nsv * KC + blockDim.x - 1) / blockDim.x;  // <= 4
         double nxt[4];
         auto fetch = [&](int64_t k0) {
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int e = threadIdx.x + q * blockDim.x;
-                const int r = e / KC, c = e % KC;
+                const int r = e >> kcs, c = e & (KC - 1);
                 nxt[q] = (q < per && r < nsv && k0 + c < D) ? row(r)[k0 + c] : 0.0;
             }
         };
@@ -149,19 +156,21 @@ __device__ __forceinline__ BqrOut block_qr(const AcceptArgs &a, int nsv, int64_t
             for (int q = 0; q < 4; ++q) {
                 const int e = threadIdx.x + q * blockDim.x;
                 if (q < per && e < nsv * KC)
-                    stage[(e / KC) * KS + e % KC] = nxt[q];
+                    stage[(e >> kcs) * KS + (e & (KC - 1))] = nxt[q];
             }
             __syncthreads();
             if (k0 + KC < D)
                 fetch(k0 + KC);
             if (w < ntile) {
                 const int ia = tI * 16 + (lane & 15), ib = tJ * 16 + (lane & 15);
+                for (int q0 = 0; q0 < KC / 4; q0 += 16) {
 #pragma unroll
-                for (int q = 0; q < KC / 4; ++q) {
-                    const int k = 4 * q + (lane >> 4);
-                    const double av = ia < nsv ? stage[ia * KS + k] : 0.0;
-                    const double bv = ib < nsv ? stage[ib * KS + k] : 0.0;
-                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+                    for (int q = 0; q < 16; ++q) {
+                        const int k = 4 * (q0 + q) + (lane >> 4);
+                        const double av = ia < nsv ? stage[ia * KS + k] : 0.0;
+                        const double bv = ib < nsv ? stage[ib * KS + k] : 0.0;
+                        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+                    }
                 }
             }
         }
@@ -684,7 +693,10 @@ __device__ __forceinline__ void accept_body(const AcceptArgs &a)
     // most of the LDS) into R, which the pass does not use -- the sequential path after it
     // refills R -- with the Gram staging behind it.
     const int64_t gram_need = bqr_lds(nsv, nw);
-    const bool gram_free = rest >= gram_need, gram_in_r = !gram_free && D >= gram_need;
+    // (in R only from 8 survivors on: at such D the pass has a fixed cost of a few hundred
+    // microseconds in latency-bound sweeps over the columns, while the sequential path
+    // takes a few tens per survivor)
+    const bool gram_free = rest >= gram_need, gram_in_r = !gram_free && D >= gram_need && nsv >= 8;
     const bool gram_ok = a.mode == 1 && nsv >= 2 && nsv <= 64 && nw >= 16 && meta_in_lds && (gram_free || gram_in_r);
     double *gram_base = gram_in_r ? R : cache2;
     if (gram_ok && gram_free)
