@@ -354,8 +354,10 @@ hipError_t launch_comm_grouped(const CommArgs &a, bool f64, hipStream_t s)
     if (a.d <= 16 || a.d > 32)
         return hipErrorInvalidValue;
     // candidates per workgroup: the sharing grows with the group, but a group runs its
-    // candidates one after the other, so keep at least about 1024 workgroups in flight
-    const int G = std::max(1, std::min(kMaxGroup, a.cnt / 1024));
+    // candidates one after the other, so keep at least about 1024 workgroups in flight.
+    // A pair list (the survivors of a screened block: few, their count on the device,
+    // rarely sharing l) takes one candidate per workgroup.
+    const int G = a.pair_list ? 1 : std::max(1, std::min(kMaxGroup, a.cnt / 1024));
     const unsigned grid = (unsigned)((a.cnt + G - 1) / G);
     if (f64)
         hipLaunchKernelGGL(k_comm_grouped<double>, dim3(grid), dim3(kThreads), 0, s, a, G);
