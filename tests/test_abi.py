@@ -154,3 +154,21 @@ def test_python_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(_lib, "_lib", None)
     with pytest.raises(ImportError):
         _lib.load()
+
+
+def test_binding_loads_one_hip_runtime():
+    """PyTorch-ROCm ships its own HIP runtime; the binding loads torch before the library so
+    the library binds to it, whatever the caller imported first (a second runtime loaded
+    beside torch's leaves torch without a device).  Checked in a fresh process: the HIP runtime
+    files mapped after loading the library through the binding, then torch."""
+    code = (
+        "from paper_2506_01120_amd import _lib\n"
+        "_lib.load()\n"
+        "import torch\n"
+        "maps = open('/proc/self/maps').read().splitlines()\n"
+        "print(len({l.split()[-1] for l in maps if 'libamdhip64' in l}))\n"
+    )
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    out = subprocess.run(["python", "-c", code], cwd=root, capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.strip().splitlines()[-1] == "1"
