@@ -64,7 +64,12 @@ struct Mma<double> {
     __device__ static int out_col(int lane) { return lane & 15; }
 };
 
-constexpr int KC = 16;  // K chunk
+// K chunk of a tile BT wide: 32 for FP32 64 x 64 tiles (more loads in flight per barrier;
+// measured faster), 16 otherwise (FP32 128 x 128 tiles measured slower with 32, and FP64's
+// LDS sets its occupancy)
+template <typename T, int BT>
+constexpr int kKC = sizeof(T) == 4 && BT == 64 ? 32 : 16;
+constexpr int KC = 16;  // FP64 (host-side split plans)
 constexpr int kMaxSlices = 16;  // K slices of a split pass
 
 __device__ inline bool aborted(const DevState *st) { return st && (st->done | st->numeric_error | st->full); }
@@ -82,7 +87,7 @@ __device__ inline bool aborted(const DevState *st) { return st && (st->done | st
 template <typename T, int BR>
 struct KContigLoader {
     static constexpr int VEC = 16 / sizeof(T);           // elements per 16-byte load
-    static constexpr int PER_ROW = KC / VEC;
+    static constexpr int PER_ROW = kKC<T, BR> / VEC;
     static constexpr int TOTAL = BR * PER_ROW;           // vectors per tile
     static constexpr int PER_THREAD = (TOTAL + 255) / 256;
     T v[PER_THREAD][VEC];
@@ -196,7 +201,7 @@ template <typename T, int BN>
 struct KRowLoader {
     static constexpr int VEC = 16 / sizeof(T);
     static constexpr int PER_ROW = BN / VEC;
-    static constexpr int TOTAL = KC * PER_ROW;
+    static constexpr int TOTAL = kKC<T, BN> * PER_ROW;
     static constexpr int PER_THREAD = (TOTAL + 255) / 256;
     T v[PER_THREAD][VEC];
     int nv[PER_THREAD];        // leading in-range values of the item
@@ -273,6 +278,8 @@ __device__ void gemm_dot_body(const GemmArgs &g, int bx0, int by, int gxs, int k
 {
     using M = Mma<T>;
     constexpr int BM = 2 * SM * M::E, BN = 2 * SN * M::E;
+    constexpr int KCT = kKC<T, BM>;
+    static_assert(BM == BN, "the operand loaders take the chunk of their own tile width");
     constexpr int PAD = 16 / sizeof(T);
     if (aborted(g.st))
         return;
@@ -281,8 +288,8 @@ __device__ void gemm_dot_body(const GemmArgs &g, int bx0, int by, int gxs, int k
     const int m0 = by * BM;
     if ((int64_t)bx0 * BN >= N || m0 >= Mrows)
         return;
-    __shared__ T As[2][KC][BM + PAD];
-    __shared__ T Bs[2][KC][BN + PAD];
+    __shared__ T As[2][KCT][BM + PAD];
+    __shared__ T Bs[2][KCT][BN + PAD];
     const T *H = static_cast<const T *>(g.H);
     const T *V = static_cast<const T *>(g.V);
     const int *rows = g.rows;
@@ -301,11 +308,11 @@ __device__ void gemm_dot_body(const GemmArgs &g, int bx0, int by, int gxs, int k
             for (int j = 0; j < SN; ++j)
                 acc[i][j] = M::zero();
         int clo = 0, chi = 0;
-        slice_range((int)((g.D + KC - 1) / KC), kz, g.ksplit > 1 ? g.ksplit : 1, clo, chi);
+        slice_range((int)((g.D + KCT - 1) / KCT), kz, g.ksplit > 1 ? g.ksplit : 1, clo, chi);
         lb.begin(V, g.D, n0, N, ident);
         if (clo < chi) {
-            la.template load<VD>((int64_t)clo * KC, g.D);
-            lb.template load<VD>((int64_t)clo * KC, g.D);
+            la.template load<VD>((int64_t)clo * KCT, g.D);
+            lb.template load<VD>((int64_t)clo * KCT, g.D);
             la.store(As[0]);
             lb.store(Bs[0]);
         }
@@ -314,12 +321,12 @@ __device__ void gemm_dot_body(const GemmArgs &g, int bx0, int by, int gxs, int k
             const int buf = (c - clo) & 1;
             // the next chunk (the last one again at the end: a redundant fetch keeps the loop
             // free of load branches); scheduling barriers keep fetch, multiply, store in order
-            const int64_t kn = (int64_t)min(c + 1, chi - 1) * KC;
+            const int64_t kn = (int64_t)min(c + 1, chi - 1) * KCT;
             la.template load<VD>(kn, g.D);
             lb.template load<VD>(kn, g.D);
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-            for (int kk = 0; kk < KC; kk += M::KS) {
+            for (int kk = 0; kk < KCT; kk += M::KS) {
                 T a[SM], b[SN];
 #pragma unroll
                 for (int i = 0; i < SM; ++i)
@@ -361,6 +368,8 @@ __device__ void gemm_sub_body(const GemmArgs &g, int bx, int by, int ntiles, int
 {
     using M = Mma<T>;
     constexpr int BM = 2 * SM * M::E, BN = 2 * SN * M::E;
+    constexpr int KCT = kKC<T, BM>;
+    static_assert(BM == BN, "the operand loaders take the chunk of their own tile width");
     constexpr int PAD = 16 / sizeof(T);
     if (aborted(g.st))
         return;
@@ -370,8 +379,8 @@ __device__ void gemm_sub_body(const GemmArgs &g, int bx, int by, int ntiles, int
     const int m0 = by * BM;
     if (m0 >= Mrows)
         return;
-    __shared__ T As[2][KC][BM + PAD];
-    __shared__ T Bs[2][KC][BN + PAD];
+    __shared__ T As[2][KCT][BM + PAD];
+    __shared__ T Bs[2][KCT][BN + PAD];
     __shared__ double red[BM][2][2];
     const T *Cc = static_cast<const T *>(g.C);
     const T *V = static_cast<const T *>(g.V);
@@ -391,22 +400,22 @@ __device__ void gemm_sub_body(const GemmArgs &g, int bx, int by, int ntiles, int
         for (int j = 0; j < SN; ++j)
             acc[i][j] = M::zero();
     int clo = 0, chi = 0;
-    slice_range((int)((N + KC - 1) / KC), kz, g.ksplit > 1 ? g.ksplit : 1, clo, chi);
+    slice_range((int)((N + KCT - 1) / KCT), kz, g.ksplit > 1 ? g.ksplit : 1, clo, chi);
     if (clo < chi) {
-        la.template load<true>((int64_t)clo * KC, N);
-        lb.template load<VD>(g.D, (int64_t)clo * KC, N);
+        la.template load<true>((int64_t)clo * KCT, N);
+        lb.template load<VD>(g.D, (int64_t)clo * KCT, N);
         la.store(As[0]);
         lb.store(Bs[0]);
     }
     __syncthreads();
     for (int c = clo; c < chi; ++c) {
         const int buf = (c - clo) & 1;
-        const int64_t kn = (int64_t)min(c + 1, chi - 1) * KC;  // as in the coefficient GEMM
+        const int64_t kn = (int64_t)min(c + 1, chi - 1) * KCT;  // as in the coefficient GEMM
         la.template load<true>(kn, N);
         lb.template load<VD>(g.D, kn, N);
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int kk = 0; kk < KC; kk += M::KS) {
+        for (int kk = 0; kk < KCT; kk += M::KS) {
             T a[SM], b[SN];
 #pragma unroll
             for (int i = 0; i < SM; ++i)
