@@ -154,7 +154,7 @@ typedef struct lie_closure_stats {
     int64_t accepted;             /* elements appended by the bracket loop */
     int64_t block_qr_accepted;    /* of those, appended by the block Cholesky-QR prefix of a block's survivors */
     int64_t blocks;               /* block steps executed */
-    int64_t host_syncs;           /* device-to-host synchronisations of the driver */
+    int64_t host_syncs;           /* device-to-host synchronisations of the host loop */
     double min_accepted_residual; /* smallest FP64 residual that was accepted (bracket loop) */
     double max_rejected_residual; /* largest FP64 residual that was rejected (bracket loop) */
     double max_screen_rejected;   /* largest screened residual among screen rejects */

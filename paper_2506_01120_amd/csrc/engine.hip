@@ -1,6 +1,6 @@
-// Host driver and C ABI of the closure engine (see include/lie_closure.h).
+// Host control loop and C ABI of the closure engine (see include/lie_closure.h).
 //
-// The driver owns one problem's device state: the FP64 basis V64 in the
+// The host loop owns one problem's device state: the FP64 basis V64 in the
 // packed anti-Hermitian layout, the candidate block buffer, coefficient and
 // scratch buffers, and the DevState counters.  It runs the generator phase and
 // then the bracket loop of the dimension-only orthonormalization algorithm as a
@@ -60,7 +60,7 @@ int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
 // Per-kernel-class launch counters, algorithmic work, and (optionally) HIP-event
 // durations.  Events bracket single kernel launches on the handle's stream and
-// are harvested at the driver's synchronisation points.
+// are harvested at the host loop's synchronisation points.
 struct KernelTimer {
     bool on = false;
     struct Pending {
@@ -1406,7 +1406,7 @@ const char *lie_last_error(void) { return g_last_error.c_str(); }
 // Grouped executor: every round advances each live problem by one block step,
 // and each stage of the step is one launch for all problems of the round
 // (workgroups find their problem through a prefix table).  Problems leave the
-// batch when they complete; the driver synchronises once for all problems when
+// batch when they complete; the host loop synchronises once for all problems when
 // any of them runs out of known pairs (or after 64 rounds).
 struct lie_closure_batch {
     std::vector<lie_closure *> probs;
