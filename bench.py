@@ -4,15 +4,21 @@
 One step = one complete closure (the whole bracket loop, full certification
 unless --early-exit) of the workload's generators; the generator phase of each
 step's handle runs before the timed region, so the inputs (and the first basis
-elements) are resident in HBM when timing starts.
+elements) are resident in HBM when timing starts.  The time of one closure
+including its init (allocation, generator phase) is reported beside it.
 
-Default workload: two random traceless anti-Hermitian 16 x 16 matrices
-(seed 2, Frobenius-normalised), tol 1e-10, FP64 decisions -- closure su(16),
-dim 255, 32,385 brackets per step.
+Default workload: the largest single-GPU configuration -- two random traceless
+anti-Hermitian 64 x 64 matrices (seed 5, Frobenius-normalised), tol 1e-8, full
+certification: closure su(64), dim 4095, 8,382,465 bracket checks per step,
+screened in split BF16 on the matrix cores with every decision that keeps a
+candidate taken in FP64 (certified screen), autotuned block size and tiles.
 
 Prints ONE JSON line.  `roofline` describes the dominant kernel, timed live
-with HIP events on the library's stream during the timed steps; `cpu_baseline`
-times the CPU reference on a bounded sample of the same workload.
+with HIP events on the library's stream; `cpu_baseline` times the CPU
+reference on a bounded sample of the same workload; `plain_fp64` and
+`blocked_fp64` time the one-candidate-at-a-time and blocked FP64 GPU forms of
+the same closure (extrapolated from a measured prefix when a full run would
+take minutes).
 """
 from __future__ import annotations
 
@@ -53,7 +59,7 @@ def workload(name: str):
     raise SystemExit(f"unknown workload {name}")
 
 
-def run_steps(gens, tol, cfg, steps):
+def run_steps(gens, tol, cfg, steps, budget=0):
     import torch
 
     from paper_2506_01120_amd import BatchClosure, LieClosure
@@ -75,7 +81,7 @@ def run_steps(gens, tol, cfg, steps):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for h in handles:
-        h.run()
+        h.run(budget or None)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     stats = [h.stats() for h in handles]
@@ -120,6 +126,12 @@ def roofline(stats, precision: str):
     breakdown = {k: {"ms": round(ms[k], 3), "launches": n[k], "avg_us": round(1e3 * ms[k] / n[k], 3) if n[k] else 0,
                      **cls_roof(k)}
                  for k in names if n[k]}
+    for k, b in breakdown.items():
+        # a class above its peak means its algorithmic accounting is wrong, not a fast kernel
+        if b.get("frac", 0) > 1.0:
+            b["suspect"] = True
+            print(f"[bench] WARNING: kernel class {k} reads {b['frac']:.2f} of its peak; its work accounting "
+                  f"overstates the launches' work", file=sys.stderr, flush=True)
     return {"kernel": dom, "bound": bound, "achieved": round(achieved, 4), "peak": peak, "unit": unit,
             "frac": round(achieved / peak, 5), "traffic": None,
             "algorithmic_flops_per_launch": fl[dom] / n[dom], "algorithmic_bytes_per_launch": by[dom] / n[dom],
@@ -178,21 +190,169 @@ def calibrate_copy(mib: int, copies: int = 5):
     print(json.dumps({"calibration": "device-to-device copy", "bytes_per_copy": n, "copies": copies}))
 
 
-def cpu_baseline(gens, tol, early_exit: bool, target_s: float = 10.0):
-    """The CPU reference as it stands, single-threaded, on this host: whole closures until ~target_s."""
+def _oracle_work(d: int, n: float) -> float:
+    """Flops the CPU reference spends on one candidate against n accepted elements: the two
+    naive complex products of the bracket (16 d^3) and n Householder reflectors applied to a
+    vector of d^2 complex entries (about 16 d^2 n)."""
+    return 16.0 * d ** 3 + 16.0 * d * d * n
+
+
+def cpu_sample(gens, tol, early_exit: bool, target_s: float) -> dict:
+    """The CPU reference as it stands, single-threaded: whole closures (at most three) while
+    they fit in about target_s, else a prefix of one closure in chunks of candidates."""
     from oracle import oracle as ref
 
     ref.load()
-    done, cands, t = 0, 0, 0.0
-    while t < target_s and done < 3:
+    d = int(gens.shape[-1])
+    checks, t, work, complete, n_reached = 0, 0.0, 0.0, 0, 0
+    while t < target_s and complete < 3:
         o = ref.Oracle(gens, tol)
-        t0 = time.perf_counter()
-        o.run(early_exit=early_exit)
-        t += time.perf_counter() - t0
-        cands += o.result().candidates
-        done += 1
-    return {"value": cands / t, "unit": "checks/s", "cores": 1, "kind": "oracle",
-            "sample": f"{done} complete closure(s) of the same workload, {cands} bracket checks, {t:.1f} s"}
+        c_prev = 0
+        chunk = 64 if d >= 48 else 256  # a chunk of about a second or less
+        while t < target_s:
+            n0 = o.dim
+            t0 = time.perf_counter()
+            o.run(early_exit=early_exit, budget=chunk)
+            t += time.perf_counter() - t0
+            c = o.candidates
+            work += (c - c_prev) * _oracle_work(d, 0.5 * (n0 + o.dim))
+            checks += c - c_prev
+            c_prev = c
+            n_reached = o.dim
+            if o.done:
+                break
+        if not o.done:
+            break
+        complete += 1
+    partial = complete == 0 or t >= target_s and not o.done
+    return {"checks": checks, "seconds": t, "work": work, "complete": complete, "partial": bool(partial),
+            "n_reached": n_reached}
+
+
+def cpu_baseline(gens, tol, early_exit: bool, full_checks: int, dim: int, target_s: float = 15.0,
+                 workers: int = 1, workload_name: str = "") -> dict:
+    """Oracle throughput on this host.  workers = 1: this process.  workers > 1: that many
+    single-threaded copies run concurrently as child processes (all-core throughput of
+    independent closures; one closure is sequential).  When no closure completes inside the
+    sample, the rate in flops of the flop model above is extrapolated to the whole closure."""
+    import subprocess
+
+    d = int(gens.shape[-1])
+    if workers == 1:
+        samples = [cpu_sample(gens, tol, early_exit, target_s)]
+    else:
+        cmd = [sys.executable, os.path.abspath(__file__), "--cpu-worker", "--workload", workload_name,
+               "--cpu-target-s", str(target_s)] + (["--early-exit"] if early_exit else [])
+        env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1")
+        procs = [subprocess.Popen(cmd, stdout=subprocess.PIPE, text=True, env=env) for _ in range(workers)]
+        samples = []
+        for pr in procs:
+            out, _ = pr.communicate()
+            if pr.returncode != 0:
+                raise RuntimeError(f"CPU worker failed with status {pr.returncode}")
+            samples.append(json.loads(out.strip().splitlines()[-1]))
+    checks = sum(x["checks"] for x in samples)
+    secs = max(x["seconds"] for x in samples)
+    if not any(x["partial"] for x in samples):
+        value = sum(x["checks"] / x["seconds"] for x in samples)
+        what = (f"{sum(x['complete'] for x in samples)} complete closure(s) of the same workload over "
+                f"{len(samples)} process(es), {checks} bracket checks, {secs:.1f} s")
+        return {"value": value, "unit": "checks/s", "cores": workers, "kind": "oracle", "sample": what,
+                "extrapolated": False}
+    rate = sum(x["work"] / x["seconds"] for x in samples)
+    full_work = full_checks * _oracle_work(d, dim)
+    value = full_checks / (full_work / rate)
+    n_reached = min(x["n_reached"] for x in samples)
+    what = (f"prefix of the same closure in {len(samples)} process(es): {checks} bracket checks in {secs:.1f} s, "
+            f"basis grown to {n_reached} elements, {rate / 1e9:.2f} GFLOP/s of the oracle's flop model "
+            f"16d^3 + 16d^2 N per check; extrapolated to all {full_checks} checks at N = {dim} "
+            f"(an upper bound of the CPU rate: at N = {dim} each check streams {16 * d * d * dim / 1e6:.0f} MB "
+            f"of reflectors)")
+    return {"value": value, "unit": "checks/s", "cores": workers, "kind": "oracle", "sample": what,
+            "extrapolated": True, "s_per_closure": full_work / rate}
+
+
+def host_description() -> dict:
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    cores = os.cpu_count() or 1
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        pass
+    return {"cpu_model": model, "nproc": cores, "cpu_count": os.cpu_count()}
+
+
+def gpu_form(gens, tol, cfg, full_checks: int, window_s: float = 2.0, chunk: int = 1024) -> dict:
+    """Time another GPU form of the same closure: run it to completion when it finishes within
+    about window_s past saturation, else through the growth phase (|V| reaching the ambient
+    bound) plus a window of about window_s in the saturated phase, and extrapolate the rest of
+    the closure at that window's rate (labelled)."""
+    import torch
+
+    from paper_2506_01120_amd import LieClosure
+
+    h = LieClosure(gens, tol, **cfg)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    done = False
+    while not done:
+        done = h.run(budget=chunk)
+        st = h.stats()
+        if st["dim"] >= st["ambient"]:
+            break
+    t_growth = time.perf_counter() - t0
+    c_growth = st["candidates"]
+    t1 = time.perf_counter()
+    while not done and time.perf_counter() - t1 < window_s:
+        done = h.run(budget=chunk)
+    t_end = time.perf_counter()
+    st = h.stats()
+    h.close()
+    c_end = st["candidates"]
+    if done:
+        return {"checks_per_s": c_end / (t_end - t0), "s_per_closure": t_end - t0, "extrapolated": False}
+    rate = (c_end - c_growth) / (t_end - t1)
+    total = (t_end - t0) + (full_checks - c_end) / rate
+    return {"checks_per_s": full_checks / total, "s_per_closure": total, "extrapolated": True,
+            "measured": f"{c_end} of {full_checks} checks in {t_end - t0:.2f} s (growth phase to |V| = "
+                        f"{st['dim']}: {c_growth} checks in {t_growth:.2f} s; saturated window: "
+                        f"{c_end - c_growth} checks in {t_end - t1:.2f} s)"}
+
+
+def time_with_init(gens, tol, cfg) -> dict:
+    """One closure including its init: handle creation (allocations, generator upload and phase;
+    the autotuner's choice is already cached in the process) and the bracket loop."""
+    import torch
+
+    from paper_2506_01120_amd import BatchClosure, LieClosure
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    if isinstance(gens, list):
+        h = BatchClosure([p.gens for p in gens], [p.tol for p in gens], **cfg)
+    else:
+        h = LieClosure(gens, tol, **cfg)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    h.run()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    h.close()
+    return {"init_ms": round(1e3 * (t1 - t0), 3), "run_ms": round(1e3 * (t2 - t1), 3),
+            "total_ms": round(1e3 * (t2 - t0), 3)}
+
+
+# Per-workload defaults of the screen precision: the benchmark configurations run the
+# FP64 form at d = 8 and 16, split BF16 at d = 32 and 64, and FP32 for the batch.
+DEFAULT_PRECISION = {"ising3": "fp64", "su16": "fp64", "su32": "bf16x3", "su64": "bf16x3", "batch64": "fp32",
+                     "ising7": "fp64", "sums5": "fp64"}
 
 
 def main():
@@ -200,13 +360,14 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="su16")
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16x3"])
+    ap.add_argument("--workload", default="su64")
+    ap.add_argument("--precision", default=None, choices=["fp64", "fp32", "bf16x3"],
+                    help="screen precision (default: per workload, split BF16 for su64)")
     ap.add_argument("--decide", default="screen", choices=["fp64", "strict", "screen"])
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--early-exit", action="store_true")
-    ap.add_argument("--autotune", action="store_true",
-                    help="pick the saturated block size and GEMM tiles by timing them at init (before timing)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="block size and GEMM tiles from the shape heuristics instead of timing them at init")
     ap.add_argument("--tune-cache", default=None, help="text cache of autotuner choices")
     ap.add_argument("--gemm-tile", type=int, default=0,
                     help="screening GEMM workgroup tile of saturated blocks (1: 64x64, 2: 128x128); "
@@ -219,14 +380,27 @@ def main():
                     help="pauli: the sparse Pauli-sum representation (d = 2^n, FP64)")
     ap.add_argument("--raw-basis", action="store_true",
                     help="Algorithm 3: also keep the raw basis B and bracket raw elements (single problems)")
+    ap.add_argument("--profiled-steps", type=int, default=3,
+                    help="closures of the per-kernel HIP-event pass (at most --steps)")
+    ap.add_argument("--budget", type=int, default=0,
+                    help="profiling runs only: each step runs at most this many candidates (0: whole closures)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-plain", action="store_true", help="skip the one-candidate-at-a-time FP64 comparison run")
+    ap.add_argument("--cpu-workers", type=int, default=16,
+                    help="concurrent single-threaded oracle processes of the all-core CPU figure (0: skip)")
+    ap.add_argument("--cpu-target-s", type=float, default=15.0)
+    ap.add_argument("--cpu-worker", action="store_true", help=argparse.SUPPRESS)
+    ap.add_argument("--no-plain", action="store_true", help="skip the plain and blocked FP64 comparison runs")
     ap.add_argument("--tol", type=float, default=0.0, help="override the workload's tolerance")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a device copy of MIB MiB (counter calibration) and exit")
     args = ap.parse_args()
     if args.calibrate_copy:
         calibrate_copy(args.calibrate_copy)
+        return
+    if args.cpu_worker:
+        # child process of the all-core CPU figure: the oracle only, no GPU
+        gens, tol, _ = workload(args.workload)
+        print(json.dumps(cpu_sample(gens, args.tol or tol, args.early_exit, args.cpu_target_s)))
         return
 
     if args.gpus != 1:
@@ -245,31 +419,39 @@ def main():
         if isinstance(gens, list):
             for p in gens:
                 p.tol = tol
-    cfg = dict(precision=args.precision, decide=args.decide, block=args.block, early_exit=args.early_exit,
-               autotune=args.autotune, tune_cache=args.tune_cache, raw_basis=args.raw_basis, method=args.method,
+    precision = args.precision or DEFAULT_PRECISION.get(args.workload, "fp64")
+    autotune = not args.no_autotune and args.block == 0 and args.method == "orthonormalization"
+    cfg = dict(precision=precision, decide=args.decide, block=args.block, early_exit=args.early_exit,
+               autotune=autotune, tune_cache=args.tune_cache, raw_basis=args.raw_basis, method=args.method,
                representation=args.representation, gemm_tile=args.gemm_tile)
     if args.raw_basis and args.workload == "batch64":
         raise SystemExit("--raw-basis is for single problems")
+    is_batch = isinstance(gens, list)
 
     print(f"[bench] warmup {args.warmup} x {args.workload} {cfg}", file=sys.stderr, flush=True)
     if args.warmup:
-        run_steps(gens, tol, cfg, args.warmup)
+        run_steps(gens, tol, cfg, args.warmup, args.budget)
     print(f"[bench] timed {args.steps} steps", file=sys.stderr, flush=True)
-    elapsed, stats0, dims = run_steps(gens, tol, cfg, args.steps)
+    elapsed, stats0, dims = run_steps(gens, tol, cfg, args.steps, args.budget)
     checks = sum(s["candidates"] for s in stats0)
     value = checks / elapsed
     ms_per_step = 1e3 * elapsed / args.steps
-    # per-kernel HIP events need eager launches: a second timed pass of the same steps
-    print(f"[bench] profiled {args.steps} steps (HIP events per kernel)", file=sys.stderr, flush=True)
-    elapsed_p, stats, _ = run_steps(gens, tol, dict(cfg, profile=True), args.steps)
-    roof = roofline(stats, args.precision)
-    roof["profiled_ms_per_step"] = round(1e3 * elapsed_p / args.steps, 3)
-    roof["traffic"] = measured_traffic(roof["kernel"], args.workload, args.precision)
+    full_checks = checks // args.steps
+    # per-kernel HIP events need eager launches: a second pass of (some of) the same steps
+    psteps = max(1, min(args.steps, args.profiled_steps))
+    print(f"[bench] profiled {psteps} steps (HIP events per kernel)", file=sys.stderr, flush=True)
+    elapsed_p, stats, _ = run_steps(gens, tol, dict(cfg, profile=True), psteps, args.budget)
+    roof = roofline(stats, precision)
+    roof["profiled_ms_per_step"] = round(1e3 * elapsed_p / psteps, 3)
+    roof["profiled_steps"] = psteps
+    roof["traffic"] = measured_traffic(roof["kernel"], args.workload, precision)
+    print(f"[bench] one closure including init", file=sys.stderr, flush=True)
+    with_init = time_with_init(gens, tol, cfg) if not args.budget else None
 
-    plain = None
-    if not args.no_plain:
-        plain_cfg = dict(cfg, precision="fp64", block=1, autotune=False, representation="dense")
-        if isinstance(gens, list):
+    plain = blocked = None
+    if not args.no_plain and not args.budget:
+        plain_cfg = dict(cfg, precision="fp64", block=1, autotune=False, representation="dense", gemm_tile=0)
+        if is_batch:
             # the batched workload's denominator: every problem on its own, one candidate at a time
             print("[bench] plain one-at-a-time FP64 comparison: each problem alone", file=sys.stderr, flush=True)
             pt, pc = 0.0, 0
@@ -277,17 +459,32 @@ def main():
                 t, ps, _ = run_steps(p.gens, p.tol, plain_cfg, 1)
                 pt += t
                 pc += ps[0]["candidates"]
-            plain = {"checks_per_s": pc / pt, "ms_per_step": 1e3 * pt, "form": "each problem alone, block 1, FP64"}
+            plain = {"checks_per_s": pc / pt, "s_per_closure": pt, "form": "each problem alone, block 1, FP64",
+                     "extrapolated": False}
+            print("[bench] blocked FP64 comparison: the batch in FP64", file=sys.stderr, flush=True)
+            bt, bs, _ = run_steps(gens, tol, dict(cfg, precision="fp64", gemm_tile=0), 1)
+            blocked = {"checks_per_s": bs[0]["candidates"] / bt, "s_per_closure": bt,
+                       "form": "grouped batch, FP64 decisions and projections", "extrapolated": False}
         else:
-            print("[bench] plain one-at-a-time FP64 comparison step", file=sys.stderr, flush=True)
-            pt, pstats, _ = run_steps(gens, tol, plain_cfg, 1)
-            plain = {"checks_per_s": pstats[0]["candidates"] / pt, "ms_per_step": 1e3 * pt,
-                     "form": "block 1, FP64"}
+            print("[bench] plain one-at-a-time FP64 comparison", file=sys.stderr, flush=True)
+            plain = dict(gpu_form(gens, tol, plain_cfg, full_checks), form="block 1, FP64")
+            print("[bench] blocked FP64 comparison", file=sys.stderr, flush=True)
+            blocked = dict(gpu_form(gens, tol, dict(cfg, precision="fp64", gemm_tile=0), full_checks,
+                                    chunk=16384), form="adaptive blocks, FP64, autotuned" if autotune else
+                           "adaptive blocks, FP64")
 
-    cpu = None
-    if not args.no_cpu_baseline:
-        print("[bench] CPU reference baseline", file=sys.stderr, flush=True)
-        cpu = cpu_baseline(gens, tol, args.early_exit)
+    cpu = cpu_all = None
+    host = host_description()
+    if not args.no_cpu_baseline and not is_batch and not args.budget:
+        print("[bench] CPU reference baseline (one thread)", file=sys.stderr, flush=True)
+        dim0 = dims[0]
+        cpu = cpu_baseline(gens, tol, args.early_exit, full_checks, dim0, args.cpu_target_s)
+        cpu["host"] = host
+        workers = min(args.cpu_workers, host["nproc"])
+        if workers > 1:
+            print(f"[bench] CPU reference, {workers} concurrent processes", file=sys.stderr, flush=True)
+            cpu_all = cpu_baseline(gens, tol, args.early_exit, full_checks, dim0, args.cpu_target_s, workers,
+                                   args.workload)
 
     out = {
         "metric": METRIC,
@@ -300,26 +497,32 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.precision == "fp64" else ("f32+f64" if args.precision == "fp32" else "bf16x3+f64"),
+        "dtype": "f64" if precision == "fp64" else ("f32+f64" if precision == "fp32" else "bf16x3+f64"),
         "data": "synthetic (seeded generators)",
         "config": {"workload": desc,
-                   "d": (int(gens.shape[-1]) if not isinstance(gens, list) else "8..128"),
-                   "n_gen": (int(gens.shape[0]) if not isinstance(gens, list) else "2..13"), "tol": tol,
-                   "dim": (dims[0] if not isinstance(gens, list) else sum(dims[0])),
-                   "checks_per_step": checks // args.steps, "precision": args.precision,
-                   "decide": args.decide if args.precision != "fp64" else "fp64",
+                   "d": (int(gens.shape[-1]) if not is_batch else "8..128"),
+                   "n_gen": (int(gens.shape[0]) if not is_batch else "2..13"), "tol": tol,
+                   "dim": (dims[0] if not is_batch else sum(dims[0])),
+                   "checks_per_step": full_checks, "precision": precision,
+                   "decide": args.decide if precision != "fp64" else "fp64",
                    "block": stats0[0]["block"], "block_growth": stats0[0]["block_growth"],
                    "tile_dot": stats0[0]["tile_dot"], "tile_sub": stats0[0]["tile_sub"],
                    "autotuned": stats0[0]["autotuned"], "early_exit": bool(args.early_exit),
+                   "budget_per_step": args.budget or None,
                    "representation": args.representation,
                    "algorithm": ("Algorithm 1, SVD rank test (baseline)" if args.method == "rank_svd" else
                                  "Algorithm 2, matrix inversion" if args.method == "matrix_inversion" else
                                  "Algorithm 3 (raw basis kept)" if args.raw_basis else "Algorithm 4 (dimension only)"),
                    "parallelism": "single GPU"},
+        "time_to_closure_ms": round(ms_per_step, 3),
+        "time_to_closure_with_init": with_init,
         "roofline": roof,
         "cpu_baseline": cpu,
+        "cpu_baseline_all_cores": cpu_all,
         "plain_fp64": plain,
+        "blocked_fp64": blocked,
         "speedup_vs_plain_fp64": round(value / plain["checks_per_s"], 2) if plain else None,
+        "speedup_vs_blocked_fp64": round(value / blocked["checks_per_s"], 2) if blocked else None,
     }
     print(json.dumps(out))
 

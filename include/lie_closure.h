@@ -20,9 +20,12 @@
  * basis elements is kept iff ||h_perp|| > tol.  Exactly zero brackets are
  * rejected.
  *
- * All device work runs in the library's own HIP kernels on one GPU.  Host
- * pointers are plain CPU memory; device pointers are HIP device memory of the
- * handle's device.  No function throws; every failure returns a negative
+ * The orthonormalization method (the default; Algorithms 3 and 4) runs all of
+ * its device work in the library's own HIP kernels on one GPU.  The comparison
+ * method LIE_METHOD_RANK_SVD takes its singular values from rocSOLVER (that
+ * library SVD is what the baseline is), and LIE_METHOD_MATRIX_INVERSION forms
+ * and applies the inverse Gram matrix with rocBLAS and rocSOLVER.  Host pointers are plain CPU memory;
+ * device pointers are HIP device memory of the handle's device.  No function throws; every failure returns a negative
  * lie_status and records a message readable with lie_last_error().
  *
  * Threading: a handle is not thread-safe; distinct handles are independent.
@@ -87,11 +90,26 @@ typedef enum lie_representation {
     LIE_REP_PAULI = 1
 } lie_representation;
 
-/* How a screened candidate is decided (ignored for LIE_PREC_FP64). */
+/* How a screened candidate is decided (ignored for LIE_PREC_FP64).
+ *
+ * A screened residual carries rounding of about 1e-7 (FP32) to 1e-5 (split BF16) of the candidate's
+ * scale, far above a threshold such as tol = 1e-8, so a small screened residual never proves that
+ * the FP64 residual is at most tol (a weakly coupled direction of the closure screens as small as
+ * noise).  Dependence is proved instead by the basis size: once |V| equals the ambient bound
+ * (d^2 - 1 for traceless generators, else d^2) V spans every operator a bracket can produce and
+ * every candidate is dependent.  STRICT and SCREEN therefore reject from the screen only at the
+ * ambient bound ("certified"); below it every candidate is decided from its FP64 residual (those
+ * blocks run the FP64 step directly).  Decisions then equal those of the FP64 path. */
 typedef enum lie_decide {
-    LIE_DECIDE_FP64 = 0,   /* every candidate is decided from its FP64 residual (screen used for nothing) */
-    LIE_DECIDE_STRICT = 1, /* screened residual <= tol/100 rejects; every other candidate is decided in FP64 */
-    LIE_DECIDE_SCREEN = 2  /* screened residual < tau_rej rejects; the rest are decided in FP64 */
+    LIE_DECIDE_FP64 = 0,   /* every candidate is decided from its FP64 residual; the screen is computed on
+                              saturated blocks and only recorded (screen_max_dependent / _min_independent) */
+    LIE_DECIDE_STRICT = 1, /* certified; at the ambient bound a screened residual below 100 * tol rejects,
+                              every other candidate is decided in FP64 */
+    LIE_DECIDE_SCREEN = 2  /* certified; at the ambient bound a screened residual below the precision's
+                              threshold (1e-4 FP32, 1e-2 split BF16) rejects, the rest are decided in FP64.
+                              With config.tau_rej > 0 that threshold rejects at every basis size: an
+                              approximate, uncertified screen (a candidate whose FP64 residual exceeds tol
+                              but screens below tau_rej is lost) */
 } lie_decide;
 
 typedef struct lie_closure_config {
@@ -104,7 +122,8 @@ typedef struct lie_closure_config {
                               screened blocks after) */
     int32_t early_exit;    /* 1: stop once |V| equals the ambient bound (exact; d^2-1 for traceless inputs) */
     int32_t device;        /* HIP device ordinal; -1 = the calling thread's current device */
-    double tau_rej;        /* SCREEN reject threshold on the screened residual; 0 = precision default */
+    double tau_rej;        /* SCREEN: 0 = certified screen with the precision's threshold; > 0 = this threshold,
+                              applied at every basis size (approximate; see lie_decide) */
     int64_t max_dim;       /* basis capacity; 0 = ambient bound */
     void *stream;          /* hipStream_t the handle runs on; NULL = a stream the library creates */
     int32_t use_graphs;    /* 1: replay block steps from captured hipGraphs (default 1) */

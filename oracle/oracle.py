@@ -154,6 +154,11 @@ class Oracle:
     def done(self) -> bool:
         return bool(self.lib.lo_done(self._s))
 
+    @property
+    def candidates(self) -> int:
+        """Bracket candidates evaluated so far."""
+        return int(self.lib.lo_candidates(self._s))
+
     def basis(self) -> np.ndarray:
         n = self.dim
         out = np.empty((n, self.d, self.d), dtype=np.complex128)

@@ -49,9 +49,14 @@ constexpr int kGemvRows = 16;
 thread_local bool t_batch_member = false;
 // Block steps enqueued between two synchronisations: growth-size blocks, saturated blocks.
 constexpr int kGrowthQueued = 4;
-// Default SCREEN reject threshold on the FP32-screened residual (paper norm).
+// SCREEN threshold on the FP32-screened residual (paper norm) once the basis is at the ambient
+// bound: below it a candidate is rejected without FP64 work (every candidate is dependent there),
+// at or above it the candidate is re-checked in FP64.  It lies far above the screen's rounding
+// (dependent candidates screen at <= 2e-6) and far below the residual of any candidate that is
+// independent of a basis short of the bound; with config.tau_rej > 0 the given value is applied
+// at every basis size instead (an uncertified, approximate screen).
 constexpr double kDefaultTauFp32 = 1e-4;
-// Default SCREEN reject threshold on the split-BF16-screened residual.
+// The same threshold for the split-BF16 screen (dependent candidates screen at <= 2e-5).
 constexpr double kDefaultTauBf16x3 = 1e-2;
 constexpr int kMaxBlock = 16384;
 constexpr int kMaxD = 128;
@@ -153,6 +158,7 @@ struct lie_closure {
     bool screened = false;   // FP32 screening pass in front of the FP64 decisions
     int policy = lie::POL_ALL;
     double policy_thr = 0.0;
+    bool certify = false;    // screen rejections only at the ambient bound (see classify_body)
     // device
     int device = -1;
     hipStream_t stream = nullptr;
@@ -286,7 +292,10 @@ struct lie_closure {
                        int64_t n_hi, int kid_dot, int kid_sub, int kid_red)
     {
         lie::ProjShape sh{D, cnt, std::min(std::max<int64_t>(n_hi, 1), cap)};
-        const double N = (double)n_lo, Dd = (double)D, c = cnt, w = sizeof(double);
+        // verification passes run over the device-side survivor count: their work is accounted
+        // by the acceptance kernel from that count (DevState::vfy_flops / vfy_bytes)
+        const double acc = kid_dot == LIE_K_VERIFY ? 0.0 : 1.0;
+        const double N = acc * (double)n_lo, Dd = (double)D, c = acc * cnt, w = sizeof(double);
         if (cnt > kGemvRows) {
             // matrix-core path: coefficients, then residual with fused norms, then the norm sums;
             // the coefficient rows span the capacity so that any basis size fits
@@ -328,17 +337,19 @@ struct lie_closure {
         return LIE_OK;
     }
 
-    lie_status classify(int cnt, int64_t p0, int pol, double thr, const int64_t *dp0 = nullptr)
+    lie_status classify(int cnt, int64_t p0, int pol, double thr, const int64_t *dp0 = nullptr, bool cert = false)
     {
         timer.begin(stream);
         HIP_TRY(lie::launch_classify(cand_a2, cand_n2, cnt, p0, pol, thr, st, surv_rows, surv_pairs, slot, nsurv,
-                                     stream, dp0));
+                                     stream, dp0, ambient, cert ? 1 : 0));
         timer.end(LIE_K_REDUCE, stream, 0, 0);
         return LIE_OK;
     }
 
+    // vpasses / vbracket: the FP64 verification the survivors went through before this launch
+    // (projection passes, recomputed bracket), accounted by the kernel from the survivor count.
     lie_status accept(int cnt, int mode, bool screen_first, const int *rrow, const double *h2_surv, int kid,
-                      int64_t src0 = 0)
+                      int64_t src0 = 0, int vpasses = 0, int vbracket = 0)
     {
         lie::AcceptArgs a{};
         a.V = V64;
@@ -368,6 +379,9 @@ struct lie_closure {
         a.screened = screen_first ? 1 : 0;
         a.early_exit = mode == 1 ? cfg.early_exit : 0;
         a.lds_doubles = lie::accept_lds_doubles(cnt, D);
+        a.vpasses = vpasses;
+        a.vbracket = vbracket;
+        a.d = d;
         timer.begin(stream);
         HIP_TRY(lie::launch_accept_f64(a, stream));
         timer.end(kid, stream, 0, 0);
@@ -488,7 +502,7 @@ struct lie_closure {
         if ((s = project(surv_rows, nsurv, rho2, h2b, cnt, 0, n_hi, LIE_K_VERIFY, LIE_K_VERIFY, LIE_K_VERIFY)) !=
             LIE_OK)
             return s;
-        return accept(cnt, 1, false, surv_rows, nullptr, LIE_K_ACCEPT);
+        return accept(cnt, 1, false, surv_rows, nullptr, LIE_K_ACCEPT, 0, 1, 0);
     }
 
     // Screened block step: FP32 bracket and projection on MFMA, classification,
@@ -519,7 +533,7 @@ struct lie_closure {
                                        st, cand_a2, nullptr, stream));
         timer.end(LIE_K_REDUCE, stream, 0, 0);
         lie_status s;
-        if ((s = classify(cnt, cursor, policy, policy_thr, dp0)) != LIE_OK)
+        if ((s = classify(cnt, cursor, policy, policy_thr, dp0, certify)) != LIE_OK)
             return s;
         timer.begin(stream);
         HIP_TRY(lie::launch_comm_f64(raw ? B64 : V64, d, 0, surv_pairs, nsurv, cnt, st, H64, stream));
@@ -528,7 +542,7 @@ struct lie_closure {
             return s;
         if ((s = project(nullptr, nsurv, rho2, h2b, cnt, 0, n_hi, LIE_K_VERIFY, LIE_K_VERIFY, LIE_K_VERIFY)) != LIE_OK)
             return s;
-        return accept(cnt, 1, policy != lie::POL_ALL, nullptr, h2, LIE_K_ACCEPT);
+        return accept(cnt, 1, policy != lie::POL_ALL, nullptr, h2, LIE_K_ACCEPT, 0, 2, 1);
     }
 
     // Capture one block step (kernels reading the pair cursor from d_cursor, then
@@ -830,9 +844,10 @@ struct lie_closure {
             }
             const int cnt = (int)std::min<int64_t>(cur, avail - cursor);
             const int64_t n_hi = std::min<int64_t>(cap, n_lo + queued_rows);
-            // while most candidates are accepted the screen filters nothing: decide in FP64 directly
+            // while most candidates are accepted the screen filters nothing: decide in FP64 directly;
+            // a certified screen rejects nothing below the ambient bound, so it waits for it too
             const bool growth = block == 0 && cur == block_growth;
-            const bool screen_step = screened && !growth;
+            const bool screen_step = screened && !growth && (!certify || n_lo >= ambient);
             // full-size steps of the steady state replay a captured graph; the grid bound
             // is the synchronised basis size (the coefficient GEMMs stride beyond it)
             const bool steady = cnt == cur && !growth && cnt > kGemvRows && cfg.use_graphs && !timer.on;
@@ -1022,13 +1037,16 @@ lie_status lie_closure_init(lie_closure **out, const double *generators, int32_t
             h->policy = lie::POL_ALL;
             break;
         case LIE_DECIDE_STRICT:
-            h->policy = lie::POL_ABS;
-            h->policy_thr = tol / 100.0;
+            // certified; at the ambient bound only screened residuals below 100 * tol skip FP64
+            h->policy = lie::POL_GE;
+            h->policy_thr = 100.0 * tol;
+            h->certify = true;
             break;
         default:
             h->policy = lie::POL_GE;
             h->policy_thr = cfg.tau_rej > 0 ? cfg.tau_rej
                                             : (cfg.precision == LIE_PREC_BF16X3 ? kDefaultTauBf16x3 : kDefaultTauFp32);
+            h->certify = !(cfg.tau_rej > 0);  // an explicit threshold is applied uncertified
             break;
         }
     }
@@ -1041,9 +1059,7 @@ lie_status lie_closure_init(lie_closure **out, const double *generators, int32_t
     h->raw = cfg.raw_basis != 0 || cfg.method != LIE_METHOD_ORTHONORMALIZATION;  // the other methods keep B
     if (h->raw) {
         // Algorithm 3: raw brackets have no fixed scale, so every threshold is relative to ||h||
-        if (h->policy == lie::POL_ABS)
-            h->policy = lie::POL_REL;
-        else if (h->policy == lie::POL_GE)
+        if (h->policy == lie::POL_GE)
             h->policy = lie::POL_GE_REL;
     }
     h->cap = cfg.max_dim > 0 ? std::min<int64_t>(cfg.max_dim, h->D) : std::max<int64_t>(ambient, 1);
@@ -1374,6 +1390,9 @@ lie_status lie_closure_stats_get(const lie_closure *h, lie_closure_stats *out)
         const double D = (double)h->D;
         out->kernel_bytes[LIE_K_ACCEPT] = 20.0 * (double)h->hs.n_cand + 8.0 * D * (double)h->hs.n_rows +
                                           (8.0 + (h->screened ? 4.0 : 0.0)) * D * (double)h->hs.n_acc;
+        // the FP64 verification passes run over device-side survivor counts as well
+        out->kernel_flops[LIE_K_VERIFY] = h->hs.vfy_flops;
+        out->kernel_bytes[LIE_K_VERIFY] = h->hs.vfy_bytes;
     }
     return LIE_OK;
 }
@@ -1608,7 +1627,8 @@ struct lie_closure_batch {
                 const int cnt = (int)std::min<int64_t>(h->b_cur, avail - h->cursor);
                 const int64_t n_hi = std::min<int64_t>(h->cap, h->b_nlo + h->b_qrows);
                 const bool growth = h->block == 0 && h->b_cur == h->block_growth;
-                (h->screened && !growth ? scr : f64).push_back(Item{h, cnt, n_hi});
+                const bool screen = h->screened && !growth && (!h->certify || h->b_nlo >= h->ambient);
+                (screen ? scr : f64).push_back(Item{h, cnt, n_hi});
             }
             if (f64.empty() && scr.empty())
                 break;
@@ -1747,7 +1767,8 @@ struct lie_closure_batch {
             const int pol = screen ? h->policy : lie::POL_ABS;
             const double thr = screen ? h->policy_thr : h->tol;
             g.add(lie::ClassifyArgs{h->cand_a2, h->cand_n2, it.cnt, h->cursor, nullptr, pol, thr, h->st,
-                                    h->surv_rows, h->surv_pairs, h->slot, h->nsurv},
+                                    h->surv_rows, h->surv_pairs, h->slot, h->nsurv, h->ambient,
+                                    screen && h->certify ? 1 : 0},
                   1, 1);
         }
         return record(CLASSIFY, g, false, 0, LIE_K_REDUCE, 0);
@@ -1781,6 +1802,9 @@ struct lie_closure_batch {
             a.mode = 1;
             a.screened = screen && h->policy != lie::POL_ALL ? 1 : 0;
             a.early_exit = h->cfg.early_exit;
+            a.vpasses = screen ? 2 : 1;
+            a.vbracket = screen ? 1 : 0;
+            a.d = h->d;
             a.lds_doubles = 0;  // set below to the launch-wide size
             g.add(a, 1, 1);
             lds_acc = std::max<int64_t>(lds_acc, lie::accept_lds_doubles(it.cnt, h->D));
@@ -2034,7 +2058,7 @@ lie_status lie_closure_batch_stats_get(const lie_closure_batch *b, int32_t i, li
     agg.done = b->done ? 1 : 0;
     agg.min_accepted_residual = INFINITY;
     agg.screen_min_independent = INFINITY;
-    double acc_bytes = 0.0;  // acceptance bytes come from each problem's counters
+    double acc_bytes = 0.0, vfy_flops = 0.0, vfy_bytes = 0.0;  // from each problem's device counters
     for (lie_closure *h : b->probs) {
         lie_closure_stats one;
         one.struct_size = sizeof one;
@@ -2062,6 +2086,8 @@ lie_status lie_closure_batch_stats_get(const lie_closure_batch *b, int32_t i, li
         agg.tile_sub = one.tile_sub;
         agg.autotuned = std::max(agg.autotuned, one.autotuned);
         acc_bytes += one.kernel_bytes[LIE_K_ACCEPT];
+        vfy_flops += one.kernel_flops[LIE_K_VERIFY];
+        vfy_bytes += one.kernel_bytes[LIE_K_VERIFY];
     }
     agg.blocks = b->rounds;
     agg.host_syncs = b->host_syncs;
@@ -2073,6 +2099,8 @@ lie_status lie_closure_batch_stats_get(const lie_closure_batch *b, int32_t i, li
         agg.kernel_bytes[k] = b->timer.bytes[k];
     }
     agg.kernel_bytes[LIE_K_ACCEPT] = acc_bytes;
+    agg.kernel_flops[LIE_K_VERIFY] = vfy_flops;
+    agg.kernel_bytes[LIE_K_VERIFY] = vfy_bytes;
     *out = agg;
     return LIE_OK;
 }

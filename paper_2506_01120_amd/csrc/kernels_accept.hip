@@ -957,6 +957,18 @@ __device__ __forceinline__ void accept_body(const AcceptArgs &a)
         st->min_acc = fmin(s0.min_acc, l_minacc);
         st->scr_max_dep = fmax(s0.scr_max_dep, l_sdep);
         st->scr_min_indep = fmin(s0.scr_min_indep, l_sind);
+        // work of the FP64 verification of this block's ns survivors against the N0-element
+        // snapshot: per projection pass 2 N0 D flops for the coefficients and 2 N0 D for the
+        // subtraction; bytes per pass: the basis streamed by both GEMMs, the rows read by both
+        // and written once, the coefficients written and read; the recomputed bracket (one
+        // complex product, 8 d^3 flops) reads two operands and writes one row
+        if (a.vpasses > 0 && ns > 0) {
+            const double n = (double)ns, Nd = (double)N0, Dd = (double)D, dd = (double)a.d;
+            const double br = a.vbracket ? 1.0 : 0.0;
+            st->vfy_flops = s0.vfy_flops + n * (a.vpasses * 4.0 * Nd * Dd + br * 8.0 * dd * dd * dd);
+            st->vfy_bytes = s0.vfy_bytes + 8.0 * (a.vpasses * (2.0 * Nd * Dd + 3.0 * n * Dd + 2.0 * n * Nd) +
+                                                  br * 3.0 * n * Dd);
+        }
         st->N = sN;
     }
 }

@@ -242,6 +242,18 @@ __global__ void __launch_bounds__(kThreads) k_comm_f32_reg_b(Batch b)
 // One workgroup of 1024 threads walks the block in chunks of 1024 candidates.
 // Survivors are written in candidate order: rows[r] = c, pairs[r] = p0 + c,
 // and slot[c] = r (or -1); *nsurv receives their count.
+//
+// Certified screening (A.certify = 1).  A screened residual carries rounding of
+// order 1e-7 (FP32) to 1e-5 (split BF16) of the candidate's scale, far above the
+// FP64 threshold tol, so a small screened residual does not prove that the FP64
+// residual is at most tol: a direction of the closure that couples only weakly
+// screens as small as rounding noise.  What does prove dependence is the basis
+// size: once |V| equals the ambient bound (d^2 - 1 for traceless operators,
+// d^2 otherwise) V spans every operator a bracket can produce, so every
+// candidate is dependent.  With certify set, the policy therefore rejects only
+// while st->N >= ambient; there its threshold only separates the candidates
+// whose screen looks healthy from those re-checked in FP64.  Below the bound
+// every candidate survives to the FP64 decision.
 __device__ void classify_body(const ClassifyArgs &A)
 {
     const double *a2 = A.a2, *n2 = A.n2;
@@ -258,6 +270,7 @@ __device__ void classify_body(const ClassifyArgs &A)
     __shared__ int wbase[16];
     __shared__ int running;
     const bool ab = aborted(st);
+    const bool below_bound = A.certify && st->N < A.ambient;  // no rejection can be certified yet
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     if (threadIdx.x == 0)
         running = 0;
@@ -277,6 +290,7 @@ __device__ void classify_body(const ClassifyArgs &A)
                 case POL_GE: keep = h > 0.0 && r >= thr; break;
                 case POL_GE_REL: keep = h > 0.0 && r >= thr * h; break;
                 }
+                keep = keep || below_bound;
             }
         }
         const unsigned long long mask = __ballot(keep);
@@ -355,12 +369,12 @@ hipError_t launch_comm_f32_batched(const Batch &b, bool lds_variant, int dmax, h
 
 hipError_t launch_classify(const double *a2, const double *n2, int cnt, int64_t p0, int policy, double thr,
                            const DevState *st, int *rows, int64_t *pairs, int *slot, int *nsurv, hipStream_t s,
-                           const int64_t *dp0)
+                           const int64_t *dp0, int64_t ambient, int certify)
 {
     if (cnt <= 0)
         return hipSuccess;
     const int threads = cnt >= 1024 ? 1024 : ((cnt + 63) / 64) * 64;
-    ClassifyArgs a{a2, n2, cnt, p0, dp0, policy, thr, st, rows, pairs, slot, nsurv};
+    ClassifyArgs a{a2, n2, cnt, p0, dp0, policy, thr, st, rows, pairs, slot, nsurv, ambient, certify};
     hipLaunchKernelGGL(k_classify, dim3(1), dim3(threads), 0, s, a);
     return hipGetLastError();
 }

@@ -40,6 +40,8 @@ struct DevState {
     int64_t n_bqr;           // appended by the block Cholesky-QR prefix of the acceptance kernel
     int64_t n_rows;          // survivor residual rows read by the acceptance kernel's in-block decisions
     int64_t raw_lo;          // Algorithm 3: |V| when the last acceptance launch started (raw rows from here on)
+    double vfy_flops;        // algorithmic flops of the FP64 verification of survivors (bracket + passes)
+    double vfy_bytes;        // algorithmic bytes of the same
 };
 
 // Pair index p <-> (l, m) with 0 <= m < l: p = l(l-1)/2 + m.  Row l holds the
@@ -156,6 +158,8 @@ struct ClassifyArgs {
     int64_t *pairs;
     int *slot;
     int *nsurv;
+    int64_t ambient;           // the ambient bound (d^2 - 1 or d^2) of the problem
+    int certify;               // 1: the policy may reject only while st->N >= ambient (see classify_body)
 };
 
 struct GemmArgs {
@@ -256,6 +260,9 @@ struct AcceptArgs {
     int screened;            // 1: non-survivors were rejected by the screen
     int early_exit;
     int64_t lds_doubles;     // dynamic LDS of the launch, in doubles (accept_lds_doubles)
+    int vpasses;             // FP64 projection passes the block's survivors went through before this launch
+    int vbracket;            // 1: the survivors' brackets were recomputed in FP64 before those passes
+    int d;                   // matrix size (bracket work of vbracket)
 };
 hipError_t launch_accept_f64(const AcceptArgs &args, hipStream_t s);
 // Dynamic LDS (doubles) for an acceptance launch of cnt candidates of length D.
@@ -350,10 +357,12 @@ hipError_t launch_gemm_sub_bf16x3_batched(const Batch &b, hipStream_t s);
 // Hs[c] = fp32 packed [Vs_l, Vs_m] for pair p0 + c, hs2[c] = ||Hs[c]||^2.
 hipError_t launch_comm_f32(const float *Vs, int d, int64_t p0, int cnt, const DevState *st, float *Hs, double *hs2,
                            hipStream_t s, const int64_t *dp0 = nullptr);
-// Survivor compaction under a policy (cnt <= 1024).
+// Survivor compaction under a policy.  certify = 1: a candidate may be rejected by the policy
+// only while the basis holds `ambient` elements (then it is dependent whatever its residual);
+// below that bound every candidate survives.
 hipError_t launch_classify(const double *a2, const double *n2, int cnt, int64_t p0, int policy, double thr,
                            const DevState *st, int *rows, int64_t *pairs, int *slot, int *nsurv, hipStream_t s,
-                           const int64_t *dp0 = nullptr);
+                           const int64_t *dp0 = nullptr, int64_t ambient = 0, int certify = 0);
 
 // ------------------------------------------------------------- rank-test baseline (rank_svd.hip)
 // Standard algorithm (Algorithm 1): a candidate raises the rank of the raw basis iff the

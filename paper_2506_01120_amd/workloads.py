@@ -27,6 +27,8 @@ __all__ = [
     "rand_pair",
     "batch_problems",
     "Problem",
+    "weak_coupling",
+    "embed",
 ]
 
 _P1 = {
@@ -181,3 +183,40 @@ def batch_problems(tol: float = 1e-8, count: int = 64) -> list[Problem]:
             d = 8 + (i - 38) % 17
             probs.append(Problem(f"pair{d}s{seed}", rand_pair(d, seed), tol, d * d - 1))
     return probs
+
+
+def weak_coupling(eps: float, seed: int = 7) -> np.ndarray:
+    """Two d = 16 generators A (+) 0 and B (+) eps*C, with A, B = rand_pair(8, seed) in the upper
+    block and C = i diag(1, -1, 0, ..., 0) in the lower one.  The closure is su(8) (+) span(0 (+) C),
+    dim 64; the direction 0 (+) C enters only through the small eps, so the candidate that adds it
+    has a residual of a few eps -- a closure whose last direction couples weakly."""
+    a, b = rand_pair(8, seed)
+    c = np.zeros((8, 8), dtype=np.complex128)
+    c[0, 0], c[1, 1] = 1j, -1j
+    g = np.zeros((2, 16, 16), dtype=np.complex128)
+    g[0, :8, :8] = a
+    g[1, :8, :8] = b
+    g[1, 8:, 8:] = eps * c
+    return g
+
+
+def embed(gens: np.ndarray, d: int, seed: int | None = None) -> np.ndarray:
+    """Generators of size k placed in the upper-left k x k block of d x d zero matrices (d >= k),
+    then, with a seed, conjugated by one seeded random unitary U (QR of a complex Gaussian matrix):
+    g -> U g U^H.  Conjugation keeps anti-Hermiticity, traces and the closure's dimension and
+    spreads every element over the whole d x d matrix, so a closure of a small algebra exercises
+    kernels at any d with dense operands."""
+    gens = np.asarray(gens, dtype=np.complex128)
+    k = gens.shape[-1]
+    if d < k:
+        raise ValueError("d must be at least the generators' size")
+    out = np.zeros((gens.shape[0], d, d), dtype=np.complex128)
+    out[:, :k, :k] = gens
+    if seed is not None:
+        rng = np.random.default_rng(seed)
+        z = rng.standard_normal((d, d)) + 1j * rng.standard_normal((d, d))
+        q, r = np.linalg.qr(z)
+        u = q * (np.diag(r) / np.abs(np.diag(r)))  # a unitary with a fixed phase convention
+        out = u[None] @ out @ u.conj().T[None]
+        out = 0.5 * (out - np.conj(np.swapaxes(out, 1, 2)))  # exactly anti-Hermitian after rounding
+    return out

@@ -1,0 +1,150 @@
+"""GPU: certified screening decisions and the quality report, checked independently.
+
+Certified screening.  A screened residual (FP32 or split BF16) carries rounding far above
+tol = 1e-8, so it can prove a candidate dependent only where every candidate is dependent:
+at the ambient bound (|V| = d^2 - 1 for traceless generators).  The weak-coupling closure
+[A (+) 0, B (+) eps C] (dim 64 at d = 16, ambient bound 255) adds its last direction through
+a candidate whose FP64 residual is only about 5.6 eps.  Every precision and decision mode
+must return the CPU reference's dimension and basis on it, at eps = 1e-4 (below the default
+split-BF16 threshold 1e-2) and eps = 1e-6 (below the FP32 one, 1e-4).
+
+Quality report.  The device value of ||V^H V - I||_F (lie_closure_orthogonality) is compared
+with the same quantity formed by numpy from the returned basis; the residual-gap statistics
+(smallest accepted FP64 residual) with the CPU reference's.
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import pins
+from oracle import oracle as O
+from paper_2506_01120_amd import LieClosure, workloads as W
+
+pytestmark = pytest.mark.gpu
+
+ELEM_TOL = 1e-8
+DEFAULT_TAU = {"fp32": 1e-4, "bf16x3": 1e-2}
+
+_REF = {}
+
+
+def reference(gens, tol, early_exit=False):
+    key = (gens.tobytes(), gens.shape, tol, early_exit)
+    if key not in _REF:
+        _REF[key] = O.closure(gens, tol, early_exit=early_exit)
+    return _REF[key]
+
+
+def gpu_run(gens, tol, budget=None, **cfg):
+    print(f"[gpu] d={gens.shape[-1]} n_gen={len(gens)} tol={tol} budget={budget} cfg={cfg}", flush=True)
+    with LieClosure(gens, tol, **cfg) as lc:
+        lc.run(budget)
+        return lc.dim, lc.basis(), lc.stats(), lc.orthogonality()
+
+
+MODES = [("fp64", "fp64"), ("fp32", "fp64"), ("fp32", "strict"), ("fp32", "screen"),
+         ("bf16x3", "fp64"), ("bf16x3", "strict"), ("bf16x3", "screen")]
+
+
+@pytest.mark.parametrize("eps", [1e-4, 1e-6])
+@pytest.mark.parametrize("block", [0, 256])
+@pytest.mark.parametrize("precision,decide", MODES)
+def test_weak_coupling_direction_kept(eps, block, precision, decide):
+    gens = W.weak_coupling(eps)
+    ref = reference(gens, 1e-8)
+    assert ref.dim == 64
+    dim, v, st, orth = gpu_run(gens, 1e-8, precision=precision, decide=decide, block=block)
+    assert dim == ref.dim == 64, (dim, st)
+    assert st["candidates"] == ref.candidates
+    assert np.max(np.abs(v - ref.basis)) <= ELEM_TOL
+    assert orth <= 1e-10
+    # below the ambient bound no candidate may be rejected from a screened residual alone
+    assert st["screen_rejected"] == 0
+    # the weak direction's residual, as the reference measures it
+    assert abs(st["min_accepted_residual"] - ref.min_accepted) <= 1e-6 * ref.min_accepted
+    assert 4 * eps < ref.min_accepted < 8 * eps
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_certified_screen_rejects_only_at_ambient_bound(precision):
+    """su(16), full certification: every screen rejection happens once |V| = 255, and the
+    result equals the reference's element by element."""
+    gens = W.rand_pair(16, seed=2)
+    ref = reference(gens, 1e-10)
+    dim, v, st, orth = gpu_run(gens, 1e-10, precision=precision, decide="screen")
+    assert dim == ref.dim == 255 and st["candidates"] == ref.candidates
+    assert np.max(np.abs(v - ref.basis)) <= ELEM_TOL
+    # the saturated phase is where the candidates are: nearly all of them are screen-rejected
+    assert st["screen_rejected"] > 0.9 * st["candidates"]
+    assert st["max_screen_rejected"] < DEFAULT_TAU[precision]
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_explicit_tau_is_applied_everywhere(precision):
+    """config.tau_rej > 0 (the uncertified screen) rejects below the bound as well; on su(16) the
+    default thresholds lie inside the residual gap, so the result still equals the reference."""
+    gens = W.rand_pair(16, seed=2)
+    ref = reference(gens, 1e-10)
+    dim, v, st, _ = gpu_run(gens, 1e-10, precision=precision, decide="screen", block=256,
+                            tau_rej=DEFAULT_TAU[precision])
+    assert dim == ref.dim == 255
+    assert np.max(np.abs(v - ref.basis)) <= ELEM_TOL
+
+
+def test_uncertified_screen_loses_the_weak_direction():
+    """The failure the certification prevents, shown with the uncertified split-BF16 screen:
+    the weak direction (FP64 residual 5.6e-4) screens below tau_rej = 1e-2 and is lost."""
+    gens = W.weak_coupling(1e-4)
+    dim, _, st, _ = gpu_run(gens, 1e-8, precision="bf16x3", decide="screen", block=256, tau_rej=1e-2)
+    assert dim == 63, (dim, st)
+
+
+@pytest.mark.parametrize("precision,tau", [("fp32", 1e-4), ("bf16x3", 1e-2)])
+def test_screen_audit_su64_prefix(precision, tau):
+    """su(64), seed 5, tol 1e-8, a prefix of the closure that runs through the growth phase into
+    the saturated one with the screen computed on every block and every candidate decided in
+    FP64: every snapshot-dependent candidate screens below the threshold, every independent one
+    above it."""
+    gens = W.rand_pair(64, seed=5)
+    dim, v, st, orth = gpu_run(gens, 1e-8, budget=12288, precision=precision, decide="fp64", block=512)
+    assert dim == 4095, dim
+    assert st["candidates"] > 4095 * 2  # well past saturation
+    print("screen margin:", precision, st["screen_max_dependent"], st["screen_min_independent"])
+    assert st["screen_max_dependent"] < tau < st["screen_min_independent"]
+    assert pins.su_span_distance(v) <= 1e-8
+    assert orth <= 1e-9
+
+
+# ------------------------------------------------------------------ quality report
+
+def numpy_orthogonality(v):
+    return pins.orthonormality_loss(v)
+
+
+@pytest.mark.parametrize("d,seed,tol,cfg", [
+    (16, 2, 1e-10, {}),
+    (32, 3, 1e-8, {"precision": "bf16x3"}),
+    (64, 5, 1e-8, {"precision": "bf16x3", "early_exit": True}),
+])
+def test_orthogonality_matches_numpy(d, seed, tol, cfg):
+    """lie_closure_orthogonality against ||Q^H Q - I||_F formed by numpy (complex128 BLAS) from the
+    host basis: both must be far below 1e-10, and they must agree to their own rounding."""
+    dim, v, st, orth = gpu_run(W.rand_pair(d, seed=seed), tol, **cfg)
+    assert dim == d * d - 1
+    ref = numpy_orthogonality(v)
+    print(f"orthogonality d={d}: device {orth:.3e} numpy {ref:.3e}")
+    assert ref <= 1e-10
+    assert abs(orth - ref) <= 0.1 * ref + 1e-13
+
+
+@pytest.mark.parametrize("block", [1, 0])
+def test_residual_gap_matches_reference(block):
+    """Smallest accepted FP64 residual (bracket loop) against the reference's, at su(16); the
+    largest rejected one is rounding noise on both sides, far below tol."""
+    gens = W.rand_pair(16, seed=2)
+    ref = reference(gens, 1e-10)
+    dim, v, st, _ = gpu_run(gens, 1e-10, block=block)
+    assert dim == ref.dim
+    assert abs(st["min_accepted_residual"] - ref.min_accepted) <= 1e-9 * max(1.0, ref.min_accepted)
+    assert st["max_rejected_residual"] <= 1e-12 and ref.max_rejected <= 1e-12

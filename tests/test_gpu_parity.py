@@ -146,11 +146,22 @@ def test_basis_device_matches_host():
 # The screen (FP32 bracket + projection on MFMA) only filters candidates; every
 # decision that keeps a candidate, the appended vector and its normalisation
 # are FP64.  Bar: dimensions identical to the reference, span distance
-# <= 1e-5 (mixed-precision bar), orthogonality <= 1e-10.
+# <= 1e-5 (the mixed-precision bar of the span), and -- since every kept
+# element is recomputed in FP64 -- the basis equal to the reference's element
+# by element to 1e-8; orthogonality <= 1e-10.  The "approx" modes set an
+# explicit tau_rej, so the screen rejects below the ambient bound too and its
+# kernels decide which candidates reach FP64.
 SPAN_TOL_MIXED = 1e-5
 
-SCREEN_MODES = [("fp32", "fp64"), ("fp32", "strict"), ("fp32", "screen"),
-                ("bf16x3", "fp64"), ("bf16x3", "strict"), ("bf16x3", "screen")]
+SCREEN_MODES = [("fp32", "fp64"), ("fp32", "strict"), ("fp32", "screen"), ("fp32", "approx"),
+                ("bf16x3", "fp64"), ("bf16x3", "strict"), ("bf16x3", "screen"), ("bf16x3", "approx")]
+APPROX_TAU = {"fp32": 1e-4, "bf16x3": 1e-2}
+
+
+def mode_cfg(precision, decide):
+    if decide == "approx":
+        return dict(precision=precision, decide="screen", tau_rej=APPROX_TAU[precision])
+    return dict(precision=precision, decide=decide)
 
 
 _REF_CACHE = {}
@@ -170,6 +181,7 @@ def assert_parity_mixed(gens, tol, *, early_exit=False, expected=None, **cfg):
     if expected is not None:
         assert dim == expected
     assert pins.span_distance(v, ref.basis) <= SPAN_TOL_MIXED
+    assert np.max(np.abs(v - ref.basis)) <= ELEM_TOL_FP64
     assert orth <= ORTH_TOL_FP64
     assert st["done"] == 1
     if not early_exit:
@@ -188,7 +200,7 @@ def test_screened_small(case, precision, decide):
         "pauli4x6": (W.pauli_set(4, 6, 11), 1e-10, 100),
         "pair5_ragged": (W.rand_pair(5, seed=22), 1e-10, 33),
     }[case]
-    assert_parity_mixed(gens, tol, precision=precision, decide=decide, block=block)
+    assert_parity_mixed(gens, tol, block=block, **mode_cfg(precision, decide))
 
 
 @pytest.mark.parametrize("d,block,precision", [(17, 4096, "fp64"), (17, 4096, "fp32"), (20, 2048, "fp64")])
@@ -217,8 +229,8 @@ def test_screen_gemm_tiles(precision, tile):
 @pytest.mark.parametrize("precision,decide", SCREEN_MODES)
 def test_screened_su32_early_exit(precision, decide):
     """d=32 random pair (seed 3), tol 1e-8, early exit at d^2-1 = 1023, against the reference."""
-    assert_parity_mixed(W.rand_pair(32, seed=3), 1e-8, early_exit=True, expected=1023, precision=precision,
-                        decide=decide, block=256)
+    assert_parity_mixed(W.rand_pair(32, seed=3), 1e-8, early_exit=True, expected=1023, block=256,
+                        **mode_cfg(precision, decide))
 
 
 @pytest.mark.parametrize("precision,tau", [("fp32", 1e-4), ("bf16x3", 1e-2)])
