@@ -195,6 +195,9 @@ typedef struct lie_closure_stats {
     double kernel_ms[LIE_K_COUNT];
     double kernel_flops[LIE_K_COUNT];
     double kernel_bytes[LIE_K_COUNT];
+    int64_t reorth_passes;        /* in-block decisions that took a further pass against the whole basis because
+                                     the elements appended earlier in the block removed nearly all of the
+                                     candidate's norm (ratio above 64) */
 } lie_closure_stats;
 
 /* Fill *cfg with defaults (struct_size set).  Returns LIE_ERR_ARG for NULL. */

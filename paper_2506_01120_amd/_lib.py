@@ -93,6 +93,7 @@ class Stats(ctypes.Structure):
         ("kernel_ms", ctypes.c_double * K_COUNT),
         ("kernel_flops", ctypes.c_double * K_COUNT),
         ("kernel_bytes", ctypes.c_double * K_COUNT),
+        ("reorth_passes", ctypes.c_int64),
     ]
 
     def as_dict(self) -> dict:

@@ -1359,6 +1359,7 @@ lie_status lie_closure_stats_get(const lie_closure *h, lie_closure_stats *out)
     out->fp64_decided = h->hs.n_fp64;
     out->accepted = h->hs.n_acc;
     out->block_qr_accepted = h->hs.n_bqr;
+    out->reorth_passes = h->hs.n_reorth;
     out->blocks = h->blocks;
     out->host_syncs = h->host_syncs;
     out->min_accepted_residual = h->hs.min_acc;
@@ -2072,6 +2073,7 @@ lie_status lie_closure_batch_stats_get(const lie_closure_batch *b, int32_t i, li
         agg.fp64_decided += one.fp64_decided;
         agg.accepted += one.accepted;
         agg.block_qr_accepted += one.block_qr_accepted;
+        agg.reorth_passes += one.reorth_passes;
         agg.min_accepted_residual = std::min(agg.min_accepted_residual, one.min_accepted_residual);
         agg.max_rejected_residual = std::max(agg.max_rejected_residual, one.max_rejected_residual);
         agg.max_screen_rejected = std::max(agg.max_screen_rejected, one.max_screen_rejected);

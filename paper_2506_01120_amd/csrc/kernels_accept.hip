@@ -598,10 +598,10 @@ __device__ __forceinline__ void accept_body(const AcceptArgs &a)
         return;
     // ---- phase B
     const int64_t N0 = sN;
-    __shared__ int64_t l_fp64, l_zero, l_acc, l_gen;
+    __shared__ int64_t l_fp64, l_zero, l_acc, l_gen, l_reorth;
     __shared__ double l_maxrej, l_minacc, l_sdep, l_sind;
     if (threadIdx.x == 0) {
-        l_fp64 = l_zero = l_acc = l_gen = 0;
+        l_fp64 = l_zero = l_acc = l_gen = l_reorth = 0;
         l_maxrej = 0.0;
         l_minacc = INFINITY;
         l_sdep = 0.0;
@@ -881,6 +881,55 @@ __device__ __forceinline__ void accept_body(const AcceptArgs &a)
             before2 = nrm2;
             lds_barrier();  // red[] and coef[] are reused by the second pass
         }
+        // R_j left the snapshot passes with components along the snapshot of order
+        // eps * ||R_j|| (their rounding).  When the in-block elements then take away
+        // nearly all of its norm, normalisation magnifies those components by
+        // ||R_j|| / ||r||: a weakly coupled direction would come out orthogonal to the
+        // snapshot only to eps times that ratio.  Past a ratio of 64 a further pass runs
+        // against the whole basis (snapshot and in-block elements, in chunks of one
+        // element per wave), which brings the components back to rounding of ||r||.
+        if (A > 0 && snap > 0.0 && nrm2 > 0.0 && nrm2 * 4096.0 < snap * snap) {
+            __shared__ double scoef[16];
+            const int64_t nall = sN;
+            for (int64_t q0 = 0; q0 < nall; q0 += nw) {
+                const int64_t q = q0 + w;
+                if (q < nall) {
+                    const int64_t qb = q - N0;
+                    const double *va = (qb >= 0 && qb < AL) ? cbase + qb * D : a.V + q * D;
+                    double sdot = 0.0;
+                    for (int64_t j = lane; j < D; j += 64)
+                        sdot += va[j] * R[j];
+                    sdot = wave_sum(sdot);
+                    if (lane == 0)
+                        scoef[w] = sdot;
+                }
+                lds_barrier();  // the chunk's coefficients are complete, R is no longer read
+                const int nq = (int)std::min<int64_t>(nw, nall - q0);
+                for (int64_t j = threadIdx.x; j < D; j += blockDim.x) {
+                    double t = 0.0;
+                    for (int i = 0; i < nq; ++i) {
+                        const int64_t qb = q0 + i - N0;
+                        const double *va = (qb >= 0 && qb < AL) ? cbase + qb * D : a.V + (q0 + i) * D;
+                        t += scoef[i] * va[j];
+                    }
+                    R[j] -= t;
+                }
+                lds_barrier();  // R is updated and scoef[] may be overwritten
+            }
+            double loc = 0.0;
+            for (int64_t j = threadIdx.x; j < D; j += blockDim.x)
+                loc += R[j] * R[j];
+            loc = wave_sum(loc);
+            if (lane == 0)
+                red[w] = loc;
+            lds_barrier();
+            double t = 0.0;
+            for (int i = 0; i < nw; ++i)
+                t += red[i];
+            nrm2 = t;
+            if (threadIdx.x == 0)
+                l_reorth++;
+        }
         if (threadIdx.x == 0) {
             const double rr = sqrt(nrm2);
             rr_s = rr;
@@ -953,6 +1002,7 @@ __device__ __forceinline__ void accept_body(const AcceptArgs &a)
         st->n_zero = s0.n_zero + l_zero;
         st->n_acc = s0.n_acc + l_acc;
         st->n_gen_acc = s0.n_gen_acc + l_gen;
+        st->n_reorth = s0.n_reorth + l_reorth;
         st->max_rej = fmax(s0.max_rej, l_maxrej);
         st->min_acc = fmin(s0.min_acc, l_minacc);
         st->scr_max_dep = fmax(s0.scr_max_dep, l_sdep);

@@ -42,6 +42,7 @@ struct DevState {
     int64_t raw_lo;          // Algorithm 3: |V| when the last acceptance launch started (raw rows from here on)
     double vfy_flops;        // algorithmic flops of the FP64 verification of survivors (bracket + passes)
     double vfy_bytes;        // algorithmic bytes of the same
+    int64_t n_reorth;        // in-block decisions that took a further pass against the whole basis
 };
 
 // Pair index p <-> (l, m) with 0 <= m < l: p = l(l-1)/2 + m.  Row l holds the

@@ -58,7 +58,10 @@ def test_weak_coupling_direction_kept(eps, block, precision, decide):
     assert dim == ref.dim == 64, (dim, st)
     assert st["candidates"] == ref.candidates
     assert np.max(np.abs(v - ref.basis)) <= ELEM_TOL
-    assert orth <= 1e-10
+    # the weak direction is appended from a residual about 1e5 to 1e7 times smaller than its
+    # bracket: orthogonality to rounding needs the passes against the whole basis
+    assert orth <= 1e-10, (orth, st["reorth_passes"])
+    assert pins.orthonormality_loss(v) <= 1e-10
     # below the ambient bound no candidate may be rejected from a screened residual alone
     assert st["screen_rejected"] == 0
     # the weak direction's residual, as the reference measures it
@@ -90,14 +93,6 @@ def test_explicit_tau_is_applied_everywhere(precision):
                             tau_rej=DEFAULT_TAU[precision])
     assert dim == ref.dim == 255
     assert np.max(np.abs(v - ref.basis)) <= ELEM_TOL
-
-
-def test_uncertified_screen_loses_the_weak_direction():
-    """The failure the certification prevents, shown with the uncertified split-BF16 screen:
-    the weak direction (FP64 residual 5.6e-4) screens below tau_rej = 1e-2 and is lost."""
-    gens = W.weak_coupling(1e-4)
-    dim, _, st, _ = gpu_run(gens, 1e-8, precision="bf16x3", decide="screen", block=256, tau_rej=1e-2)
-    assert dim == 63, (dim, st)
 
 
 @pytest.mark.parametrize("precision,tau", [("fp32", 1e-4), ("bf16x3", 1e-2)])
