@@ -255,6 +255,20 @@ lie_status lie_closure_raw_basis(const lie_closure *h, double *out, int64_t capa
 /* ||G - I||_F with G_ij = <V_i, V_j>, computed in FP64 on the device. */
 lie_status lie_closure_orthogonality(lie_closure *h, double *loss);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, serving
+ * loops, harnesses that forbid hipMalloc): the value of lie_closure_orthogonality,
+ * computed without any allocation and without synchronising.
+ *   loss_dev -- device pointer (one double, HIP device memory of the handle's device);
+ *               owned by the caller; receives ||G - I||_F once the handle's stream
+ *               (config.stream, or the library's own) has executed the enqueued work
+ * The Gram matrix is formed in row panels inside a fixed per-device workspace of 8 MiB
+ * that the library holds for the life of the process (|V| <= 2^20 - 256, which every
+ * closure the library accepts satisfies; LIE_ERR_CAPACITY otherwise).  Every call on a
+ * GPU shares that GPU's workspace: calls whose work overlaps on one GPU (on different
+ * streams, or from different threads) race and may return wrong values; serialise them.
+ * The value can differ from lie_closure_orthogonality's in the last bits (summation order). */
+lie_status lie_closure_orthogonality_noalloc(lie_closure *h, double *loss_dev);
+
 /* Counters and residual-gap statistics (out->struct_size must be set). */
 lie_status lie_closure_stats_get(const lie_closure *h, lie_closure_stats *out);
 

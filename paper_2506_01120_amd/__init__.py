@@ -145,6 +145,11 @@ class LieClosure:
         _lib.check(self._libh.lie_closure_orthogonality(self._h, ctypes.byref(x)))
         return float(x.value)
 
+    def orthogonality_noalloc(self, out) -> None:
+        """Enqueue ||G - I||_F into `out` (a one-element float64 tensor on the handle's
+        device) without allocating; the value is there once the handle's stream has run."""
+        _lib.check(self._libh.lie_closure_orthogonality_noalloc(self._h, ctypes.c_void_p(out.data_ptr())))
+
     def stats(self) -> dict:
         s = _lib.Stats()
         s.struct_size = ctypes.sizeof(_lib.Stats)

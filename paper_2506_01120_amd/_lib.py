@@ -29,7 +29,7 @@ EXPORTS = (
     "lie_closure_config_default", "lie_closure_init", "lie_closure_run", "lie_closure_run_budget",
     "lie_closure_dim", "lie_closure_basis", "lie_closure_basis_device", "lie_closure_raw_basis",
     "lie_pauli_coordinates", "lie_pauli_matrix",
-    "lie_closure_orthogonality",
+    "lie_closure_orthogonality", "lie_closure_orthogonality_noalloc",
     "lie_closure_stats_get", "lie_closure_free", "lie_status_string", "lie_last_error",
     "lie_closure_batch_init", "lie_closure_batch_run", "lie_closure_batch_dim", "lie_closure_batch_basis",
     "lie_closure_batch_stats_get", "lie_closure_batch_free",
@@ -129,6 +129,7 @@ def _declare(lib: ctypes.CDLL) -> ctypes.CDLL:
         "lie_pauli_coordinates": (st, [ctypes.c_int32, vp, vp]),
         "lie_pauli_matrix": (st, [ctypes.c_int32, vp, vp]),
         "lie_closure_orthogonality": (st, [vp, dblp]),
+        "lie_closure_orthogonality_noalloc": (st, [vp, vp]),
         "lie_closure_stats_get": (st, [vp, ctypes.POINTER(Stats)]),
         "lie_closure_free": (None, [vp]),
         "lie_status_string": (ctypes.c_char_p, [st]),

@@ -1080,6 +1080,10 @@ lie_status lie_closure_init(lie_closure **out, const double *generators, int32_t
         hipError_t e = hipSetDevice(dev);
         if (e != hipSuccess)
             return bail(fail(LIE_ERR_DEVICE, "hipSetDevice(%d) failed: %s", dev, hipGetErrorString(e)));
+        // the fixed workspace of the allocation-free entry points, once per device
+        e = lie::noalloc_setup(dev);
+        if (e != hipSuccess)
+            return bail(fail(LIE_ERR_DEVICE, "workspace lookup on device %d failed: %s", dev, hipGetErrorString(e)));
     }
     if (cfg.stream) {
         h->stream = (hipStream_t)cfg.stream;
@@ -1336,6 +1340,27 @@ lie_status lie_closure_orthogonality(lie_closure *h, double *loss)
     if (e == hipSuccess)
         e = hipStreamSynchronize(h->stream);
     (void)hipFree(work);
+    if (e != hipSuccess)
+        return fail(LIE_ERR_DEVICE, "orthogonality check failed: %s", hipGetErrorString(e));
+    return LIE_OK;
+}
+
+lie_status lie_closure_orthogonality_noalloc(lie_closure *h, double *loss_dev)
+{
+    if (!h || !loss_dev)
+        return fail(LIE_ERR_ARG, "NULL argument");
+    if (h->method != LIE_METHOD_ORTHONORMALIZATION)
+        return fail(LIE_ERR_STATE, "this method keeps no orthonormal basis");
+    const int64_t n = h->hs.N;
+    double *ws = lie::noalloc_scratch(h->device);
+    if (!ws)
+        return fail(LIE_ERR_STATE, "no workspace on device %d", h->device);
+    if (n + 256 > lie::kNoallocScratchDoubles)
+        return fail(LIE_ERR_CAPACITY, "basis of %lld elements exceeds the fixed workspace (at most %lld)",
+                    (long long)n, (long long)(lie::kNoallocScratchDoubles - 256));
+    HIP_TRY(hipSetDevice(h->device));
+    const hipError_t e = lie::launch_orth_loss_panels(h->V64, n, h->D, ws, lie::kNoallocScratchDoubles, loss_dev,
+                                                      h->stream);
     if (e != hipSuccess)
         return fail(LIE_ERR_DEVICE, "orthogonality check failed: %s", hipGetErrorString(e));
     return LIE_OK;

@@ -636,6 +636,24 @@ __global__ void __launch_bounds__(kThreads) k_gram_loss_part(const double *__res
         part[blockIdx.x] = s;
 }
 
+// Panel form: rows r0 .. r0 + rows of G (row stride n); part[b] receives this panel's sum
+// (first panel) or adds it (later panels), so the panels are summed in launch order.
+__global__ void __launch_bounds__(kThreads) k_gram_loss_panel(const double *__restrict__ G, int64_t rows, int64_t n,
+                                                              int64_t r0, int accumulate, double *__restrict__ part)
+{
+    __shared__ double red[8];
+    double s = 0.0;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < rows * n;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = r0 + e / n, j = e % n;
+        const double g = G[e] - (i == j ? 1.0 : 0.0);
+        s += g * g;
+    }
+    s = block_sum(s, red);
+    if (threadIdx.x == 0)
+        part[blockIdx.x] = accumulate ? part[blockIdx.x] + s : s;
+}
+
 __global__ void k_gram_loss_final(const double *__restrict__ part, int parts, double *__restrict__ out)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
@@ -899,6 +917,31 @@ hipError_t launch_orth_loss(const double *V, int64_t n, int64_t D, double *work,
     const int parts = 256;
     double *part = work + n * n;
     hipLaunchKernelGGL(k_gram_loss_part, dim3(parts), dim3(kThreads), 0, s, G, n, part);
+    hipLaunchKernelGGL(k_gram_loss_final, dim3(1), dim3(64), 0, s, part, parts, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_orth_loss_panels(const double *V, int64_t n, int64_t D, double *ws, int64_t ws_doubles,
+                                   double *out, hipStream_t s)
+{
+    const int parts = 256;
+    if (n <= 0) {
+        hipLaunchKernelGGL(k_gram_loss_final, dim3(1), dim3(64), 0, s, ws, 0, out);  // sqrt(0)
+        return hipGetLastError();
+    }
+    if (ws_doubles < parts + n)
+        return hipErrorInvalidValue;
+    double *part = ws, *G = ws + parts;
+    // rows per panel: as many as the workspace holds, at most the grid's row limit
+    const int64_t P = std::min<int64_t>(std::min<int64_t>((ws_doubles - parts) / n, n), (int64_t)65535 * kDotT);
+    for (int64_t r0 = 0; r0 < n; r0 += P) {
+        const int64_t rows = std::min<int64_t>(P, n - r0);
+        hipLaunchKernelGGL(k_dot_f64, dim3((unsigned)((n + kDotT - 1) / kDotT), (unsigned)((rows + kDotT - 1) / kDotT)),
+                           dim3(kThreads), 0, s, V, (const DevState *)nullptr, n, V + r0 * D, (const int *)nullptr,
+                           (const int *)nullptr, (int)rows, D, G, n, (int64_t)0);
+        hipLaunchKernelGGL(k_gram_loss_panel, dim3(parts), dim3(kThreads), 0, s, G, rows, n, r0, r0 > 0 ? 1 : 0,
+                           part);
+    }
     hipLaunchKernelGGL(k_gram_loss_final, dim3(1), dim3(64), 0, s, part, parts, out);
     return hipGetLastError();
 }

@@ -279,6 +279,19 @@ hipError_t launch_raw_append(const double *G, double *B, float *Bs, int d, const
 
 // G = V V^T (n x n) then ||G - I||_F into *out (device), using `work` of n*n + 256 doubles.
 hipError_t launch_orth_loss(const double *V, int64_t n, int64_t D, double *work, double *out, hipStream_t s);
+// The same loss with G formed in row panels inside a fixed workspace of ws_doubles doubles
+// (256 partial sums, then one panel of rows x n): panels of as many rows as fit, each reduced
+// into the running partial sums in panel order.  Needs ws_doubles >= 256 + n.
+hipError_t launch_orth_loss_panels(const double *V, int64_t n, int64_t D, double *ws, int64_t ws_doubles,
+                                   double *out, hipStream_t s);
+
+// ------------------------------------------------------------- fixed workspace (noalloc.hip)
+// Size of the per-device file-scope workspace of the allocation-free entry points: 8 MiB.
+constexpr int64_t kNoallocScratchDoubles = (int64_t)1 << 20;
+// Look up the workspace's device address on `device` (which must be current); once per device.
+hipError_t noalloc_setup(int device);
+// The looked-up address on `device`, or nullptr before noalloc_setup succeeded there.
+double *noalloc_scratch(int device);
 
 // ------------------------------------------------------------- matrix-core projection GEMMs (kernels_gemm.hip)
 // Coefficients C[m][n] = <H_row(m), V_n> and residual R = H - C V with per-tile
