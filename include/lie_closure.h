@@ -20,11 +20,11 @@
  * basis elements is kept iff ||h_perp|| > tol.  Exactly zero brackets are
  * rejected.
  *
- * The orthonormalization method (the default; Algorithms 3 and 4) runs all of
- * its device work in the library's own HIP kernels on one GPU.  The comparison
- * method LIE_METHOD_RANK_SVD takes its singular values from rocSOLVER (that
- * library SVD is what the baseline is), and LIE_METHOD_MATRIX_INVERSION forms
- * and applies the inverse Gram matrix with rocBLAS and rocSOLVER.  Host pointers are plain CPU memory;
+ * The orthonormalization method (the default; Algorithms 3 and 4) and the
+ * matrix-inversion method (Algorithm 2) run all of their device work in the
+ * library's own HIP kernels on one GPU.  Only the comparison method
+ * LIE_METHOD_RANK_SVD calls a vendor library: it takes its singular values from
+ * rocSOLVER (that library SVD is what the baseline is).  Host pointers are plain CPU memory;
  * device pointers are HIP device memory of the handle's device.  No function throws; every failure returns a negative
  * lie_status and records a message readable with lie_last_error().
  *
@@ -70,8 +70,11 @@ typedef enum lie_precision {
  * (lie_closure_raw_basis); it runs in FP64, one problem at a time, for d <= 16.
  * MATRIX_INVERSION is the paper's other method (Algorithm 2, Section 3.1): unit-norm raw elements
  * B, the inverse of their Gram matrix A, and the explicit residual h - B A^{-1} beta of a unit-norm
- * candidate (beta_k = <B_k, h>), kept iff its norm exceeds tol; A^{-1} is recomputed after each
- * block that appended elements.  FP64, single problems, raw basis only (unit-norm elements). */
+ * candidate (beta_k = <B_k, h>), kept iff its norm exceeds tol; each appended element expands A
+ * (new row and column <B_i, b>, diagonal 1), and A^{-1} = L^{-T} L^{-1} follows by bordering the
+ * inverse Cholesky factor; a bordered pivot that is not positive is reported as LIE_ERR_NUMERIC.
+ * FP64, single problems,
+ * raw basis only (unit-norm elements). */
 typedef enum lie_method {
     LIE_METHOD_ORTHONORMALIZATION = 0,
     LIE_METHOD_RANK_SVD = 1,

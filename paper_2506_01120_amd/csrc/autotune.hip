@@ -40,6 +40,12 @@ __global__ void k_fill64(double *p, int64_t n, double a)
         p[i] = a * (double)((i * 2654435761ll) % 1024 - 512) / 512.0;
 }
 
+__global__ void k_fill_bf16(__bf16 *p, int64_t n, float a)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = (__bf16)(a * (float)((i * 2654435761ll) % 1024 - 512) / 512.0f);
+}
+
 struct Key {
     std::string arch;
     int precision;
@@ -79,7 +85,7 @@ bool file_lookup(const char *path, const Key &k, TuneChoice *out)
         int prec = -1, d = -1, b = 0, td = 0, ts = 0;
         long long amb = -1;
         double us = 0;
-        if (std::sscanf(line, "lie-tune v1 arch=%127s precision=%d d=%d ambient=%lld block_sat=%d tile_dot=%d "
+        if (std::sscanf(line, "lie-tune v2 arch=%127s precision=%d d=%d ambient=%lld block_sat=%d tile_dot=%d "
                               "tile_sub=%d us_per_candidate=%lf",
                         arch, &prec, &d, &amb, &b, &td, &ts, &us) == 8 &&
             k.arch == arch && prec == k.precision && d == k.d && amb == k.ambient && b > 0) {
@@ -97,7 +103,7 @@ void file_append(const char *path, const Key &k, const TuneChoice &c)
     if (!f)
         return;
     std::fprintf(f,
-                 "lie-tune v1 arch=%s precision=%d d=%d ambient=%lld block_sat=%d tile_dot=%d tile_sub=%d "
+                 "lie-tune v2 arch=%s precision=%d d=%d ambient=%lld block_sat=%d tile_dot=%d tile_sub=%d "
                  "us_per_candidate=%.6g\n",
                  k.arch.c_str(), k.precision, k.d, (long long)k.ambient, c.block_sat, c.tile_dot, c.tile_sub,
                  c.us_per_candidate);
@@ -106,12 +112,14 @@ void file_append(const char *path, const Key &k, const TuneChoice &c)
 
 struct Buffers {
     void *V = nullptr, *H = nullptr, *C = nullptr;
+    __bf16 *Vp = nullptr, *Vt = nullptr, *Hp = nullptr, *Cp = nullptr;  // split-BF16 planes
+    PlaneGeom pg{};
     double *normpart = nullptr;
     DevState *st = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     ~Buffers()
     {
-        for (void *p : {V, H, C, (void *)normpart, (void *)st})
+        for (void *p : {V, H, C, (void *)normpart, (void *)st, (void *)Vp, (void *)Vt, (void *)Hp, (void *)Cp})
             if (p)
                 (void)hipFree(p);
         if (e0)
@@ -139,11 +147,10 @@ hipError_t time_step(const Buffers &B, int precision, int64_t D, int64_t n, int6
                 e = launch_gemm_sub_f32((const float *)B.V, B.st, (const float *)B.H, (const float *)B.C, n, ldc, b, D,
                                         B.normpart, ts, s);
         } else {
-            e = launch_gemm_dot_bf16x3((const float *)B.V, B.st, (const float *)B.H, b, D, n, ldc, (float *)B.C, td,
-                                       s);
+            // split BF16: the plane GEMMs of single problems
+            e = launch_bfp_dot(B.Hp, B.Vp, B.st, b, n, B.Cp, B.pg, s);
             if (e == hipSuccess)
-                e = launch_gemm_sub_bf16x3((const float *)B.V, B.st, (const float *)B.H, (const float *)B.C, n, ldc, b,
-                                           D, B.normpart, ts, s);
+                e = launch_bfp_sub(B.Cp, B.Vt, B.Hp, B.st, b, D, B.normpart, B.pg, s);
         }
         return e;
     };
@@ -220,10 +227,28 @@ hipError_t autotune_block_step(int device, int precision, int d, int64_t ambient
         hipLaunchKernelGGL(k_fill, dim3(1024), dim3(256), 0, s, (float *)B.V, n * D, 1.0f / std::sqrt((float)D));
         hipLaunchKernelGGL(k_fill, dim3(1024), dim3(256), 0, s, (float *)B.H, (int64_t)bmax * D, 1.0f);
     }
+    if (precision == 2) {
+        // planes of unit-scale synthetic values (the timing does not depend on them)
+        B.pg = plane_geom(D, n, bmax);
+        const PlaneGeom &g = B.pg;
+        if ((e = hipMalloc((void **)&B.Vp, (size_t)(g.cap_rows * g.ld) * 2)) != hipSuccess ||
+            (e = hipMalloc((void **)&B.Vt, (size_t)(g.d_rows * g.ldt) * 2)) != hipSuccess ||
+            (e = hipMalloc((void **)&B.Hp, (size_t)(g.b_rows * g.ld) * 2)) != hipSuccess ||
+            (e = hipMalloc((void **)&B.Cp, (size_t)(g.b_rows * g.ldt) * 2)) != hipSuccess)
+            return e;
+        for (auto pz : {std::make_pair((void *)B.Vp, (size_t)(g.cap_rows * g.ld)),
+                        std::make_pair((void *)B.Vt, (size_t)(g.d_rows * g.ldt)),
+                        std::make_pair((void *)B.Hp, (size_t)(g.b_rows * g.ld)),
+                        std::make_pair((void *)B.Cp, (size_t)(g.b_rows * g.ldt))})
+            hipLaunchKernelGGL(k_fill_bf16, dim3(1024), dim3(256), 0, s, (__bf16 *)pz.first, (int64_t)pz.second,
+                               1.0f / std::sqrt((float)D));
+    }
     if ((e = hipGetLastError()) != hipSuccess)
         return e;
     TuneChoice best{blocks.front(), 0, 0, 1e30};
-    const std::vector<int> tiles = precision == 0 ? std::vector<int>{0} : std::vector<int>{1, 2};
+    // the plane GEMMs have one tile shape (reported as 2: 128 x 128)
+    const std::vector<int> tiles = precision == 0 ? std::vector<int>{0}
+                                   : precision == 2 ? std::vector<int>{2} : std::vector<int>{1, 2};
     for (int b : blocks)
         for (int td : tiles)
             for (int ts : tiles) {

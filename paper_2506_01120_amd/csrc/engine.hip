@@ -173,6 +173,15 @@ struct lie_closure {
     double *splitws = nullptr;   // K slices of small matrix-core passes
     size_t splitws_n = 0;
     double *normpart_s = nullptr;// block x tiles, screened residual partial norms
+    // split-BF16 screen (single problems): pre-split interleaved hi/lo planes of the basis
+    // (rows, and transposed), of the candidate block and of its coefficients
+    bool planes = false;
+    lie::PlaneGeom pg{};
+    __bf16 *Vp = nullptr;        // cap_rows x ld
+    __bf16 *Vt = nullptr;        // d_rows x ldt
+    __bf16 *Hp = nullptr;        // b_rows x ld
+    __bf16 *Cp = nullptr;        // b_rows x ldt
+    int64_t *planes_n = nullptr; // basis rows already in Vp / Vt
     double *cand_a2 = nullptr;   // block: squared residual of the first pass (screen or FP64)
     double *cand_n2 = nullptr;   // block: squared candidate norm of the first pass
     double *rho2 = nullptr;      // block: squared FP64 residuals of survivors
@@ -246,7 +255,8 @@ struct lie_closure {
                         (void *)part, (void *)splitws,
                         (void *)normpart_s, (void *)cand_a2, (void *)cand_n2, (void *)rho2, (void *)h2, (void *)h2b,
                         (void *)surv_rows, (void *)surv_pairs, (void *)slot, (void *)keep, (void *)nsurv,
-                        (void *)st, (void *)scalar, (void *)B64, (void *)Bs, (void *)Graw, (void *)elem_src})
+                        (void *)st, (void *)scalar, (void *)B64, (void *)Bs, (void *)Graw, (void *)elem_src,
+                        (void *)Vp, (void *)Vt, (void *)Hp, (void *)Cp, (void *)planes_n})
             if (p)
                 (void)hipFree(p);
         if (own_stream && stream)
@@ -519,6 +529,27 @@ struct lie_closure {
         const int tile_s = tuned ? tile_sub : lie::gemm_tile_f32(cnt, D);
         const bool bf = cfg.precision == LIE_PREC_BF16X3;
         const int64_t ldc = lie::coef_ld(cap);
+        if (planes) {
+            // candidate rows into planes (with the bracket's class: the split is its output stage),
+            // new basis rows into planes, then the two GEMMs on planes
+            timer.begin(stream);
+            HIP_TRY(lie::launch_split_rows(Hs, D, cnt, Hp, pg, stream));
+            timer.end(LIE_K_COMM, stream, 0.0, c * Dd * (4.0 + 4.0));
+            timer.begin(stream);
+            HIP_TRY(lie::launch_planes_refresh(V64, D, st, planes_n, Vp, Vt, pg, stream));
+            timer.end(LIE_K_OTHER, stream, 0.0, 0.0);
+            timer.begin(stream);
+            HIP_TRY(lie::launch_bfp_dot(Hp, Vp, st, cnt, cap, Cp, pg, stream));  // tiles up to the capacity: N may grow
+            timer.end(LIE_K_DOT, stream, 2.0 * N * Dd * c, (N * Dd + c * Dd + c * N) * w);
+            timer.begin(stream);
+            HIP_TRY(lie::launch_bfp_sub(Cp, Vt, Hp, st, cnt, D, normpart_s, pg, stream));
+            timer.end(LIE_K_SUB, stream, 2.0 * N * Dd * c, (N * Dd + c * N + c * Dd) * w);
+            timer.begin(stream);
+            HIP_TRY(lie::launch_norm_final(normpart_s, nullptr, cnt, lie::plane_sub_tiles(D, 0), st, cand_a2, nullptr,
+                                           stream));
+            timer.end(LIE_K_REDUCE, stream, 0, 0);
+            return step_screen_verify(cnt, n_hi, dp0);
+        }
         timer.begin(stream);
         HIP_TRY(bf ? lie::launch_gemm_dot_bf16x3(Vs, st, Hs, cnt, D, nh, ldc, Cs, tile_d, stream)
                    : lie::launch_gemm_dot_f32(Vs, st, Hs, cnt, D, nh, ldc, Cs, tile_d, stream));
@@ -532,6 +563,13 @@ struct lie_closure {
                                        bf ? lie::gemm_sub_tiles_bf16(D, tile_s) : lie::gemm_sub_tiles_f32(D, tile_s),
                                        st, cand_a2, nullptr, stream));
         timer.end(LIE_K_REDUCE, stream, 0, 0);
+        return step_screen_verify(cnt, n_hi, dp0);
+    }
+
+    // The rest of a screened block step: classification, then the FP64 recomputation
+    // (bracket + two projection passes) of the survivors and their acceptance.
+    lie_status step_screen_verify(int cnt, int64_t n_hi, const int64_t *dp0)
+    {
         lie_status s;
         if ((s = classify(cnt, cursor, policy, policy_thr, dp0, certify)) != LIE_OK)
             return s;
@@ -726,7 +764,8 @@ struct lie_closure {
         return accept(cnt, generator ? 0 : 1, false, surv_rows, nullptr, LIE_K_ACCEPT, src0);
     }
 
-    // A^{-1} after appends; a failed Cholesky factorisation of A is the method's numerical failure.
+    // A^{-1} expanded by the elements appended since the last call (bordered updates in element
+    // order); a Schur complement that is not positive is the method's numerical failure.
     lie_status refresh_inverse()
     {
         int info = 0;
@@ -735,8 +774,9 @@ struct lie_closure {
             return fail(LIE_ERR_DEVICE, "inverse Gram update failed: %s", hipGetErrorString(e));
         if (info != 0)
             return fail(LIE_ERR_NUMERIC, "Gram matrix of %lld elements is not numerically positive definite "
-                                         "(minor %d); the matrix-inversion method lost accuracy",
-                        (long long)hs.N, info);
+                                         "(bordered Cholesky pivot of element %d not positive); the matrix-inversion "
+                                         "method lost accuracy",
+                        (long long)hs.N, info - 1);
         return LIE_OK;
     }
 
@@ -1157,6 +1197,28 @@ lie_status lie_closure_init(lie_closure **out, const double *generators, int32_t
             (s = alloc(&h->Cs, (size_t)bmax * capr)) != LIE_OK ||
             (s = alloc(&h->normpart_s, (size_t)bmax * lie::gemm_sub_tiles_f32(D, 1) * 2)) != LIE_OK)
             return bail(s);
+        if (cfg.precision == LIE_PREC_BF16X3 && !t_batch_member) {
+            // the split-BF16 screen of single problems runs on pre-split planes; their padding
+            // must read as zeros, so every plane starts cleared
+            h->planes = true;
+            h->pg = lie::plane_geom(D, h->cap, bmax);
+            const lie::PlaneGeom &g = h->pg;
+            if ((s = alloc(&h->Vp, (size_t)(g.cap_rows * g.ld))) != LIE_OK ||
+                (s = alloc(&h->Vt, (size_t)(g.d_rows * g.ldt))) != LIE_OK ||
+                (s = alloc(&h->Hp, (size_t)(g.b_rows * g.ld))) != LIE_OK ||
+                (s = alloc(&h->Cp, (size_t)(g.b_rows * g.ldt))) != LIE_OK || (s = alloc(&h->planes_n, 1)) != LIE_OK)
+                return bail(s);
+            hipError_t e = hipSuccess;
+            for (auto pz : {std::make_pair((void *)h->Vp, (size_t)(g.cap_rows * g.ld) * 2),
+                            std::make_pair((void *)h->Vt, (size_t)(g.d_rows * g.ldt) * 2),
+                            std::make_pair((void *)h->Hp, (size_t)(g.b_rows * g.ld) * 2),
+                            std::make_pair((void *)h->Cp, (size_t)(g.b_rows * g.ldt) * 2),
+                            std::make_pair((void *)h->planes_n, sizeof(int64_t))})
+                if (e == hipSuccess)
+                    e = hipMemsetAsync(pz.first, 0, pz.second, h->stream);
+            if (e != hipSuccess)
+                return bail(fail(LIE_ERR_DEVICE, "clearing the screen planes failed: %s", hipGetErrorString(e)));
+        }
     }
     if (h->method == LIE_METHOD_RANK_SVD) {
         const hipError_t e = lie::rank_tester_create(&h->rank, D, 64, h->stream);
@@ -1170,7 +1232,7 @@ lie_status lie_closure_init(lie_closure **out, const double *generators, int32_t
     if (h->inv) {
         if ((s = alloc(&h->Xc, (size_t)bmax * capr)) != LIE_OK)
             return bail(s);
-        const hipError_t e = lie::gram_inverse_create(&h->ginv, h->cap, D, h->stream);
+        const hipError_t e = lie::gram_inverse_create(&h->ginv, h->cap, D, bmax, h->stream);
         if (e != hipSuccess)
             return bail(fail(LIE_ERR_DEVICE, "inverse Gram setup failed: %s", hipGetErrorString(e)));
     }

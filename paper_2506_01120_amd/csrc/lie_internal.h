@@ -359,6 +359,45 @@ hipError_t launch_gather_states(const DevState *const *src, int n, DevState *dst
 // ------------------------------------------------------------- split-BF16 projection GEMMs (kernels_bf16.hip)
 // Same contracts as the FP32 coefficient / residual GEMMs; FP32 operands are
 // split into bf16 hi + lo while staged, products are hi*hi + hi*lo + lo*hi.
+// Split-BF16 GEMMs on pre-split interleaved planes (kernels_bf16p.hip): a row of K values
+// is K/8 groups of 32 bytes, 8 hi values then 8 lo values; K is padded to a multiple of 32
+// and rows to whole tiles, all padding zero.
+struct PlaneGeom {
+    int64_t Kp;        // d^2 padded to a multiple of 32 (K of the coefficient GEMM)
+    int64_t ld;        // row stride of H and V row planes, in bf16 elements (2 Kp)
+    int64_t cap_rows;  // rows of the V row planes (capacity padded)
+    int64_t ldt_k;     // capacity padded to a multiple of 32 (K of the residual GEMM)
+    int64_t ldt;       // row stride of the transposed V planes and of the C planes (2 ldt_k)
+    int64_t d_rows;    // rows of the transposed V planes (d^2 padded)
+    int64_t b_rows;    // rows of the H and C planes (block size padded)
+};
+PlaneGeom plane_geom(int64_t D, int64_t cap, int bmax);
+struct PlaneGemmArgs {
+    const __bf16 *A;   // rows m, K contiguous (interleaved planes)
+    int64_t lda;
+    const __bf16 *B;   // rows n, K contiguous (interleaved planes)
+    int64_t ldb;
+    int64_t K;         // coefficient GEMM: padded K (the residual GEMM takes K = N from st)
+    int cnt;           // rows m
+    const DevState *st;
+    __bf16 *Cout;      // coefficient GEMM: C planes (row m, K index n)
+    int64_t ldcout;
+    const __bf16 *Hp;  // residual GEMM: candidate planes for the epilogue
+    int64_t ldh;
+    int64_t D;         // residual GEMM: columns j
+    double *normpart;  // residual GEMM: [m][tn][2] squared norms of R and H
+    int tm, tn;        // output tiles
+};
+int plane_sub_tiles(int64_t D, int tile);
+// Basis rows [*done, st->N) into the row planes Vp and transposed planes Vt, then *done = N.
+hipError_t launch_planes_refresh(const double *V64, int64_t D, const DevState *st, int64_t *done, __bf16 *Vp,
+                                 __bf16 *Vt, const PlaneGeom &p, hipStream_t s);
+// FP32 rows [cnt][D] into row planes.
+hipError_t launch_split_rows(const float *src, int64_t D, int cnt, __bf16 *dst, const PlaneGeom &p, hipStream_t s);
+hipError_t launch_bfp_dot(const __bf16 *Hp, const __bf16 *Vp, const DevState *st, int cnt, int64_t n_hi, __bf16 *Cp,
+                          const PlaneGeom &p, hipStream_t s);
+hipError_t launch_bfp_sub(const __bf16 *Cp, const __bf16 *Vt, const __bf16 *Hp, const DevState *st, int cnt,
+                          int64_t D, double *normpart, const PlaneGeom &p, hipStream_t s);
 int gemm_sub_tiles_bf16(int64_t D, int tile);
 hipError_t launch_gemm_dot_bf16x3(const float *Vs, const DevState *st, const float *Hs, int cnt, int64_t D,
                                   int64_t n_hi, int64_t ldc, float *C, int tile, hipStream_t s);
@@ -390,12 +429,14 @@ void rank_tester_destroy(RankTester *t);
 hipError_t rank_tester_run(RankTester *t, const double *B, int64_t N, const double *H, int cnt, unsigned char *flags);
 
 // ------------------------------------------------------------- matrix-inversion method (inverse_gram.hip)
-// A^{-1} for the Gram matrix A = B B^T of the first N unit-norm raw rows (Algorithm 2).
+// A^{-1} for the Gram matrix A = B B^T of the first N unit-norm raw rows (Algorithm 2), kept as
+// the inverse of its Cholesky factor and bordered by each appended element.
 struct GramInverse;
-hipError_t gram_inverse_create(GramInverse **out, int64_t cap, int64_t D, hipStream_t s);
+hipError_t gram_inverse_create(GramInverse **out, int64_t cap, int64_t D, int max_rows, hipStream_t s);
 void gram_inverse_destroy(GramInverse *g);
-// Recompute A^{-1} (N x N) from B (device, row stride D); *info_host != 0 when the Cholesky
-// factorisation of A failed (A not numerically positive definite).  Synchronises the stream.
+// Expand the factor by the rows appended since the last call, up to N (B: device, row stride D);
+// *info_host = (element index + 1) when its bordered pivot was not positive (A not numerically
+// positive definite), else 0.  Synchronises the stream.
 hipError_t gram_inverse_update(GramInverse *g, const double *B, int64_t N, int *info_host);
 // X (cnt x N, row stride ldx) = beta (cnt x N, row stride ldb) A^{-1}.
 hipError_t gram_inverse_apply(GramInverse *g, const double *beta, int64_t ldb, int64_t N, int cnt, double *X,

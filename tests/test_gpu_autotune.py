@@ -56,7 +56,7 @@ def test_tune_cache_file_format(tmp_path):
         st = lc.stats()
     if st["autotuned"] == 1:  # timed in this process: the line was appended
         lines = cache.read_text().splitlines()
-        assert len(lines) == 1 and lines[0].startswith("lie-tune v1 arch=")
+        assert len(lines) == 1 and lines[0].startswith("lie-tune v2 arch=")
         assert " precision=1 d=8 ambient=63 " in lines[0]
         assert f"block_sat={-st['block']} tile_dot={st['tile_dot']} tile_sub={st['tile_sub']}" in lines[0]
 
