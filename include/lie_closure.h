@@ -160,6 +160,8 @@ typedef enum lie_kernel_id {
     LIE_K_ACCEPT = 4,    /* sequential in-block acceptance and append (FP64) */
     LIE_K_VERIFY = 5,    /* FP64 recomputation of screen survivors (bracket + CGS2 passes) */
     LIE_K_OTHER = 6,     /* everything else (packing, shadow copies, bookkeeping) */
+    LIE_K_GROWTH = 7,    /* FP64 bracket and projections of the unscreened blocks of a screened run
+                            (growth phase); FP64 runs account these as COMM / DOT / SUB */
     LIE_K_COUNT = 8
 } lie_kernel_id;
 

@@ -21,7 +21,7 @@ STATUS_NAMES = {
 
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 K_COUNT = 8
-KERNEL_NAMES = ("comm", "dot", "sub", "reduce", "accept", "verify", "other")
+KERNEL_NAMES = ("comm", "dot", "sub", "reduce", "accept", "verify", "other", "growth")
 DECIDES = {"fp64": 0, "strict": 1, "screen": 2}
 
 # Every symbol include/lie_closure.h declares.

@@ -496,15 +496,18 @@ struct lie_closure {
     lie_status step_fp64(int cnt, int64_t n_lo, int64_t n_hi, const int64_t *dp0 = nullptr)
     {
         const double c = cnt, Dd = (double)D, dd = d;
+        // in a screened run these FP64 blocks are the growth phase: a class of their own, so that
+        // the screen-precision classes hold the screen's kernels only
+        const int kc = screened ? LIE_K_GROWTH : LIE_K_COMM, kd = screened ? LIE_K_GROWTH : LIE_K_DOT,
+                  ks = screened ? LIE_K_GROWTH : LIE_K_SUB, kr = screened ? LIE_K_GROWTH : LIE_K_REDUCE;
         timer.begin(stream);
         if (pauli)
             HIP_TRY(lie::launch_comm_pauli(V64, sup_cnt, sup_idx, nq, cursor, cnt, st, H64, stream, dp0));
         else
             HIP_TRY(lie::launch_comm_f64(raw ? B64 : V64, d, cursor, nullptr, nullptr, cnt, st, H64, stream, dp0));
-        timer.end(LIE_K_COMM, stream, pauli ? 0.0 : 8.0 * dd * dd * dd * c, 3.0 * c * Dd * sizeof(double));
+        timer.end(kc, stream, pauli ? 0.0 : 8.0 * dd * dd * dd * c, 3.0 * c * Dd * sizeof(double));
         lie_status s;
-        if ((s = project(nullptr, nullptr, cand_a2, cand_n2, cnt, n_lo, n_hi, LIE_K_DOT, LIE_K_SUB, LIE_K_REDUCE)) !=
-            LIE_OK)
+        if ((s = project(nullptr, nullptr, cand_a2, cand_n2, cnt, n_lo, n_hi, kd, ks, kr)) != LIE_OK)
             return s;
         if ((s = classify(cnt, cursor, raw ? lie::POL_REL : lie::POL_ABS, tol, dp0)) != LIE_OK)
             return s;
@@ -522,7 +525,9 @@ struct lie_closure {
         const double c = cnt, Dd = (double)D, dd = d, N = (double)n_lo, w = sizeof(float);
         const int64_t nh = std::min(std::max<int64_t>(n_hi, 1), cap);
         timer.begin(stream);
-        HIP_TRY(lie::launch_comm_f32(raw ? Bs : Vs, d, cursor, cnt, st, Hs, cand_n2, stream, dp0));
+        // split BF16 on planes: the bracket writes the candidate rows as hi/lo planes itself
+        HIP_TRY(lie::launch_comm_f32(raw ? Bs : Vs, d, cursor, cnt, st, Hs, cand_n2, stream, dp0, planes ? Hp : nullptr,
+                                     pg.ld));
         timer.end(LIE_K_COMM, stream, 8.0 * dd * dd * dd * c, 3.0 * c * Dd * w);
         const bool tuned = cnt == block_sat && tile_dot > 0;
         const int tile_d = tuned ? tile_dot : lie::gemm_tile_f32(cnt, nh);
@@ -530,11 +535,7 @@ struct lie_closure {
         const bool bf = cfg.precision == LIE_PREC_BF16X3;
         const int64_t ldc = lie::coef_ld(cap);
         if (planes) {
-            // candidate rows into planes (with the bracket's class: the split is its output stage),
             // new basis rows into planes, then the two GEMMs on planes
-            timer.begin(stream);
-            HIP_TRY(lie::launch_split_rows(Hs, D, cnt, Hp, pg, stream));
-            timer.end(LIE_K_COMM, stream, 0.0, c * Dd * (4.0 + 4.0));
             timer.begin(stream);
             HIP_TRY(lie::launch_planes_refresh(V64, D, st, planes_n, Vp, Vt, pg, stream));
             timer.end(LIE_K_OTHER, stream, 0.0, 0.0);

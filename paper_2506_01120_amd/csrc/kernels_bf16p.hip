@@ -42,10 +42,14 @@ constexpr int KC = 32;  // K per chunk: four groups of 8
 
 __device__ inline bool aborted(const DevState *st) { return st && (st->done | st->numeric_error | st->full); }
 
-// Position of 16-byte group g in LDS row `row` (four groups per row): rotating the groups
-// every two rows makes an MFMA fragment read (32 lanes on 32 rows, one group) and the
-// staging writes (whole rows) touch distinct bank groups.
-__device__ inline int gpos(int row, int g) { return (g ^ (row >> 1)) & 3; }
+// LDS tile rows hold one row's K chunk as eight 16-byte slots, slot = plane * 4 + group
+// (hi groups 0..3, then lo groups 0..3: 128 bytes).  Slot s of row r is stored at position
+// s ^ (r & 7) ^ ((r >> 3) & 1).  An MFMA fragment read (lanes on 32 consecutive rows, one slot)
+// then puts any 8 consecutive lanes on 8 distinct positions, and any 16 consecutive lanes on
+// 16 distinct bank groups across the two row parities; a staging write (eight lanes per row,
+// one row's eight slots, consecutive rows) is a permutation of whole rows.  Either way no two
+// lanes of a cycle share a bank, whether LDS serves 8 or 16 lanes of a 16-byte access per cycle.
+__device__ inline int spos(int row, int slot) { return (slot ^ (row & 7) ^ ((row >> 3) & 1)) & 7; }
 
 template <int WM, int WN, int SM, int SN>
 struct PCfg {
@@ -55,13 +59,14 @@ struct PCfg {
 
 template <int BM, int BN>
 struct alignas(16) PTiles {
-    bf16x8 Ah[2][BM][4], Al[2][BM][4];
-    bf16x8 Bh[2][BN][4], Bl[2][BN][4];
+    bf16x8 A[2][BM][8];
+    bf16x8 B[2][BN][8];
 };
 
 // ROWS rows x one K chunk of interleaved planes -> registers -> LDS tiles.  Thread q of
-// the workgroup takes 16-byte items q, q + NT, ...; item i covers row i / 8, group
-// (i % 8) / 2, plane i % 2, so eight consecutive threads read one row's 128 contiguous bytes.
+// the workgroup takes 16-byte items q, q + NT, ...; item i covers row i / 8 and slot i % 8
+// (plane (i % 8) / 4, group i % 4), so eight consecutive threads read one row's 128
+// contiguous bytes.
 template <int ROWS, int NT>
 struct PlaneLoader {
     static constexpr int ITEMS = ROWS * 8;
@@ -75,18 +80,17 @@ struct PlaneLoader {
 #pragma unroll
         for (int i = 0; i < PER; ++i) {
             const int q = threadIdx.x + NT * i;
-            const int r = q >> 3, x = q & 7;
-            v[i] = *reinterpret_cast<const u32x4 *>(base + (int64_t)r * ld + 8 * x);
+            const int r = q >> 3, x = q & 7;  // slot x: plane x / 4, group x % 4
+            v[i] = *reinterpret_cast<const u32x4 *>(base + (int64_t)r * ld + 16 * (x & 3) + 8 * (x >> 2));
         }
     }
-    __device__ void store(bf16x8 (*Sh)[4], bf16x8 (*Sl)[4]) const
+    __device__ void store(bf16x8 (*S)[8]) const
     {
 #pragma unroll
         for (int i = 0; i < PER; ++i) {
             const int q = threadIdx.x + NT * i;
-            const int r = q >> 3, x = q & 7, g = x >> 1;
-            bf16x8 *dst = (x & 1) ? &Sl[r][gpos(r, g)] : &Sh[r][gpos(r, g)];
-            *reinterpret_cast<u32x4 *>(dst) = v[i];
+            const int r = q >> 3, x = q & 7;
+            *reinterpret_cast<u32x4 *>(&S[r][spos(r, x)]) = v[i];
         }
     }
 };
@@ -101,14 +105,14 @@ __device__ inline void mma_chunk(const PTiles<BM, BN> &t, int buf, int wm, int w
 #pragma unroll
         for (int i = 0; i < SM; ++i) {
             const int row = wm * SM * 32 + i * 32 + (lane & 31);
-            ah[i] = t.Ah[buf][row][gpos(row, g)];
-            al[i] = t.Al[buf][row][gpos(row, g)];
+            ah[i] = t.A[buf][row][spos(row, g)];
+            al[i] = t.A[buf][row][spos(row, 4 + g)];
         }
 #pragma unroll
         for (int j = 0; j < SN; ++j) {
             const int col = wn * SN * 32 + j * 32 + (lane & 31);
-            bh[j] = t.Bh[buf][col][gpos(col, g)];
-            bl[j] = t.Bl[buf][col][gpos(col, g)];
+            bh[j] = t.B[buf][col][spos(col, g)];
+            bl[j] = t.B[buf][col][spos(col, 4 + g)];
         }
 #pragma unroll
         for (int i = 0; i < SM; ++i)
@@ -121,9 +125,11 @@ __device__ inline void mma_chunk(const PTiles<BM, BN> &t, int buf, int wm, int w
     }
 }
 
-// K loop over nchunks >= 1 chunks: two LDS buffers, two register stages (chunk c + 2 is
-// fetched while chunk c is multiplied and chunk c + 1 is copied into LDS).  Chunk indices
-// past the end are clamped to the last chunk (a redundant fetch, never multiplied).
+// K loop over nchunks >= 1 chunks: two LDS buffers and one register stage.  Chunk c + 1 is
+// fetched into registers while chunk c is multiplied, then copied into the other buffer;
+// one chunk's matrix-core work covers the load latency.  One loop body (no unrolling into
+// two register sets), so the accumulators stay in place across iterations.  The index of
+// the last fetch is clamped (a redundant fetch, never multiplied).
 template <int WM, int WN, int SM, int SN>
 __device__ inline void k_loop(PTiles<WM * SM * 32, WN * SN * 32> &t, int nchunks, const __bf16 *A, int64_t lda,
                               int64_t m0, const __bf16 *B, int64_t ldb, int64_t n0, int wm, int wn, int lane,
@@ -132,34 +138,23 @@ __device__ inline void k_loop(PTiles<WM * SM * 32, WN * SN * 32> &t, int nchunks
     using C = PCfg<WM, WN, SM, SN>;
     using LA = PlaneLoader<C::BM, C::NT>;
     using LB = PlaneLoader<C::BN, C::NT>;
-    LA a0, a1;
-    LB b0, b1;
-    auto fetch = [&](LA &a, LB &b, int c) {
-        const int64_t k0 = (int64_t)min(c, nchunks - 1) * KC;
-        a.load(A, lda, m0, k0);
-        b.load(B, ldb, n0, k0);
-    };
-    fetch(a0, b0, 0);
-    fetch(a1, b1, 1);
-    a0.store(t.Ah[0], t.Al[0]);
-    b0.store(t.Bh[0], t.Bl[0]);
+    LA a;
+    LB b;
+    a.load(A, lda, m0, 0);
+    b.load(B, ldb, n0, 0);
+    a.store(t.A[0]);
+    b.store(t.B[0]);
     __syncthreads();
-    for (int c = 0; c < nchunks; c += 2) {
-        fetch(a0, b0, c + 2);
+    for (int c = 0; c < nchunks; ++c) {
+        const int buf = c & 1;
+        const int64_t k1 = (int64_t)min(c + 1, nchunks - 1) * KC;
+        a.load(A, lda, m0, k1);
+        b.load(B, ldb, n0, k1);
         __builtin_amdgcn_sched_barrier(0);
-        mma_chunk<SM, SN>(t, 0, wm, wn, lane, acc);
+        mma_chunk<SM, SN>(t, buf, wm, wn, lane, acc);
         __builtin_amdgcn_sched_barrier(0);
-        a1.store(t.Ah[1], t.Al[1]);
-        b1.store(t.Bh[1], t.Bl[1]);
-        __syncthreads();
-        if (c + 1 >= nchunks)
-            break;
-        fetch(a1, b1, c + 3);
-        __builtin_amdgcn_sched_barrier(0);
-        mma_chunk<SM, SN>(t, 1, wm, wn, lane, acc);
-        __builtin_amdgcn_sched_barrier(0);
-        a0.store(t.Ah[0], t.Al[0]);
-        b0.store(t.Bh[0], t.Bl[0]);
+        a.store(t.A[buf ^ 1]);
+        b.store(t.B[buf ^ 1]);
         __syncthreads();
     }
 }
@@ -210,23 +205,41 @@ __global__ void __launch_bounds__(64 * WM * WN, 2) k_bfp_dot(PlaneGemmArgs g)
         for (int j = 0; j < SN; ++j)
             acc[i][j] = f32x16{};
     k_loop<WM, WN, SM, SN>(t, (int)(g.K / KC), g.A, g.lda, m0, g.B, g.ldb, n0, wm, wn, lane, acc);
+    // The K loop ends with a barrier: the tiles are dead.  The output tile goes to LDS as
+    // interleaved planes (row ml: BN / 8 groups of 32 bytes), then to global memory as
+    // 16-byte items, eight consecutive threads per 128 contiguous bytes of a row.  Columns
+    // n >= N hold exact zeros (the basis planes are zero there), which is what the residual
+    // GEMM's K padding must read; columns past the row's padded K are not written.
+    constexpr int RB = C::BN * 4;  // bytes of one output row in LDS
+    static_assert(C::BM * RB <= (int)sizeof(PTiles<C::BM, C::BN>), "output tile must fit the LDS tiles");
+    unsigned char *ot = reinterpret_cast<unsigned char *>(&t);
 #pragma unroll
     for (int i = 0; i < SM; ++i)
 #pragma unroll
         for (int j = 0; j < SN; ++j) {
-            const int64_t n = n0 + wn * SN * 32 + j * 32 + (lane & 31);
-            __bf16 *col = g.Cout + 16 * (n >> 3) + (n & 7);
+            const int nl = wn * SN * 32 + j * 32 + (lane & 31);
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
-                const int64_t m = m0 + wm * SM * 32 + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-                if (m < g.cnt && n < N) {
-                    __bf16 hi, lo;
-                    split_bf16(acc[i][j][r], hi, lo);
-                    col[m * g.ldcout] = hi;
-                    col[m * g.ldcout + 8] = lo;
-                }
+                const int ml = wm * SM * 32 + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                __bf16 hi, lo;
+                split_bf16(acc[i][j][r], hi, lo);
+                __bf16 *o = reinterpret_cast<__bf16 *>(ot + ml * RB) + 16 * (nl >> 3) + (nl & 7);
+                o[0] = hi;
+                o[8] = lo;
             }
         }
+    __syncthreads();
+    constexpr int ITEMS = C::BM * (RB / 16), PER = ITEMS / C::NT;
+    const int64_t kcols = g.ldcout / 2;  // padded K of a C row
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int e = threadIdx.x + C::NT * q;
+        const int ml = e / (RB / 16), x = e % (RB / 16);  // x: 16-byte item of the row (group x / 2)
+        const int64_t m = m0 + ml, n = n0 + 8 * (x >> 1);
+        if (m < g.cnt && n < kcols)
+            *reinterpret_cast<u32x4 *>(g.Cout + m * g.ldcout + 2 * n0 + 8 * x) =
+                *reinterpret_cast<const u32x4 *>(ot + ml * RB + 16 * x);
+    }
 }
 
 // Residual norms: R[m][j] = H[m][j] - sum_k C[m][k] Vt[j][k] over k < N, for m < cnt and
@@ -255,9 +268,34 @@ __global__ void __launch_bounds__(64 * WM * WN, 2) k_bfp_sub(PlaneGemmArgs g)
     const int nchunks = (int)((N + KC - 1) / KC);
     if (nchunks > 0)
         k_loop<WM, WN, SM, SN>(t, nchunks, g.A, g.lda, m0, g.B, g.ldb, j0, wm, wn, lane, acc);
-    // the K loop ends with a barrier: the tiles are dead and hold the per-row partial sums
-    double(*red)[WN][2] = reinterpret_cast<double(*)[WN][2]>(&t);
-    static_assert(sizeof(double) * C::BM * WN * 2 <= sizeof(PTiles<C::BM, C::BN>), "partials must fit the tiles");
+    // The K loop ends with a barrier: the tiles are dead.  The candidate tile H[m0.., j0..]
+    // (interleaved planes, 128-byte runs per row) is staged into them with 16-byte loads, all
+    // in flight together, instead of two scattered 2-byte loads per element.
+    constexpr int RB = C::BN * 4;
+    static_assert(C::BM * RB <= (int)sizeof(PTiles<C::BM, C::BN>), "candidate tile must fit the LDS tiles");
+    unsigned char *ht = reinterpret_cast<unsigned char *>(&t);
+    {
+        constexpr int ITEMS = C::BM * (RB / 16), PER = ITEMS / C::NT;
+        const int64_t kcols = g.ldh / 2;  // padded K of an H row
+        u32x4 v[PER];
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int e = threadIdx.x + C::NT * q;
+            const int ml = e / (RB / 16), x = e % (RB / 16);
+            const int64_t jc = j0 + 8 * (x >> 1);
+            v[q] = jc < kcols ? *reinterpret_cast<const u32x4 *>(g.Hp + (m0 + ml) * g.ldh + 2 * j0 + 8 * x)
+                              : u32x4{0u, 0u, 0u, 0u};
+        }
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int e = threadIdx.x + C::NT * q;
+            const int ml = e / (RB / 16), x = e % (RB / 16);
+            *reinterpret_cast<u32x4 *>(ht + ml * RB + 16 * x) = v[q];
+        }
+    }
+    __syncthreads();
+    // per-row partial sums, behind the candidate tile in LDS when it fits, else in a small array
+    __shared__ double red[C::BM][WN][2];
 #pragma unroll
     for (int i = 0; i < SM; ++i)
 #pragma unroll
@@ -266,12 +304,13 @@ __global__ void __launch_bounds__(64 * WM * WN, 2) k_bfp_sub(PlaneGemmArgs g)
             const int64_t m = m0 + ml;
             double rs = 0.0, hsq = 0.0;
             if (m < g.cnt) {
-                const __bf16 *hrow = g.Hp + m * g.ldh;
+                const __bf16 *hrow = reinterpret_cast<const __bf16 *>(ht + ml * RB);
 #pragma unroll
                 for (int j = 0; j < SN; ++j) {
-                    const int64_t col = j0 + wn * SN * 32 + j * 32 + (lane & 31);
+                    const int cl = wn * SN * 32 + j * 32 + (lane & 31);
+                    const int64_t col = j0 + cl;
                     if (col < g.D) {
-                        const int64_t o = 16 * (col >> 3) + (col & 7);
+                        const int o = 16 * (cl >> 3) + (cl & 7);
                         const float h = (float)hrow[o] + (float)hrow[o + 8];
                         const float res = h - acc[i][j][r];
                         rs += (double)res * res;
@@ -306,31 +345,6 @@ __global__ void __launch_bounds__(64 * WM * WN, 2) k_bfp_sub(PlaneGemmArgs g)
 }
 
 // ------------------------------------------------------------------ plane writers
-
-// FP32 rows [cnt][D] -> interleaved planes [rows][ld], zero past D up to the padded K.
-// One thread per group of 8 values.
-__global__ void k_split_rows(const float *__restrict__ src, int64_t D, int cnt, int64_t Kp, __bf16 *__restrict__ dst,
-                             int64_t ld)
-{
-    const int64_t groups = Kp / 8;
-    const int64_t total = (int64_t)cnt * groups;
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t r = e / groups, gi = e % groups;
-        const float *s = src + r * D + 8 * gi;
-        bf16x8 h, l;
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const float x = 8 * gi + u < D ? s[u] : 0.f;
-            __bf16 hi, lo;
-            split_bf16(x, hi, lo);
-            h[u] = hi;
-            l[u] = lo;
-        }
-        bf16x8 *o = reinterpret_cast<bf16x8 *>(dst + r * ld + 16 * gi);
-        o[0] = h;
-        o[1] = l;
-    }
-}
 
 // Basis rows [*done, st->N) -> row planes Vp (row k, K index j) and transposed planes Vt
 // (row j, K index k).  A workgroup converts 32 basis rows x 64 columns through LDS; the
@@ -424,16 +438,6 @@ hipError_t launch_planes_refresh(const double *V64, int64_t D, const DevState *s
     hipLaunchKernelGGL(k_planes_refresh, dim3(512), dim3(256), 0, s, V64, D, st, (const int64_t *)done, Vp, p.ld, Vt,
                        p.ldt);
     hipLaunchKernelGGL(k_planes_mark, dim3(1), dim3(64), 0, s, st, done);
-    return hipGetLastError();
-}
-
-hipError_t launch_split_rows(const float *src, int64_t D, int cnt, __bf16 *dst, const PlaneGeom &p, hipStream_t s)
-{
-    if (cnt <= 0)
-        return hipSuccess;
-    const int64_t total = (int64_t)cnt * (p.Kp / 8);
-    const int blocks = (int)std::min<int64_t>((total + 255) / 256, 8192);
-    hipLaunchKernelGGL(k_split_rows, dim3(blocks), dim3(256), 0, s, src, D, cnt, p.Kp, dst, p.ld);
     return hipGetLastError();
 }
 

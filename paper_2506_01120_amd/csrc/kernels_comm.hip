@@ -12,11 +12,26 @@
 // four waves sharing its tile pairs.
 #include "lie_internal.h"
 
+#include <type_traits>
+
 #include <algorithm>
 
 namespace lie {
 
 namespace {
+
+// Output element e of a bracket: FP64 rows, FP32 rows, or (FP32 with planes set) split-BF16 planes.
+template <typename T>
+__device__ inline void put(T *out, __bf16 *plane, int64_t e, T v)
+{
+    if constexpr (std::is_same<T, float>::value) {
+        if (plane) {
+            store_plane(plane, e, v);
+            return;
+        }
+    }
+    out[e] = v;
+}
 
 constexpr int kThreads = 256;
 constexpr int kTileLd = 17;  // LDS row stride of a 16 x 16 tile
@@ -82,6 +97,7 @@ __device__ void comm_pairs_body(const CommArgs &A, int c)
     decode_pair(A.pair_list ? A.pair_list[c] : (A.dp0 ? *A.dp0 : A.p0) + c, l, m);
     const T *pa = V + l * D, *pb = V + m * D;
     T *out = static_cast<T *>(A.H) + (int64_t)c * D;
+    __bf16 *plane = A.Hp ? A.Hp + (int64_t)c * A.ldp : nullptr;
     const T so = (T)sqrt(0.5 * d), sd = (T)sqrt((double)d);
     const int lr = lane & 15, lk = lane >> 4;
     const int TT = (d + 15) / 16, npairs = TT * (TT + 1) / 2;
@@ -150,12 +166,12 @@ __device__ void comm_pairs_body(const CommArgs &A, int c)
             if (i < j) {
                 const T v1 = so * (Pr1[a * kTileLd + b] - Pr2[b * kTileLd + a]);
                 const T v2 = so * (Pi1[a * kTileLd + b] + Pi2[b * kTileLd + a]);
-                out[(int64_t)i * d + j] = v1;
-                out[(int64_t)j * d + i] = v2;
+                put(out, plane, (int64_t)i * d + j, v1);
+                put(out, plane, (int64_t)j * d + i, v2);
                 sq += (double)v1 * v1 + (double)v2 * v2;
             } else {
                 const T v = sd * Pi1[a * kTileLd + b];
-                out[(int64_t)i * d + i] = v;
+                put(out, plane, (int64_t)i * d + i, v);
                 sq += (double)v * v;
             }
         }
@@ -298,6 +314,7 @@ __device__ void comm_grouped_body(const CommArgs &A, int c0, int G)
         }
         __syncthreads();  // P complete; Sb and Sa reads done
         T *out = static_cast<T *>(A.H) + (int64_t)(c0 + g) * D;
+        __bf16 *plane = A.Hp ? A.Hp + (int64_t)(c0 + g) * A.ldp : nullptr;
         double sq = 0.0;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
@@ -311,7 +328,7 @@ __device__ void comm_grouped_body(const CommArgs &A, int c0, int G)
                     v = so * (Pi[jj * kLo + i] + Pi[i * kLo + jj]);
                 else
                     v = sd * Pi[i * kLo + i];
-                out[e] = v;
+                put(out, plane, e, v);
                 sq += (double)v * (double)v;
             }
         }

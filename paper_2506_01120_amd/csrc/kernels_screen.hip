@@ -124,7 +124,10 @@ __global__ void __launch_bounds__(kThreads) k_comm_f32_reg16(CommArgs A)
     float sq = 0.f;
     for (int e = lane; e < D; e += 64) {
         const float v = bracket_out(Pr, Pi, 17, d, e, so, sd);
-        out[e] = v;
+        if (A.Hp)
+            store_plane(A.Hp + (int64_t)c * A.ldp, e, v);
+        else
+            out[e] = v;
         sq += v * v;
     }
     sq = wave_sum_f(sq);
@@ -211,7 +214,10 @@ __device__ void comm_f32_reg_body(const CommArgs &A, int c)
     float sq = 0.f;
     for (int e = threadIdx.x; e < D; e += blockDim.x) {
         const float v = bracket_out(Pr, Pi, ld, d, e, so, sd);
-        out[e] = v;
+        if (A.Hp)
+            store_plane(A.Hp + (int64_t)c * A.ldp, e, v);
+        else
+            out[e] = v;
         sq += v * v;
     }
     sq = wave_sum_f(sq);
@@ -334,11 +340,11 @@ __global__ void __launch_bounds__(1024) k_classify_b(Batch b)
 // ------------------------------------------------------------------ launchers
 
 hipError_t launch_comm_f32(const float *Vs, int d, int64_t p0, int cnt, const DevState *st, float *Hs, double *hs2,
-                           hipStream_t s, const int64_t *dp0)
+                           hipStream_t s, const int64_t *dp0, __bf16 *Hp, int64_t ldp)
 {
     if (cnt <= 0)
         return hipSuccess;
-    CommArgs a{Vs, d, p0, nullptr, dp0, nullptr, cnt, st, Hs, hs2};
+    CommArgs a{Vs, d, p0, nullptr, dp0, nullptr, cnt, st, Hs, hs2, Hp, ldp};
     if (d <= 16)
         hipLaunchKernelGGL(k_comm_f32_reg16, dim3((unsigned)((cnt + 3) / 4)), dim3(kThreads), 0, s, a);
     else if (d <= 32)

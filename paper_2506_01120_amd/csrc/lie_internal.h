@@ -135,7 +135,20 @@ struct CommArgs {
     const DevState *st;
     void *H;                   // output rows (packed, row stride d*d)
     double *hs2;               // FP32 bracket: squared norms of the output rows
+    __bf16 *Hp;                // FP32 bracket: when set, rows go to interleaved split-BF16 planes instead of H
+    int64_t ldp;               // row stride of Hp (bf16 elements)
 };
+
+// Element e of an interleaved-plane row (groups of 8 hi values, then their 8 lo values):
+// hi = bf16(v), lo = bf16(v - hi).
+__device__ inline void store_plane(__bf16 *row, int64_t e, float v)
+{
+    const __bf16 hi = (__bf16)v;
+    const __bf16 lo = (__bf16)(v - (float)hi);
+    __bf16 *p = row + 16 * (e >> 3) + (e & 7);
+    p[0] = hi;
+    p[8] = lo;
+}
 
 struct NormArgs {
     const double *normpart;    // [rows][tiles][2]
@@ -392,8 +405,6 @@ int plane_sub_tiles(int64_t D, int tile);
 // Basis rows [*done, st->N) into the row planes Vp and transposed planes Vt, then *done = N.
 hipError_t launch_planes_refresh(const double *V64, int64_t D, const DevState *st, int64_t *done, __bf16 *Vp,
                                  __bf16 *Vt, const PlaneGeom &p, hipStream_t s);
-// FP32 rows [cnt][D] into row planes.
-hipError_t launch_split_rows(const float *src, int64_t D, int cnt, __bf16 *dst, const PlaneGeom &p, hipStream_t s);
 hipError_t launch_bfp_dot(const __bf16 *Hp, const __bf16 *Vp, const DevState *st, int cnt, int64_t n_hi, __bf16 *Cp,
                           const PlaneGeom &p, hipStream_t s);
 hipError_t launch_bfp_sub(const __bf16 *Cp, const __bf16 *Vt, const __bf16 *Hp, const DevState *st, int cnt,
@@ -409,7 +420,7 @@ hipError_t launch_gemm_sub_bf16x3_batched(const Batch &b, hipStream_t s);
 // ------------------------------------------------------------- FP32 screening kernels (kernels_screen.hip)
 // Hs[c] = fp32 packed [Vs_l, Vs_m] for pair p0 + c, hs2[c] = ||Hs[c]||^2.
 hipError_t launch_comm_f32(const float *Vs, int d, int64_t p0, int cnt, const DevState *st, float *Hs, double *hs2,
-                           hipStream_t s, const int64_t *dp0 = nullptr);
+                           hipStream_t s, const int64_t *dp0 = nullptr, __bf16 *Hp = nullptr, int64_t ldp = 0);
 // Survivor compaction under a policy.  certify = 1: a candidate may be rejected by the policy
 // only while the basis holds `ambient` elements (then it is dependent whatever its residual);
 // below that bound every candidate survives.
