@@ -10,7 +10,7 @@
 //
 // Plane layout ("interleaved planes"): a row of K values is stored as K/8
 // groups of 32 bytes, the 8 hi values of the group followed by its 8 lo values;
-// K is padded to a multiple of 32 with zeros and rows are padded to whole
+// K is padded to a multiple of 64 with zeros and rows are padded to whole
 // workgroup tiles, so every load of a tile is in bounds and unconditional.
 //
 //   coefficients  C[m][n] = sum_k H[m][k] V[n][k]       (H planes x basis planes, K = d^2)
@@ -125,11 +125,12 @@ __device__ inline void mma_chunk(const PTiles<BM, BN> &t, int buf, int wm, int w
     }
 }
 
-// K loop over nchunks >= 1 chunks: two LDS buffers and one register stage.  Chunk c + 1 is
-// fetched into registers while chunk c is multiplied, then copied into the other buffer;
-// one chunk's matrix-core work covers the load latency.  One loop body (no unrolling into
-// two register sets), so the accumulators stay in place across iterations.  The index of
-// the last fetch is clamped (a redundant fetch, never multiplied).
+// K loop over an even number nchunks >= 2 of chunks: two LDS buffers and two register
+// stages.  Chunk c + 2 is fetched into registers while chunk c is multiplied, so each fetch
+// has two chunks of matrix-core work to arrive; chunk c + 1 is copied into the other buffer
+// after chunk c is multiplied.  The loop body covers two chunks and has no exit in between
+// (callers pad K to whole chunk pairs with zeros), which keeps the accumulators in place.
+// Fetch indices past the end are clamped to the last chunk (redundant, never multiplied).
 template <int WM, int WN, int SM, int SN>
 __device__ inline void k_loop(PTiles<WM * SM * 32, WN * SN * 32> &t, int nchunks, const __bf16 *A, int64_t lda,
                               int64_t m0, const __bf16 *B, int64_t ldb, int64_t n0, int wm, int wn, int lane,
@@ -138,23 +139,32 @@ __device__ inline void k_loop(PTiles<WM * SM * 32, WN * SN * 32> &t, int nchunks
     using C = PCfg<WM, WN, SM, SN>;
     using LA = PlaneLoader<C::BM, C::NT>;
     using LB = PlaneLoader<C::BN, C::NT>;
-    LA a;
-    LB b;
-    a.load(A, lda, m0, 0);
-    b.load(B, ldb, n0, 0);
-    a.store(t.A[0]);
-    b.store(t.B[0]);
+    LA a0, a1;
+    LB b0, b1;
+    auto fetch = [&](LA &a, LB &b, int c) {
+        const int64_t k0 = (int64_t)min(c, nchunks - 1) * KC;
+        a.load(A, lda, m0, k0);
+        b.load(B, ldb, n0, k0);
+    };
+    fetch(a0, b0, 0);
+    fetch(a1, b1, 1);
+    a0.store(t.A[0]);
+    b0.store(t.B[0]);
     __syncthreads();
-    for (int c = 0; c < nchunks; ++c) {
-        const int buf = c & 1;
-        const int64_t k1 = (int64_t)min(c + 1, nchunks - 1) * KC;
-        a.load(A, lda, m0, k1);
-        b.load(B, ldb, n0, k1);
+    for (int c = 0; c < nchunks; c += 2) {
+        fetch(a0, b0, c + 2);
         __builtin_amdgcn_sched_barrier(0);
-        mma_chunk<SM, SN>(t, buf, wm, wn, lane, acc);
+        mma_chunk<SM, SN>(t, 0, wm, wn, lane, acc);
         __builtin_amdgcn_sched_barrier(0);
-        a.store(t.A[buf ^ 1]);
-        b.store(t.B[buf ^ 1]);
+        a1.store(t.A[1]);
+        b1.store(t.B[1]);
+        __syncthreads();
+        fetch(a1, b1, c + 3);
+        __builtin_amdgcn_sched_barrier(0);
+        mma_chunk<SM, SN>(t, 1, wm, wn, lane, acc);
+        __builtin_amdgcn_sched_barrier(0);
+        a0.store(t.A[0]);
+        b0.store(t.B[0]);
         __syncthreads();
     }
 }
@@ -204,7 +214,7 @@ __global__ void __launch_bounds__(64 * WM * WN, 2) k_bfp_dot(PlaneGemmArgs g)
 #pragma unroll
         for (int j = 0; j < SN; ++j)
             acc[i][j] = f32x16{};
-    k_loop<WM, WN, SM, SN>(t, (int)(g.K / KC), g.A, g.lda, m0, g.B, g.ldb, n0, wm, wn, lane, acc);
+    k_loop<WM, WN, SM, SN>(t, (int)(g.K / KC), g.A, g.lda, m0, g.B, g.ldb, n0, wm, wn, lane, acc);  // K: whole chunk pairs
     // The K loop ends with a barrier: the tiles are dead.  The output tile goes to LDS as
     // interleaved planes (row ml: BN / 8 groups of 32 bytes), then to global memory as
     // 16-byte items, eight consecutive threads per 128 contiguous bytes of a row.  Columns
@@ -265,7 +275,8 @@ __global__ void __launch_bounds__(64 * WM * WN, 2) k_bfp_sub(PlaneGemmArgs g)
 #pragma unroll
         for (int j = 0; j < SN; ++j)
             acc[i][j] = f32x16{};
-    const int nchunks = (int)((N + KC - 1) / KC);
+    // K = N rounded up to whole chunk pairs: the C and transposed basis planes are zero there
+    const int nchunks = 2 * (int)((N + 2 * KC - 1) / (2 * KC));
     if (nchunks > 0)
         k_loop<WM, WN, SM, SN>(t, nchunks, g.A, g.lda, m0, g.B, g.ldb, j0, wm, wn, lane, acc);
     // The K loop ends with a barrier: the tiles are dead.  The candidate tile H[m0.., j0..]
@@ -420,10 +431,10 @@ __global__ void k_planes_mark(const DevState *st, int64_t *done)
 PlaneGeom plane_geom(int64_t D, int64_t cap, int bmax)
 {
     PlaneGeom p;
-    p.Kp = (D + KC - 1) / KC * KC;
+    p.Kp = (D + 2 * KC - 1) / (2 * KC) * (2 * KC);  // whole chunk pairs
     p.ld = 2 * p.Kp;
     p.cap_rows = (cap + 255) / 256 * 256;
-    p.ldt_k = (cap + KC - 1) / KC * KC;
+    p.ldt_k = (cap + 2 * KC - 1) / (2 * KC) * (2 * KC);
     p.ldt = 2 * p.ldt_k;
     p.d_rows = (D + 255) / 256 * 256;
     p.b_rows = ((int64_t)std::max(bmax, 1) + 255) / 256 * 256;

@@ -373,13 +373,13 @@ hipError_t launch_gather_states(const DevState *const *src, int n, DevState *dst
 // Same contracts as the FP32 coefficient / residual GEMMs; FP32 operands are
 // split into bf16 hi + lo while staged, products are hi*hi + hi*lo + lo*hi.
 // Split-BF16 GEMMs on pre-split interleaved planes (kernels_bf16p.hip): a row of K values
-// is K/8 groups of 32 bytes, 8 hi values then 8 lo values; K is padded to a multiple of 32
+// is K/8 groups of 32 bytes, 8 hi values then 8 lo values; K is padded to a multiple of 64
 // and rows to whole tiles, all padding zero.
 struct PlaneGeom {
-    int64_t Kp;        // d^2 padded to a multiple of 32 (K of the coefficient GEMM)
+    int64_t Kp;        // d^2 padded to a multiple of 64 (K of the coefficient GEMM)
     int64_t ld;        // row stride of H and V row planes, in bf16 elements (2 Kp)
     int64_t cap_rows;  // rows of the V row planes (capacity padded)
-    int64_t ldt_k;     // capacity padded to a multiple of 32 (K of the residual GEMM)
+    int64_t ldt_k;     // capacity padded to a multiple of 64 (K of the residual GEMM)
     int64_t ldt;       // row stride of the transposed V planes and of the C planes (2 ldt_k)
     int64_t d_rows;    // rows of the transposed V planes (d^2 padded)
     int64_t b_rows;    // rows of the H and C planes (block size padded)
