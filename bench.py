@@ -142,8 +142,8 @@ def roofline(stats, precision: str):
 KERNEL_SOURCE = {
     "accept": "kernels_accept.hip",
     "verify": "kernels_gemm.hip",
-    "dot": {"fp64": "kernels_gemm.hip", "fp32": "kernels_gemm.hip", "bf16x3": "kernels_bf16.hip"},
-    "sub": {"fp64": "kernels_gemm.hip", "fp32": "kernels_gemm.hip", "bf16x3": "kernels_bf16.hip"},
+    "dot": {"fp64": "kernels_gemm.hip", "fp32": "kernels_gemm.hip", "bf16x3": "kernels_bf16p.hip"},
+    "sub": {"fp64": "kernels_gemm.hip", "fp32": "kernels_gemm.hip", "bf16x3": "kernels_bf16p.hip"},
     "comm": {"fp64": "kernels_f64.hip", "fp32": "kernels_screen.hip", "bf16x3": "kernels_screen.hip"},
 }
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.txt")

@@ -203,6 +203,7 @@ typedef struct lie_closure_stats {
     int64_t reorth_passes;        /* in-block decisions that took a further pass against the whole basis because
                                      the elements appended earlier in the block removed nearly all of the
                                      candidate's norm (ratio above 64) */
+    int64_t pauli_terms;          /* sparse Pauli-sum handles: terms stored by the basis (16 bytes each) */
 } lie_closure_stats;
 
 /* Fill *cfg with defaults (struct_size set).  Returns LIE_ERR_ARG for NULL. */
@@ -276,6 +277,41 @@ lie_status lie_closure_orthogonality_noalloc(lie_closure *h, double *loss_dev);
 
 /* Counters and residual-gap statistics (out->struct_size must be set). */
 lie_status lie_closure_stats_get(const lie_closure *h, lie_closure_stats *out);
+
+/*
+ * Sparse Pauli-sum representation (the paper's sparse representation of operators,
+ * Sections 3 and 4.2): generators and basis elements are real combinations
+ * sum_s c_s iP_s of Pauli strings P_s = i^{|x & z|} X^x Z^z on n qubits, stored as term
+ * lists -- memory proportional to each element's support, no d x d matrices.  Distinct
+ * strings are orthonormal in the paper's inner product, so the coefficients are the
+ * element's coordinates.  Runs Algorithm 4 in FP64 (brackets of term lists, inner
+ * products by joining supports, two projection passes, the same decision rule as the
+ * dense path), one candidate at a time; terms below 1e-14 of a candidate's norm after a
+ * summation are dropped.
+ *   n_qubits      -- 1..31
+ *   term_offsets  -- host, n_gen + 1 non-decreasing offsets (term_offsets[0] = 0): generator g
+ *                    is terms [term_offsets[g], term_offsets[g+1])
+ *   strings       -- host, one 64-bit key per term: (x << 32) | z, bit q of x (z) set when
+ *                    the string has X or Y (Z or Y) on the qubit of weight 2^q in the basis
+ *                    index (qubit 0 of a label "P_0 P_1 ... P_{n-1}" is the most significant)
+ *   coefs         -- host, real coefficient of iP_s of each term; all inputs are copied
+ *   max_terms     -- capacity of the device term pool (0: 2^24 terms, 256 MiB)
+ *   cfg           -- NULL or FP64 / orthonormalization settings (early_exit, max_dim, device,
+ *                    stream are honoured; max_dim 0 = min(ambient bound, 2^20))
+ * Lists of a bracket (|S_l| |S_m| products) or of a projection longer than 2^20 terms fail
+ * with LIE_ERR_CAPACITY, as does an exhausted pool.  lie_closure_run / _run_budget / _dim /
+ * _stats_get / _free work on the handle; the dense-basis calls return LIE_ERR_STATE.
+ */
+lie_status lie_closure_init_pauli_sparse(lie_closure **out, int32_t n_qubits, int32_t n_gen,
+                                        const int64_t *term_offsets, const uint64_t *strings, const double *coefs,
+                                        double tol, int64_t max_terms, const lie_closure_config *cfg);
+
+/* Basis of a sparse Pauli-sum handle in Algorithm 4's order: element k is terms
+ * [offsets[k], offsets[k+1]) of (strings, coefs), sorted by key, with sum c^2 = 1.
+ *   offsets -- host, dim + 1 entries; strings, coefs -- host, capacity_terms entries each
+ * *terms_written = total terms; LIE_ERR_CAPACITY (nothing else written) if it exceeds capacity_terms. */
+lie_status lie_closure_basis_pauli_sparse(const lie_closure *h, int64_t *offsets, uint64_t *strings, double *coefs,
+                                          int64_t capacity_terms, int64_t *terms_written);
 
 /* Release everything the handle owns.  NULL-safe. */
 void lie_closure_free(lie_closure *h);

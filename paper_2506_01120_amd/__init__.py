@@ -19,7 +19,7 @@ import numpy as np
 from . import _lib
 from ._lib import LieError
 
-__all__ = ["LieClosure", "BatchClosure", "closure", "LieError", "make_config"]
+__all__ = ["LieClosure", "BatchClosure", "PauliSparseClosure", "closure", "LieError", "make_config", "pauli_key"]
 
 
 def make_config(*, precision: str = "fp64", decide: str = "screen", block: int = 0, early_exit: bool = False,
@@ -217,3 +217,115 @@ class BatchClosure:
         s.struct_size = ctypes.sizeof(_lib.Stats)
         _lib.check(self._libh.lie_closure_batch_stats_get(self._h, i, ctypes.byref(s)))
         return s.as_dict()
+
+
+def pauli_key(label: str) -> int:
+    """64-bit key (x << 32) | z of a Pauli-string label such as "XIZY" (qubit 0 leftmost,
+    the most significant bit of the basis index): X sets x, Z sets z, Y sets both."""
+    n = len(label)
+    x = z = 0
+    for q, c in enumerate(label):
+        b = 1 << (n - 1 - q)
+        if c in "XY":
+            x |= b
+        if c in "ZY":
+            z |= b
+        if c not in "IXYZ":
+            raise ValueError(f"not a Pauli label: {label!r}")
+    return (x << 32) | z
+
+
+def pauli_label(key: int, n: int) -> str:
+    """Inverse of :func:`pauli_key` for n qubits."""
+    x, z = key >> 32, key & 0xFFFFFFFF
+    out = []
+    for q in range(n):
+        b = 1 << (n - 1 - q)
+        out.append("Y" if (x & b and z & b) else "X" if x & b else "Z" if z & b else "I")
+    return "".join(out)
+
+
+class PauliSparseClosure:
+    """A closure problem in the sparse Pauli-sum representation (lie_closure_init_pauli_sparse).
+
+    ``generators`` is a list of dicts {label: c}, the generator being sum c iP_label with
+    real c.  ``basis()`` returns the basis as a list of such dicts, in Algorithm 4's order."""
+
+    def __init__(self, n_qubits: int, generators, tol: float, max_terms: int = 0, **config):
+        self._libh = _lib.load()
+        self.n = int(n_qubits)
+        offs, keys, coefs = [0], [], []
+        for g in generators:
+            for label, c in g.items():
+                if len(label) != self.n:
+                    raise ValueError(f"label {label!r} is not on {self.n} qubits")
+                keys.append(pauli_key(label))
+                coefs.append(float(c))
+            offs.append(len(keys))
+        self._offs = np.asarray(offs, dtype=np.int64)
+        self._keys = np.asarray(keys, dtype=np.uint64)
+        self._coefs = np.asarray(coefs, dtype=np.float64)
+        self._cfg = make_config(**config)
+        h = ctypes.c_void_p()
+        _lib.check(self._libh.lie_closure_init_pauli_sparse(
+            ctypes.byref(h), self.n, len(generators), self._offs.ctypes.data, self._keys.ctypes.data,
+            self._coefs.ctypes.data, float(tol), int(max_terms), ctypes.byref(self._cfg)))
+        self._h = h
+
+    def close(self) -> None:
+        h = getattr(self, "_h", None)
+        if h:
+            self._libh.lie_closure_free(h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def run(self, budget: int | None = None) -> bool:
+        """Run the bracket loop (to completion, or at most `budget` candidates); True when complete."""
+        if budget is None:
+            _lib.check(self._libh.lie_closure_run(self._h))
+            return True
+        st = _lib.check(self._libh.lie_closure_run_budget(self._h, int(budget)), allow_incomplete=True)
+        return st == 0
+
+    @property
+    def dim(self) -> int:
+        n = ctypes.c_int64()
+        _lib.check(self._libh.lie_closure_dim(self._h, ctypes.byref(n)))
+        return int(n.value)
+
+    def stats(self) -> dict:
+        s = _lib.Stats()
+        s.struct_size = ctypes.sizeof(_lib.Stats)
+        _lib.check(self._libh.lie_closure_stats_get(self._h, ctypes.byref(s)))
+        return s.as_dict()
+
+    def basis_arrays(self):
+        """(offsets, keys, coefficients) of the basis as numpy arrays."""
+        dim = self.dim
+        offs = np.zeros(dim + 1, dtype=np.int64)
+        w = ctypes.c_int64()
+        st = self._libh.lie_closure_basis_pauli_sparse(self._h, offs.ctypes.data, None, None, 0, ctypes.byref(w))
+        if st not in (0, -7):
+            _lib.check(st)
+        keys = np.zeros(max(w.value, 1), dtype=np.uint64)
+        coefs = np.zeros(max(w.value, 1), dtype=np.float64)
+        _lib.check(self._libh.lie_closure_basis_pauli_sparse(self._h, offs.ctypes.data, keys.ctypes.data,
+                                                             coefs.ctypes.data, int(w.value), ctypes.byref(w)))
+        return offs, keys[: w.value], coefs[: w.value]
+
+    def basis(self) -> list[dict]:
+        offs, keys, coefs = self.basis_arrays()
+        return [{pauli_label(int(keys[t]), self.n): float(coefs[t]) for t in range(offs[k], offs[k + 1])}
+                for k in range(len(offs) - 1)]
+

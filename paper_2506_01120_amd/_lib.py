@@ -30,6 +30,7 @@ EXPORTS = (
     "lie_closure_dim", "lie_closure_basis", "lie_closure_basis_device", "lie_closure_raw_basis",
     "lie_pauli_coordinates", "lie_pauli_matrix",
     "lie_closure_orthogonality", "lie_closure_orthogonality_noalloc",
+    "lie_closure_init_pauli_sparse", "lie_closure_basis_pauli_sparse",
     "lie_closure_stats_get", "lie_closure_free", "lie_status_string", "lie_last_error",
     "lie_closure_batch_init", "lie_closure_batch_run", "lie_closure_batch_dim", "lie_closure_batch_basis",
     "lie_closure_batch_stats_get", "lie_closure_batch_free",
@@ -94,6 +95,7 @@ class Stats(ctypes.Structure):
         ("kernel_flops", ctypes.c_double * K_COUNT),
         ("kernel_bytes", ctypes.c_double * K_COUNT),
         ("reorth_passes", ctypes.c_int64),
+        ("pauli_terms", ctypes.c_int64),
     ]
 
     def as_dict(self) -> dict:
@@ -130,6 +132,8 @@ def _declare(lib: ctypes.CDLL) -> ctypes.CDLL:
         "lie_pauli_matrix": (st, [ctypes.c_int32, vp, vp]),
         "lie_closure_orthogonality": (st, [vp, dblp]),
         "lie_closure_orthogonality_noalloc": (st, [vp, vp]),
+        "lie_closure_init_pauli_sparse": (st, [pp, i32, i32, vp, vp, vp, dbl, i64, ctypes.POINTER(Config)]),
+        "lie_closure_basis_pauli_sparse": (st, [vp, vp, vp, vp, i64, i64p]),
         "lie_closure_stats_get": (st, [vp, ctypes.POINTER(Stats)]),
         "lie_closure_free": (None, [vp]),
         "lie_status_string": (ctypes.c_char_p, [st]),

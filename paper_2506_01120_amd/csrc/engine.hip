@@ -206,6 +206,9 @@ struct lie_closure {
     int nq = 0;
     int *sup_cnt = nullptr;      // cap
     int *sup_idx = nullptr;      // cap x D
+    // sparse Pauli-sum representation (lie_closure_init_pauli_sparse): elements as term lists
+    bool sparse = false;
+    lie::SparsePauli *sp = nullptr;
     // matrix-inversion method (config.method = LIE_METHOD_MATRIX_INVERSION)
     bool inv = false;
     lie::GramInverse *ginv = nullptr;
@@ -247,6 +250,7 @@ struct lie_closure {
         if (graph.exec)
             (void)hipGraphExecDestroy(graph.exec);
         lie::rank_tester_destroy(rank);
+        lie::sparse_pauli_destroy(sp);
         lie::gram_inverse_destroy(ginv);
         for (void *p : {(void *)Xc, (void *)sup_cnt, (void *)sup_idx})
             if (p)
@@ -284,6 +288,14 @@ struct lie_closure {
                         "an independent candidate was found with |V| already at the ambient bound %lld (spurious "
                         "element from round-off)",
                         (long long)ambient);
+        }
+        if (hs.full == 2) {
+            failed = true;
+            return fail(LIE_ERR_CAPACITY, "a bracket's or projection's term list exceeds the scratch lists");
+        }
+        if (hs.full == 3) {
+            failed = true;
+            return fail(LIE_ERR_CAPACITY, "the term pool of the sparse representation is exhausted");
         }
         if (hs.full) {
             failed = true;
@@ -819,8 +831,52 @@ struct lie_closure {
         return s;
     }
 
+    // Sparse Pauli-sum elements: one candidate at a time in Algorithm 4's order, every list
+    // size on the device; the host learns |V| every kSparseQueued candidates.
+    lie_status run_sparse(int64_t budget)
+    {
+        constexpr int64_t kSparseQueued = 256;
+        const auto t0 = std::chrono::steady_clock::now();
+        int64_t spent = 0;
+        lie_status s = LIE_OK;
+        for (;;) {
+            const int64_t N = hs.N;
+            const int64_t avail = lie::pairs_below(N);
+            if (hs.done || (cfg.early_exit && N >= ambient) || cursor >= avail) {
+                done = true;
+                break;
+            }
+            if (budget >= 0 && spent >= budget) {
+                s = LIE_INCOMPLETE;
+                break;
+            }
+            int64_t q = std::min<int64_t>(kSparseQueued, avail - cursor);
+            if (budget >= 0)
+                q = std::min<int64_t>(q, budget - spent);
+            for (int64_t i = 0; i < q; ++i)
+                HIP_TRY(lie::sparse_pauli_candidate(sp, cursor + i, st, tol, cfg.early_exit, ambient, stream));
+            cursor += q;
+            spent += q;
+            blocks += q;
+            if ((s = sync_state()) != LIE_OK || (s = check_state()) != LIE_OK)
+                break;
+        }
+        if (s < 0)
+            failed = true;
+        run_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        return s;
+    }
+
     lie_status run(int64_t budget)
     {
+        if (sparse) {
+            if (failed)
+                return fail(LIE_ERR_STATE, "a previous run of this handle failed");
+            if (done)
+                return LIE_OK;
+            HIP_TRY(hipSetDevice(device));
+            return run_sparse(budget);
+        }
         if (method == LIE_METHOD_MATRIX_INVERSION) {
             if (failed)
                 return fail(LIE_ERR_STATE, "a previous run of this handle failed");
@@ -1279,6 +1335,8 @@ static lie_status basis_common(const lie_closure *h, void *dst, int64_t capacity
 {
     if (!h || !written || (!dst && capacity > 0))
         return fail(LIE_ERR_ARG, "NULL argument");
+    if (h->sparse)
+        return fail(LIE_ERR_STATE, "a sparse Pauli-sum handle returns its basis through lie_closure_basis_pauli_sparse");
     if (h->method != LIE_METHOD_ORTHONORMALIZATION)
         return fail(LIE_ERR_STATE, "this method keeps only the raw basis (lie_closure_raw_basis)");
     const int64_t n = h->hs.N;
@@ -1391,6 +1449,8 @@ lie_status lie_closure_orthogonality(lie_closure *h, double *loss)
 {
     if (!h || !loss)
         return fail(LIE_ERR_ARG, "NULL argument");
+    if (h->sparse)
+        return fail(LIE_ERR_STATE, "a sparse Pauli-sum handle keeps no dense basis");
     if (h->method != LIE_METHOD_ORTHONORMALIZATION)
         return fail(LIE_ERR_STATE, "this method keeps no orthonormal basis");
     const int64_t n = h->hs.N;
@@ -1412,6 +1472,8 @@ lie_status lie_closure_orthogonality_noalloc(lie_closure *h, double *loss_dev)
 {
     if (!h || !loss_dev)
         return fail(LIE_ERR_ARG, "NULL argument");
+    if (h->sparse)
+        return fail(LIE_ERR_STATE, "a sparse Pauli-sum handle keeps no dense basis");
     if (h->method != LIE_METHOD_ORTHONORMALIZATION)
         return fail(LIE_ERR_STATE, "this method keeps no orthonormal basis");
     const int64_t n = h->hs.N;
@@ -1448,6 +1510,12 @@ lie_status lie_closure_stats_get(const lie_closure *h, lie_closure_stats *out)
     out->accepted = h->hs.n_acc;
     out->block_qr_accepted = h->hs.n_bqr;
     out->reorth_passes = h->hs.n_reorth;
+    if (h->sparse) {
+        int64_t terms = 0;
+        if (lie::sparse_pauli_terms(h->sp, h->hs.N, &terms, h->stream) != hipSuccess)
+            return fail(LIE_ERR_DEVICE, "reading the term count failed");
+        out->pauli_terms = terms;
+    }
     out->blocks = h->blocks;
     out->host_syncs = h->host_syncs;
     out->min_accepted_residual = h->hs.min_acc;
@@ -1483,6 +1551,120 @@ lie_status lie_closure_stats_get(const lie_closure *h, lie_closure_stats *out)
         out->kernel_flops[LIE_K_VERIFY] = h->hs.vfy_flops;
         out->kernel_bytes[LIE_K_VERIFY] = h->hs.vfy_bytes;
     }
+    return LIE_OK;
+}
+
+lie_status lie_closure_init_pauli_sparse(lie_closure **out, int32_t n_qubits, int32_t n_gen,
+                                        const int64_t *term_offsets, const uint64_t *strings, const double *coefs,
+                                        double tol, int64_t max_terms, const lie_closure_config *cfg_in)
+{
+    g_last_error.clear();
+    if (!out)
+        return fail(LIE_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    if (n_qubits < 1 || n_qubits > 31)
+        return fail(LIE_ERR_ARG, "n_qubits must be in 1..31 (got %d)", n_qubits);
+    if (n_gen < 1 || !term_offsets || !strings || !coefs)
+        return fail(LIE_ERR_ARG, "NULL argument or n_gen < 1");
+    if (!(tol > 0.0 && tol < 1.0))
+        return fail(LIE_ERR_ARG, "tol must be in (0, 1)");
+    if (max_terms < 0)
+        return fail(LIE_ERR_ARG, "max_terms must be >= 0");
+    if (term_offsets[0] != 0)
+        return fail(LIE_ERR_ARG, "term_offsets[0] must be 0");
+    const uint64_t mask = (1ull << n_qubits) - 1ull;
+    bool identity = false;
+    for (int g = 0; g < n_gen; ++g) {
+        if (term_offsets[g + 1] < term_offsets[g])
+            return fail(LIE_ERR_ARG, "term_offsets must be non-decreasing");
+        for (int64_t t = term_offsets[g]; t < term_offsets[g + 1]; ++t) {
+            const uint64_t x = strings[t] >> 32, z = strings[t] & 0xffffffffull;
+            if ((x & ~mask) || (z & ~mask))
+                return fail(LIE_ERR_ARG, "term %lld names a qubit beyond n_qubits", (long long)t);
+            if (!std::isfinite(coefs[t]))
+                return fail(LIE_ERR_NONFINITE, "coefficient %lld is not finite", (long long)t);
+            if (strings[t] == 0 && coefs[t] != 0.0)
+                identity = true;
+        }
+    }
+    lie_closure_config cfg;
+    lie_status s;
+    if ((s = resolve_config(cfg_in, &cfg)) != LIE_OK)
+        return s;
+    if (cfg.precision != LIE_PREC_FP64 || cfg.method != LIE_METHOD_ORTHONORMALIZATION || cfg.raw_basis)
+        return fail(LIE_ERR_ARG, "the sparse Pauli-sum representation runs Algorithm 4 in FP64 only");
+    lie_closure *h = new (std::nothrow) lie_closure();
+    if (!h)
+        return fail(LIE_ERR_OOM, "host allocation failed");
+    auto bail = [&](lie_status st) {
+        delete h;
+        return st;
+    };
+    h->sparse = true;
+    h->d = 0;
+    h->D = 0;
+    h->tol = tol;
+    h->n_gen = n_gen;
+    h->nq = n_qubits;
+    // traceless generators (no identity term) stay traceless: 4^n - 1 strings, else 4^n
+    h->ambient = (int64_t)1 << (2 * n_qubits);
+    if (!identity)
+        h->ambient -= 1;
+    h->cfg = cfg;
+    h->cap = cfg.max_dim > 0 ? std::min<int64_t>(cfg.max_dim, h->ambient) : std::min<int64_t>(h->ambient, 1 << 20);
+    int dev = cfg.device;
+    if (dev < 0 && hipGetDevice(&dev) != hipSuccess)
+        return bail(fail(LIE_ERR_DEVICE, "hipGetDevice failed"));
+    h->device = dev;
+    if (hipSetDevice(dev) != hipSuccess)
+        return bail(fail(LIE_ERR_DEVICE, "hipSetDevice(%d) failed", dev));
+    if (cfg.stream) {
+        h->stream = (hipStream_t)cfg.stream;
+    } else {
+        if (hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking) != hipSuccess)
+            return bail(fail(LIE_ERR_DEVICE, "hipStreamCreate failed"));
+        h->own_stream = true;
+    }
+    if (hipMalloc(&h->st, sizeof(lie::DevState)) != hipSuccess)
+        return bail(fail(LIE_ERR_OOM, "device allocation failed"));
+    hipError_t e = lie::sparse_pauli_create(&h->sp, n_qubits, h->cap, max_terms > 0 ? max_terms : (int64_t)1 << 24,
+                                            (int64_t)1 << 20, term_offsets, n_gen, strings, coefs, h->stream);
+    if (e != hipSuccess)
+        return bail(fail(e == hipErrorOutOfMemory ? LIE_ERR_OOM : LIE_ERR_DEVICE, "sparse pool setup failed: %s",
+                         hipGetErrorString(e)));
+    h->hs = lie::DevState{};
+    h->hs.min_acc = INFINITY;
+    h->hs.scr_min_indep = INFINITY;
+    if (hipMemcpyAsync(h->st, &h->hs, sizeof h->hs, hipMemcpyHostToDevice, h->stream) != hipSuccess)
+        return bail(fail(LIE_ERR_DEVICE, "state upload failed"));
+    // Algorithm 4's generator phase: each generator against the basis, relative threshold
+    for (int g = 0; g < n_gen; ++g) {
+        if (term_offsets[g + 1] - term_offsets[g] > ((int64_t)1 << 20))
+            return bail(fail(LIE_ERR_CAPACITY, "generator %d has more terms than the scratch lists hold", g));
+        if ((e = lie::sparse_pauli_generator(h->sp, g, h->st, tol, h->ambient, h->stream)) != hipSuccess)
+            return bail(fail(LIE_ERR_DEVICE, "generator phase failed: %s", hipGetErrorString(e)));
+    }
+    if ((s = h->sync_state()) != LIE_OK || (s = h->check_state()) != LIE_OK)
+        return bail(s);
+    *out = h;
+    return LIE_OK;
+}
+
+lie_status lie_closure_basis_pauli_sparse(const lie_closure *h, int64_t *offsets, uint64_t *strings, double *coefs,
+                                          int64_t capacity_terms, int64_t *terms_written)
+{
+    if (!h || !terms_written || !offsets || (capacity_terms > 0 && (!strings || !coefs)))
+        return fail(LIE_ERR_ARG, "NULL argument");
+    if (!h->sparse)
+        return fail(LIE_ERR_STATE, "the handle was not created by lie_closure_init_pauli_sparse");
+    HIP_TRY(hipSetDevice(h->device));
+    const hipError_t e = lie::sparse_pauli_basis(h->sp, h->hs.N, offsets, strings, coefs, capacity_terms,
+                                                 terms_written, h->stream);
+    if (e != hipSuccess)
+        return fail(LIE_ERR_DEVICE, "basis copy failed: %s", hipGetErrorString(e));
+    if (*terms_written > capacity_terms)
+        return fail(LIE_ERR_CAPACITY, "output holds %lld terms, basis has %lld", (long long)capacity_terms,
+                    (long long)*terms_written);
     return LIE_OK;
 }
 

@@ -439,6 +439,25 @@ void rank_tester_destroy(RankTester *t);
 // Synchronises the tester's stream.
 hipError_t rank_tester_run(RankTester *t, const double *B, int64_t N, const double *H, int cnt, unsigned char *flags);
 
+// ------------------------------------------------------------- sparse Pauli-sum representation (pauli_sparse.hip)
+// Elements as sorted (key = x << 32 | z, coefficient of iP) term lists in a pool on the device.
+struct SparsePauli;
+hipError_t sparse_pauli_create(SparsePauli **out, int nq, int64_t cap, int64_t max_terms, int64_t scratch,
+                               const int64_t *gen_off, int n_gen, const uint64_t *keys, const double *coefs,
+                               hipStream_t s);
+void sparse_pauli_destroy(SparsePauli *s);
+// Generator g: projection passes and the relative decision (appends to the pool).
+hipError_t sparse_pauli_generator(SparsePauli *sp, int g, DevState *st, double tol, int64_t ambient, hipStream_t s);
+// Candidate of pair index p: sparse bracket, projection passes, decision.
+hipError_t sparse_pauli_candidate(SparsePauli *sp, int64_t p, DevState *st, double tol, int early_exit,
+                                  int64_t ambient, hipStream_t s);
+// Terms stored by the first N elements (synchronises).
+hipError_t sparse_pauli_terms(const SparsePauli *sp, int64_t N, int64_t *terms, hipStream_t s);
+// Offsets (N + 1), keys and coefficients of the first N elements; nothing is copied but
+// *written when it exceeds capacity (synchronises).
+hipError_t sparse_pauli_basis(const SparsePauli *sp, int64_t N, int64_t *offsets, uint64_t *keys, double *coefs,
+                              int64_t capacity, int64_t *written, hipStream_t s);
+
 // ------------------------------------------------------------- matrix-inversion method (inverse_gram.hip)
 // A^{-1} for the Gram matrix A = B B^T of the first N unit-norm raw rows (Algorithm 2), kept as
 // the inverse of its Cholesky factor and bordered by each appended element.

@@ -100,11 +100,10 @@ def pauli_set(n: int, k: int, seed: int) -> np.ndarray:
     return np.ascontiguousarray(np.stack([c * pauli_string(s) for s, c in zip(strings, coeffs)]))
 
 
-def pauli_sums(n: int, k: int, terms: int, seed: int) -> np.ndarray:
-    """k generators, each i * sum of `terms` distinct random non-identity Pauli strings on n
-    qubits with standard-normal real weights (numpy PCG64 ``default_rng(seed)``),
-    Frobenius-normalised: sparse sums of Pauli strings, the operators of the sparse
-    representation."""
+def pauli_sums_terms(n: int, k: int, terms: int, seed: int) -> list[dict[str, float]]:
+    """The generators of :func:`pauli_sums` as {label: weight} dicts, before normalisation:
+    k sums of `terms` distinct random non-identity strings with standard-normal weights
+    (numpy PCG64 ``default_rng(seed)``)."""
     rng = np.random.default_rng(seed)
     letters = "IXYZ"
     out = []
@@ -114,10 +113,38 @@ def pauli_sums(n: int, k: int, terms: int, seed: int) -> np.ndarray:
             s = "".join(letters[i] for i in rng.integers(0, 4, size=n))
             if s != "I" * n:
                 picked.add(s)
-        m = sum(w * pauli_string(s) for s, w in zip(sorted(picked), rng.standard_normal(terms)))
-        m = 1j * m
+        out.append(dict(zip(sorted(picked), (float(w) for w in rng.standard_normal(terms)))))
+    return out
+
+
+def pauli_sums(n: int, k: int, terms: int, seed: int) -> np.ndarray:
+    """k generators, each i * sum of `terms` distinct random non-identity Pauli strings on n
+    qubits with standard-normal real weights (numpy PCG64 ``default_rng(seed)``),
+    Frobenius-normalised: sparse sums of Pauli strings, the operators of the sparse
+    representation."""
+    out = []
+    for g in pauli_sums_terms(n, k, terms, seed):
+        m = 1j * sum(w * pauli_string(s) for s, w in g.items())
         out.append(m / np.linalg.norm(m))
     return np.ascontiguousarray(np.stack(out))
+
+
+def ising_terms(n: int) -> list[dict[str, float]]:
+    """:func:`ising` as sparse generators {label: c} (generator = sum c iP_label)."""
+    gens = [{_site(n, {j: "X"}): 1.0} for j in range(n)]
+    gens += [{_site(n, {j: "Z", j + 1: "Z"}): 1.0} for j in range(n - 1)]
+    return gens
+
+
+def xxyy_terms(n: int) -> list[dict[str, float]]:
+    """:func:`xxyy` as sparse generators."""
+    return [{_site(n, {j: "X", j + 1: "X"}): 1.0, _site(n, {j: "Y", j + 1: "Y"}): 1.0} for j in range(n - 1)]
+
+
+def pauli_set_terms(n: int, k: int, seed: int) -> list[dict[str, float]]:
+    """:func:`pauli_set` as sparse generators (c P = Im(c) iP for c = +-i)."""
+    strings, coeffs = pauli_set_strings(n, k, seed)
+    return [{s: float(c.imag)} for s, c in zip(strings, coeffs)]
 
 
 def rand_pair(d: int, seed: int) -> np.ndarray:
