@@ -910,8 +910,8 @@ struct lie_closure {
         for (;;) {
             int64_t avail = lie::pairs_below(n_lo);
             const bool over_budget = budget >= 0 && spent >= budget;
-            // growth-size blocks are re-evaluated often; saturated ones can queue deep
-            const int max_queued = (block == 0 && cur == block_growth) ? kGrowthQueued : kMaxQueued;
+            // growth and ramp-size blocks are re-evaluated often; saturated ones can queue deep
+            const int max_queued = (block == 0 && cur < block_sat) ? kGrowthQueued : kMaxQueued;
             if (cursor >= avail || queued >= max_queued || over_budget) {
                 if ((s = sync_state()) != LIE_OK || (s = check_state()) != LIE_OK)
                     break;
@@ -919,11 +919,14 @@ struct lie_closure {
                 queued_rows = 0;
                 n_lo = hs.N;
                 if (block == 0) {
-                    // adaptive block: small while candidates are mostly accepted, large otherwise;
-                    // a basis at the ambient bound cannot grow, so it is saturated at once
+                    // adaptive block: small while candidates are mostly accepted, growing fourfold per
+                    // synchronisation while few are (a block's survivors that are new to the basis
+                    // snapshot are decided in sequence, so a large block early on pays for every
+                    // in-block duplicate); a basis at the ambient bound cannot grow, so it is saturated
+                    // at once
                     const int64_t dc = hs.n_cand - last_cand, da = hs.n_acc - last_acc;
                     if (dc > 0)
-                        cur = 8 * da > dc ? block_growth : block_sat;
+                        cur = 8 * da > dc ? block_growth : std::min(block_sat, 4 * std::max(cur, block_growth));
                     if (n_lo >= ambient)
                         cur = block_sat;
                     last_cand = hs.n_cand;
@@ -1831,7 +1834,8 @@ struct lie_closure_batch {
             if (h->block == 0) {
                 const int64_t dc = h->hs.n_cand - h->b_lastc, da = h->hs.n_acc - h->b_lasta;
                 if (dc > 0)
-                    h->b_cur = 8 * da > dc ? h->block_growth : h->block_sat;
+                    h->b_cur = 8 * da > dc ? h->block_growth
+                                           : std::min(h->block_sat, 4 * std::max(h->b_cur, h->block_growth));
                 if (h->b_nlo >= h->ambient)
                     h->b_cur = h->block_sat;
                 h->b_lastc = h->hs.n_cand;
@@ -1878,7 +1882,7 @@ struct lie_closure_batch {
                     continue;
                 if (h->cursor >= lie::pairs_below(h->b_nlo))
                     need = true;
-                if (h->block == 0 && h->b_cur == h->block_growth)
+                if (h->block == 0 && h->b_cur < h->block_sat)
                     growing = true;
             }
             if (growing && queued >= kGrowthQueued)

@@ -493,6 +493,55 @@ __device__ __forceinline__ BqrOut block_qr(const AcceptArgs &a, int nsv, int64_t
     return BqrOut{s_resume, s_uk};
 }
 
+// A further projection pass of the residual R (LDS, D values) against the whole basis: the
+// snapshot rows V[0, N0) and the elements appended earlier in the block, V[N0, nall), the
+// first AL of them cached in LDS at cbase.  Chunks of one element per wave: the chunk's
+// coefficients against the current R, then their subtraction.  Returns ||R||^2 (every
+// thread).  Kept out of line: it runs rarely, and inlined it would cost the acceptance
+// kernel's hot path registers.
+__device__ __noinline__ double reorth_whole_basis(double *R, const double *V, const double *cbase, int64_t AL,
+                                                  int64_t N0, int64_t nall, int64_t D, double *red)
+{
+    __shared__ double scoef[16];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    for (int64_t q0 = 0; q0 < nall; q0 += nw) {
+        const int64_t q = q0 + w;
+        if (q < nall) {
+            const int64_t qb = q - N0;
+            const double *va = (qb >= 0 && qb < AL) ? cbase + qb * D : V + q * D;
+            double sdot = 0.0;
+            for (int64_t j = lane; j < D; j += 64)
+                sdot += va[j] * R[j];
+            sdot = wave_sum(sdot);
+            if (lane == 0)
+                scoef[w] = sdot;
+        }
+        lds_barrier();  // the chunk's coefficients are complete, R is no longer read
+        const int nq = (int)std::min<int64_t>(nw, nall - q0);
+        for (int64_t j = threadIdx.x; j < D; j += blockDim.x) {
+            double t = 0.0;
+            for (int i = 0; i < nq; ++i) {
+                const int64_t qb = q0 + i - N0;
+                const double *va = (qb >= 0 && qb < AL) ? cbase + qb * D : V + (q0 + i) * D;
+                t += scoef[i] * va[j];
+            }
+            R[j] -= t;
+        }
+        lds_barrier();  // R is updated and scoef[] may be overwritten
+    }
+    double loc = 0.0;
+    for (int64_t j = threadIdx.x; j < D; j += blockDim.x)
+        loc += R[j] * R[j];
+    loc = wave_sum(loc);
+    if (lane == 0)
+        red[w] = loc;
+    lds_barrier();
+    double t = 0.0;
+    for (int i = 0; i < nw; ++i)
+        t += red[i];
+    return t;
+}
+
 // Dynamic LDS layout of the acceptance kernel: coef[cnt] | R[D] | slots x D
 // cached copies of the vectors appended earlier in the block (the rest are
 // read from the basis in global memory).
@@ -888,45 +937,10 @@ __device__ __forceinline__ void accept_body(const AcceptArgs &a)
         // snapshot only to eps times that ratio.  Past a ratio of 64 a further pass runs
         // against the whole basis (snapshot and in-block elements, in chunks of one
         // element per wave), which brings the components back to rounding of ||r||.
-        if (A > 0 && snap > 0.0 && nrm2 > 0.0 && nrm2 * 4096.0 < snap * snap) {
-            __shared__ double scoef[16];
-            const int64_t nall = sN;
-            for (int64_t q0 = 0; q0 < nall; q0 += nw) {
-                const int64_t q = q0 + w;
-                if (q < nall) {
-                    const int64_t qb = q - N0;
-                    const double *va = (qb >= 0 && qb < AL) ? cbase + qb * D : a.V + q * D;
-                    double sdot = 0.0;
-                    for (int64_t j = lane; j < D; j += 64)
-                        sdot += va[j] * R[j];
-                    sdot = wave_sum(sdot);
-                    if (lane == 0)
-                        scoef[w] = sdot;
-                }
-                lds_barrier();  // the chunk's coefficients are complete, R is no longer read
-                const int nq = (int)std::min<int64_t>(nw, nall - q0);
-                for (int64_t j = threadIdx.x; j < D; j += blockDim.x) {
-                    double t = 0.0;
-                    for (int i = 0; i < nq; ++i) {
-                        const int64_t qb = q0 + i - N0;
-                        const double *va = (qb >= 0 && qb < AL) ? cbase + qb * D : a.V + (q0 + i) * D;
-                        t += scoef[i] * va[j];
-                    }
-                    R[j] -= t;
-                }
-                lds_barrier();  // R is updated and scoef[] may be overwritten
-            }
-            double loc = 0.0;
-            for (int64_t j = threadIdx.x; j < D; j += blockDim.x)
-                loc += R[j] * R[j];
-            loc = wave_sum(loc);
-            if (lane == 0)
-                red[w] = loc;
-            lds_barrier();
-            double t = 0.0;
-            for (int i = 0; i < nw; ++i)
-                t += red[i];
-            nrm2 = t;
+        // (Only for a vector that would be accepted: a further pass cannot lengthen it, so one
+        // already at or below the threshold is rejected either way.)
+        if (A > 0 && snap > 0.0 && nrm2 > thr * thr && nrm2 * 4096.0 < snap * snap) {
+            nrm2 = reorth_whole_basis(R, a.V, cbase, AL, N0, sN, D, red);
             if (threadIdx.x == 0)
                 l_reorth++;
         }
