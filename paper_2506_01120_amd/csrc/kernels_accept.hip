@@ -741,12 +741,15 @@ __device__ __forceinline__ void accept_body(const AcceptArgs &a)
     // workspace goes after the scalars when it fits there; otherwise (large D: R alone takes
     // most of the LDS) into R, which the pass does not use -- the sequential path after it
     // refills R -- with the Gram staging behind it.
-    const int64_t gram_need = bqr_lds(nsv, nw);
+    // The block pass takes the first 64 survivors at most; with more, the exact sequential
+    // path decides the rest against everything the pass appended.
+    const int nb = nsv < 64 ? nsv : 64;
+    const int64_t gram_need = bqr_lds(nb, nw);
     // (in R only from 8 survivors on: at such D the pass has a fixed cost of a few hundred
     // microseconds in latency-bound sweeps over the columns, while the sequential path
     // takes a few tens per survivor)
-    const bool gram_free = rest >= gram_need, gram_in_r = !gram_free && D >= gram_need && nsv >= 8;
-    const bool gram_ok = a.mode == 1 && nsv >= 2 && nsv <= 64 && nw >= 16 && meta_in_lds && (gram_free || gram_in_r);
+    const bool gram_free = rest >= gram_need, gram_in_r = !gram_free && D >= gram_need && nb >= 8;
+    const bool gram_ok = a.mode == 1 && nb >= 2 && nw >= 16 && meta_in_lds && (gram_free || gram_in_r);
     double *gram_base = gram_in_r ? R : cache2;
     if (gram_ok && gram_free)
         cache2 = gram_base + gram_need;
@@ -758,7 +761,7 @@ __device__ __forceinline__ void accept_body(const AcceptArgs &a)
         __shared__ double bstat[2];
         double *stage = gram_in_r ? R + gram_need : cache2;
         const int64_t stage_cap = gram_in_r ? D - gram_need : cslots * D;
-        const BqrOut b = block_qr(a, nsv, N0, gram_base, cache2, cslots, stage, stage_cap, bstat, hn_a);
+        const BqrOut b = block_qr(a, nb, N0, gram_base, cache2, cslots, stage, stage_cap, bstat, hn_a);
         if (threadIdx.x == 0) {
             // rows 0 .. resume-1 are decided: b.u accepted, the rest rejected
             for (int r = 0; r < b.resume; ++r) {
