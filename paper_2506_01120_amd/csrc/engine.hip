@@ -43,7 +43,7 @@ lie_status fail(lie_status st, const char *fmt, ...)
     } while (0)
 
 // Blocks of at most this many rows use the split-K GEMV projection; larger ones the matrix-core GEMMs.
-constexpr int kGemvRows = 16;
+constexpr int kGemvRows = 4;
 // Set while the batch API creates its problems: their passes are grouped launches that
 // need no split-K workspace.
 thread_local bool t_batch_member = false;
