@@ -95,14 +95,15 @@ def test_explicit_tau_is_applied_everywhere(precision):
     assert np.max(np.abs(v - ref.basis)) <= ELEM_TOL
 
 
-@pytest.mark.parametrize("precision,tau", [("fp32", 1e-4), ("bf16x3", 1e-2)])
-def test_screen_audit_su64_prefix(precision, tau):
+@pytest.mark.parametrize("precision,tau,block,budget", [("fp32", 1e-4, 512, 12288), ("bf16x3", 1e-2, 512, 12288),
+                                                       ("bf16x3", 1e-2, 8192, 32768)])
+def test_screen_audit_su64_prefix(precision, tau, block, budget):
     """su(64), seed 5, tol 1e-8, a prefix of the closure that runs through the growth phase into
     the saturated one with the screen computed on every block and every candidate decided in
     FP64: every snapshot-dependent candidate screens below the threshold, every independent one
-    above it."""
+    above it, with blocks of 512 and with the benchmarked blocks of 8192."""
     gens = W.rand_pair(64, seed=5)
-    dim, v, st, orth = gpu_run(gens, 1e-8, budget=12288, precision=precision, decide="fp64", block=512)
+    dim, v, st, orth = gpu_run(gens, 1e-8, budget=budget, precision=precision, decide="fp64", block=block)
     assert dim == 4095, dim
     assert st["candidates"] > 4095 * 2  # well past saturation
     print("screen margin:", precision, st["screen_max_dependent"], st["screen_min_independent"])
