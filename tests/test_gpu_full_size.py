@@ -24,7 +24,7 @@ from paper_2506_01120_amd import LieClosure, workloads as W
 pytestmark = pytest.mark.gpu
 
 SPAN_TOL_FP64 = 1e-8
-SPAN_TOL_MIXED = 1e-5
+SPAN_TOL_MIXED = 1e-8  # screened runs keep only FP64-recomputed rows: the FP64 bar
 
 
 def closure(d, seed, tol, **cfg):

@@ -145,13 +145,13 @@ def test_basis_device_matches_host():
 #
 # The screen (FP32 bracket + projection on MFMA) only filters candidates; every
 # decision that keeps a candidate, the appended vector and its normalisation
-# are FP64.  Bar: dimensions identical to the reference, span distance
-# <= 1e-5 (the mixed-precision bar of the span), and -- since every kept
-# element is recomputed in FP64 -- the basis equal to the reference's element
-# by element to 1e-8; orthogonality <= 1e-10.  The "approx" modes set an
+# are FP64.  Bar: dimensions identical to the reference and -- since every kept
+# element is recomputed in FP64 -- the FP64 bars: span distance <= 1e-8, the
+# basis equal to the reference's element by element to 1e-8, orthogonality
+# <= 1e-10.  The "approx" modes set an
 # explicit tau_rej, so the screen rejects below the ambient bound too and its
 # kernels decide which candidates reach FP64.
-SPAN_TOL_MIXED = 1e-5
+SPAN_TOL_MIXED = 1e-8
 
 SCREEN_MODES = [("fp32", "fp64"), ("fp32", "strict"), ("fp32", "screen"), ("fp32", "approx"),
                 ("bf16x3", "fp64"), ("bf16x3", "strict"), ("bf16x3", "screen"), ("bf16x3", "approx")]
