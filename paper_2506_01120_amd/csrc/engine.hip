@@ -163,6 +163,7 @@ struct lie_closure {
     int device = -1;
     hipStream_t stream = nullptr;
     bool own_stream = false;
+    char *pool = nullptr;        // one device allocation holding every buffer below that init sets up
     double *V64 = nullptr;       // cap x D, FP64 basis
     float *Vs = nullptr;         // cap x D, FP32 rounding of V64 (screened modes)
     double *H64 = nullptr;       // block x D, FP64 candidates, then residuals
@@ -252,16 +253,20 @@ struct lie_closure {
         lie::rank_tester_destroy(rank);
         lie::sparse_pauli_destroy(sp);
         lie::gram_inverse_destroy(ginv);
-        for (void *p : {(void *)Xc, (void *)sup_cnt, (void *)sup_idx})
-            if (p)
-                (void)hipFree(p);
+        if (pool) {
+            (void)hipFree(pool);  // every buffer of a dense handle is a slice of it
+        } else {
+            for (void *p : {(void *)Xc, (void *)sup_cnt, (void *)sup_idx})
+                if (p)
+                    (void)hipFree(p);
+        }
         for (void *p : {(void *)d_cursor, (void *)V64, (void *)Vs, (void *)H64, (void *)Hs, (void *)C, (void *)Cs,
                         (void *)part, (void *)splitws,
                         (void *)normpart_s, (void *)cand_a2, (void *)cand_n2, (void *)rho2, (void *)h2, (void *)h2b,
                         (void *)surv_rows, (void *)surv_pairs, (void *)slot, (void *)keep, (void *)nsurv,
                         (void *)st, (void *)scalar, (void *)B64, (void *)Bs, (void *)Graw, (void *)elem_src,
                         (void *)Vp, (void *)Vt, (void *)Hp, (void *)Cp, (void *)planes_n})
-            if (p)
+            if (p && !pool)
                 (void)hipFree(p);
         if (own_stream && stream)
             (void)hipStreamDestroy(stream);
@@ -1221,77 +1226,104 @@ lie_status lie_closure_init(lie_closure **out, const double *generators, int32_t
     }
     const int b = h->block > 0 ? h->block : std::max(h->block_growth, h->block_sat);
     h->bmax = b;
+    // Every buffer is a 256-byte aligned slice of one device allocation: the layout is laid out
+    // twice, once to size the allocation and once to place the slices.  A handle then costs one
+    // hipMalloc instead of some thirty, which dominates the set-up of many live handles (a batch).
+    size_t pool_off = 0;
+    bool sizing = true;
     auto alloc = [&](auto **p, size_t n) -> lie_status {
         using T = std::remove_pointer_t<std::remove_reference_t<decltype(*p)>>;
-        hipError_t e = hipMalloc((void **)p, std::max<size_t>(n, 1) * sizeof(T));
-        if (e != hipSuccess)
-            return fail(e == hipErrorOutOfMemory ? LIE_ERR_OOM : LIE_ERR_DEVICE, "hipMalloc of %zu elements failed: %s",
-                        n, hipGetErrorString(e));
+        pool_off = (pool_off + 255) & ~size_t(255);
+        if (!sizing)
+            *p = reinterpret_cast<T *>(h->pool + pool_off);
+        pool_off += std::max<size_t>(n, 1) * sizeof(T);
         return LIE_OK;
     };
     const int bmax = std::max(b, 1);
     const size_t capr = (size_t)lie::coef_ld(h->cap);
-    if ((s = alloc(&h->V64, (size_t)h->cap * D)) != LIE_OK || (s = alloc(&h->H64, (size_t)bmax * D)) != LIE_OK ||
-        (s = alloc(&h->C, (size_t)bmax * capr)) != LIE_OK ||
-        (s = alloc(&h->part, std::max(lie::proj_scratch_doubles(D, std::min(bmax, 64), h->cap),
-                                       (size_t)bmax * lie::gemm_sub_tiles_f64(D) * 2))) != LIE_OK ||
-        (s = alloc(&h->cand_a2, bmax)) != LIE_OK || (s = alloc(&h->cand_n2, bmax)) != LIE_OK ||
-        (s = alloc(&h->rho2, bmax)) != LIE_OK || (s = alloc(&h->h2, bmax)) != LIE_OK ||
-        (s = alloc(&h->h2b, bmax)) != LIE_OK || (s = alloc(&h->surv_rows, bmax)) != LIE_OK ||
-        (s = alloc(&h->surv_pairs, bmax)) != LIE_OK || (s = alloc(&h->slot, bmax)) != LIE_OK ||
-        (s = alloc(&h->keep, bmax)) != LIE_OK ||
-        (!t_batch_member && (s = alloc(&h->splitws, h->splitws_n = lie::gemm_split_ws_doubles(D, (int64_t)capr))) !=
-                                LIE_OK) ||
-        (s = alloc(&h->nsurv, 1)) != LIE_OK || (s = alloc(&h->scalar, 1)) != LIE_OK ||
-        (s = alloc(&h->d_cursor, 1)) != LIE_OK ||
-        (s = alloc(&h->st, 1)) != LIE_OK)
-        return bail(s);
-    if (h->raw) {
-        if ((s = alloc(&h->B64, (size_t)h->cap * D)) != LIE_OK || (s = alloc(&h->Graw, (size_t)n_gen * D)) != LIE_OK ||
-            (s = alloc(&h->elem_src, (size_t)h->cap)) != LIE_OK ||
-            (h->screened && (s = alloc(&h->Bs, (size_t)h->cap * D)) != LIE_OK))
-            return bail(s);
-    }
-    if (h->screened) {
-        if ((s = alloc(&h->Vs, (size_t)h->cap * D)) != LIE_OK || (s = alloc(&h->Hs, (size_t)bmax * D)) != LIE_OK ||
-            (s = alloc(&h->Cs, (size_t)bmax * capr)) != LIE_OK ||
-            (s = alloc(&h->normpart_s, (size_t)bmax * lie::gemm_sub_tiles_f32(D, 1) * 2)) != LIE_OK)
-            return bail(s);
-        if (cfg.precision == LIE_PREC_BF16X3 && !t_batch_member) {
-            // the split-BF16 screen of single problems runs on pre-split planes; their padding
-            // must read as zeros, so every plane starts cleared
-            h->planes = true;
-            h->pg = lie::plane_geom(D, h->cap, bmax);
+    const bool planes = h->screened && cfg.precision == LIE_PREC_BF16X3 && !t_batch_member;
+    if (planes)
+        h->pg = lie::plane_geom(D, h->cap, bmax);
+    auto layout = [&]() -> lie_status {
+        lie_status s;
+        if ((s = alloc(&h->V64, (size_t)h->cap * D)) != LIE_OK || (s = alloc(&h->H64, (size_t)bmax * D)) != LIE_OK ||
+            (s = alloc(&h->C, (size_t)bmax * capr)) != LIE_OK ||
+            (s = alloc(&h->part, std::max(lie::proj_scratch_doubles(D, std::min(bmax, 64), h->cap),
+                                           (size_t)bmax * lie::gemm_sub_tiles_f64(D) * 2))) != LIE_OK ||
+            (s = alloc(&h->cand_a2, bmax)) != LIE_OK || (s = alloc(&h->cand_n2, bmax)) != LIE_OK ||
+            (s = alloc(&h->rho2, bmax)) != LIE_OK || (s = alloc(&h->h2, bmax)) != LIE_OK ||
+            (s = alloc(&h->h2b, bmax)) != LIE_OK || (s = alloc(&h->surv_rows, bmax)) != LIE_OK ||
+            (s = alloc(&h->surv_pairs, bmax)) != LIE_OK || (s = alloc(&h->slot, bmax)) != LIE_OK ||
+            (s = alloc(&h->keep, bmax)) != LIE_OK ||
+            (!t_batch_member &&
+             (s = alloc(&h->splitws, h->splitws_n = lie::gemm_split_ws_doubles(D, (int64_t)capr))) != LIE_OK) ||
+            (s = alloc(&h->nsurv, 1)) != LIE_OK || (s = alloc(&h->scalar, 1)) != LIE_OK ||
+            (s = alloc(&h->d_cursor, 1)) != LIE_OK || (s = alloc(&h->st, 1)) != LIE_OK)
+            return s;
+        if (h->raw) {
+            if ((s = alloc(&h->B64, (size_t)h->cap * D)) != LIE_OK ||
+                (s = alloc(&h->Graw, (size_t)n_gen * D)) != LIE_OK ||
+                (s = alloc(&h->elem_src, (size_t)h->cap)) != LIE_OK ||
+                (h->screened && (s = alloc(&h->Bs, (size_t)h->cap * D)) != LIE_OK))
+                return s;
+        }
+        if (h->screened) {
+            if ((s = alloc(&h->Vs, (size_t)h->cap * D)) != LIE_OK || (s = alloc(&h->Hs, (size_t)bmax * D)) != LIE_OK ||
+                (s = alloc(&h->Cs, (size_t)bmax * capr)) != LIE_OK ||
+                (s = alloc(&h->normpart_s, (size_t)bmax * lie::gemm_sub_tiles_f32(D, 1) * 2)) != LIE_OK)
+                return s;
+        }
+        if (planes) {
             const lie::PlaneGeom &g = h->pg;
             if ((s = alloc(&h->Vp, (size_t)(g.cap_rows * g.ld))) != LIE_OK ||
                 (s = alloc(&h->Vt, (size_t)(g.d_rows * g.ldt))) != LIE_OK ||
                 (s = alloc(&h->Hp, (size_t)(g.b_rows * g.ld))) != LIE_OK ||
                 (s = alloc(&h->Cp, (size_t)(g.b_rows * g.ldt))) != LIE_OK || (s = alloc(&h->planes_n, 1)) != LIE_OK)
-                return bail(s);
-            hipError_t e = hipSuccess;
-            for (auto pz : {std::make_pair((void *)h->Vp, (size_t)(g.cap_rows * g.ld) * 2),
-                            std::make_pair((void *)h->Vt, (size_t)(g.d_rows * g.ldt) * 2),
-                            std::make_pair((void *)h->Hp, (size_t)(g.b_rows * g.ld) * 2),
-                            std::make_pair((void *)h->Cp, (size_t)(g.b_rows * g.ldt) * 2),
-                            std::make_pair((void *)h->planes_n, sizeof(int64_t))})
-                if (e == hipSuccess)
-                    e = hipMemsetAsync(pz.first, 0, pz.second, h->stream);
-            if (e != hipSuccess)
-                return bail(fail(LIE_ERR_DEVICE, "clearing the screen planes failed: %s", hipGetErrorString(e)));
+                return s;
         }
+        if (h->pauli) {
+            if ((s = alloc(&h->sup_cnt, (size_t)h->cap)) != LIE_OK ||
+                (s = alloc(&h->sup_idx, (size_t)h->cap * D)) != LIE_OK)
+                return s;
+        }
+        if (h->inv && (s = alloc(&h->Xc, (size_t)bmax * capr)) != LIE_OK)
+            return s;
+        return LIE_OK;
+    };
+    if ((s = layout()) != LIE_OK)
+        return bail(s);
+    {
+        const hipError_t e = hipMalloc((void **)&h->pool, pool_off);
+        if (e != hipSuccess)
+            return bail(fail(e == hipErrorOutOfMemory ? LIE_ERR_OOM : LIE_ERR_DEVICE,
+                             "hipMalloc of the handle's %zu bytes failed: %s", pool_off, hipGetErrorString(e)));
+    }
+    sizing = false;
+    pool_off = 0;
+    if ((s = layout()) != LIE_OK)
+        return bail(s);
+    if (planes) {
+        // the split-BF16 screen of single problems runs on pre-split planes; their padding
+        // must read as zeros, so every plane starts cleared
+        h->planes = true;
+        const lie::PlaneGeom &g = h->pg;
+        hipError_t e = hipSuccess;
+        for (auto pz : {std::make_pair((void *)h->Vp, (size_t)(g.cap_rows * g.ld) * 2),
+                        std::make_pair((void *)h->Vt, (size_t)(g.d_rows * g.ldt) * 2),
+                        std::make_pair((void *)h->Hp, (size_t)(g.b_rows * g.ld) * 2),
+                        std::make_pair((void *)h->Cp, (size_t)(g.b_rows * g.ldt) * 2),
+                        std::make_pair((void *)h->planes_n, sizeof(int64_t))})
+            if (e == hipSuccess)
+                e = hipMemsetAsync(pz.first, 0, pz.second, h->stream);
+        if (e != hipSuccess)
+            return bail(fail(LIE_ERR_DEVICE, "clearing the screen planes failed: %s", hipGetErrorString(e)));
     }
     if (h->method == LIE_METHOD_RANK_SVD) {
         const hipError_t e = lie::rank_tester_create(&h->rank, D, 64, h->stream);
         if (e != hipSuccess)
             return bail(fail(LIE_ERR_DEVICE, "rank tester setup failed: %s", hipGetErrorString(e)));
     }
-    if (h->pauli) {
-        if ((s = alloc(&h->sup_cnt, (size_t)h->cap)) != LIE_OK || (s = alloc(&h->sup_idx, (size_t)h->cap * D)) != LIE_OK)
-            return bail(s);
-    }
     if (h->inv) {
-        if ((s = alloc(&h->Xc, (size_t)bmax * capr)) != LIE_OK)
-            return bail(s);
         const hipError_t e = lie::gram_inverse_create(&h->ginv, h->cap, D, bmax, h->stream);
         if (e != hipSuccess)
             return bail(fail(LIE_ERR_DEVICE, "inverse Gram setup failed: %s", hipGetErrorString(e)));
